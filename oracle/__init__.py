@@ -1,0 +1,281 @@
+"""CPU oracle for the chromatic Gibbs sampler (ctypes front end of gmrf_oracle.c).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark may import this package.  It shares no code
+with the HIP library; the two meet only through the seeded input generators.
+
+The arithmetic lives in ``gmrf_oracle.c`` (plain C, FP64, no fast-math, no FP
+contraction).  This module only builds it, marshals arrays and wraps the
+chain state.  Every function cites the part of the paper it follows in the C
+source.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gmrf_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+WITH_HYPER = 1
+ZERO_NOISE = 2
+GAMMA_MAX_ATTEMPTS = 64
+
+CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+          "-std=c99", "-Wall"]
+
+
+def build(force: bool = True) -> str:
+    """Compile gmrf_oracle.c into liboracle.so with gcc."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Problem(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64),
+        ("row_ptr", C.POINTER(C.c_int64)),
+        ("col", C.POINTER(C.c_int32)),
+        ("color", C.POINTER(C.c_int32)),
+        ("k", C.c_int32),
+        ("rho", C.c_double),
+        ("y", C.POINTER(C.c_double)),
+        ("a_tau", C.c_double),
+        ("b_tau", C.c_double),
+        ("a_lam", C.c_double),
+        ("b_lam", C.c_double),
+        ("rank", C.c_int64),
+        ("burn_in", C.c_int64),
+        ("seed", C.c_uint64),
+        ("instance", C.c_uint32),
+    ]
+
+
+class _Chain(C.Structure):
+    _fields_ = [
+        ("x", C.POINTER(C.c_double)),
+        ("s1", C.POINTER(C.c_double)),
+        ("s2", C.POINTER(C.c_double)),
+        ("tau", C.c_double),
+        ("lam", C.c_double),
+        ("sweep", C.c_int64),
+        ("n_acc", C.c_int64),
+        ("q", C.c_double),
+        ("sse", C.c_double),
+        ("status", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = C.CDLL(_LIB)
+        u32, u64, i32, i64, dbl = C.c_uint32, C.c_uint64, C.c_int32, C.c_int64, C.c_double
+        L.orc_philox4x32_10.argtypes = [C.POINTER(u32), C.POINTER(u32), C.POINTER(u32)]
+        L.orc_philox4x32_10.restype = None
+        L.orc_uniform52.argtypes = [u32, u32]
+        L.orc_uniform52.restype = dbl
+        L.orc_normal.argtypes = [u64, u32, u32, u32, u32]
+        L.orc_normal.restype = dbl
+        L.orc_gamma.argtypes = [dbl, dbl, u64, u32, u32, u32, C.c_int, C.POINTER(dbl)]
+        L.orc_gamma.restype = C.c_int
+        L.orc_greedy_coloring.argtypes = [i64, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]
+        L.orc_greedy_coloring.restype = i32
+        L.orc_components.argtypes = [i64, C.POINTER(i64), C.POINTER(i32)]
+        L.orc_components.restype = i64
+        L.orc_quadratic_terms.argtypes = [C.POINTER(_Problem), C.POINTER(dbl), C.POINTER(dbl),
+                                          C.POINTER(dbl)]
+        L.orc_quadratic_terms.restype = None
+        L.orc_hyper.argtypes = [C.POINTER(_Problem), C.POINTER(_Chain)]
+        L.orc_hyper.restype = C.c_int
+        L.orc_sweeps.argtypes = [C.POINTER(_Problem), C.POINTER(_Chain), i64, u32,
+                                 C.POINTER(i64), i32]
+        L.orc_sweeps.restype = C.c_int
+        L.orc_stats.argtypes = [C.POINTER(_Chain), i64, C.POINTER(dbl), C.POINTER(dbl)]
+        L.orc_stats.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+# --------------------------------------------------------------------------
+# Random numbers
+# --------------------------------------------------------------------------
+def philox(ctr, key):
+    """Philox4x32-10 block: 4 counter words, 2 key words -> 4 output words."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c, C.c_uint32), _ptr(k, C.c_uint32), _ptr(out, C.c_uint32))
+    return out
+
+
+def uniform52(hi: int, lo: int) -> float:
+    return lib().orc_uniform52(hi, lo)
+
+
+def normal(seed: int, c0: int, c1: int, c2: int, c3: int) -> float:
+    """Box-Muller normal of the Philox block at counter (c0, c1, c2, c3)."""
+    return lib().orc_normal(seed, c0, c1, c2, c3)
+
+
+def site_normals(seed: int, sweep: int, instance: int, n: int) -> np.ndarray:
+    """The site normals z_{t,i} of one sweep, i = 0..n-1 (tag 0)."""
+    L = lib()
+    return np.array([L.orc_normal(seed, i, sweep, instance, 0) for i in range(n)])
+
+
+def gamma(shape: float, rate: float, seed: int, sweep: int, instance: int, tag: int,
+          max_attempts: int = GAMMA_MAX_ATTEMPTS):
+    """Marsaglia-Tsang Gamma(shape, rate) draw; returns (value, attempts)."""
+    out = C.c_double(0.0)
+    a = lib().orc_gamma(shape, rate, seed, sweep, instance, tag, max_attempts, C.byref(out))
+    if a == -2:
+        raise ValueError("gamma: shape must be >= 1 and rate > 0")
+    return (out.value if a > 0 else float("nan")), a
+
+
+# --------------------------------------------------------------------------
+# Graph utilities
+# --------------------------------------------------------------------------
+def _csr(row_ptr, col):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    if cl.size == 0:
+        cl = np.zeros(1, dtype=np.int32)
+    return rp, cl
+
+
+def greedy_coloring(row_ptr, col):
+    """Greedy coloring by peeling maximal independent sets (min-index first)."""
+    rp, cl = _csr(row_ptr, col)
+    n = rp.size - 1
+    color = np.zeros(max(n, 1), dtype=np.int32)
+    k = lib().orc_greedy_coloring(n, _ptr(rp, C.c_int64), _ptr(cl, C.c_int32),
+                                  _ptr(color, C.c_int32))
+    return color[:n].copy(), int(k)
+
+
+def components(row_ptr, col) -> int:
+    rp, cl = _csr(row_ptr, col)
+    return int(lib().orc_components(rp.size - 1, _ptr(rp, C.c_int64), _ptr(cl, C.c_int32)))
+
+
+# --------------------------------------------------------------------------
+# Sampler
+# --------------------------------------------------------------------------
+class Chain:
+    """One chromatic Gibbs chain on the CPU oracle.
+
+    Parameters mirror the model: a CSR adjacency (neighbours ascending), a
+    proper coloring, observations y, rho (1 = intrinsic), Gamma(a, rate b)
+    priors on tau and lam, burn-in, seed and instance.
+    """
+
+    def __init__(self, row_ptr, col, color, y, rho=1.0, a_tau=1.0, b_tau=1.0, a_lam=1.0,
+                 b_lam=1.0, tau0=1.0, lam0=1.0, burn_in=0, seed=1, instance=0, x0=None,
+                 rank=None):
+        self.row_ptr, self.col = _csr(row_ptr, col)
+        self.n = n = self.row_ptr.size - 1
+        self.color = np.ascontiguousarray(color, dtype=np.int32)
+        if self.color.size != n:
+            raise ValueError("color must have n entries")
+        self.k = int(self.color.max()) + 1 if n else 0
+        self.y = np.ascontiguousarray(y, dtype=np.float64).copy()
+        if rank is None:
+            rank = n - components(self.row_ptr, self.col) if rho == 1.0 else n
+        self.rank = int(rank)
+        self.x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+        self.s1 = np.zeros(n)
+        self.s2 = np.zeros(n)
+        self._p = _Problem(n, _ptr(self.row_ptr, C.c_int64), _ptr(self.col, C.c_int32),
+                           _ptr(self.color, C.c_int32), self.k, float(rho),
+                           _ptr(self.y, C.c_double), a_tau, b_tau, a_lam, b_lam, self.rank,
+                           int(burn_in), int(seed), int(instance))
+        self._s = _Chain(_ptr(self.x, C.c_double), _ptr(self.s1, C.c_double),
+                         _ptr(self.s2, C.c_double), float(tau0), float(lam0), 0, 0, 0.0, 0.0, 0)
+
+    # state ----------------------------------------------------------------
+    @property
+    def tau(self):
+        return self._s.tau
+
+    @property
+    def lam(self):
+        return self._s.lam
+
+    @property
+    def sweep_count(self):
+        return self._s.sweep
+
+    @property
+    def n_acc(self):
+        return self._s.n_acc
+
+    @property
+    def q(self):
+        return self._s.q
+
+    @property
+    def sse(self):
+        return self._s.sse
+
+    @property
+    def status(self):
+        return self._s.status
+
+    def set_state(self, x, tau, lam, sweep):
+        self.x[:] = x
+        self._s.tau = float(tau)
+        self._s.lam = float(lam)
+        self._s.sweep = int(sweep)
+
+    def set_y(self, y):
+        self.y[:] = y
+
+    # work -----------------------------------------------------------------
+    def sweeps(self, nsweeps: int, hyper: bool = True, zero_noise: bool = False, visit=None,
+               nthreads: int = 1):
+        flags = (WITH_HYPER if hyper else 0) | (ZERO_NOISE if zero_noise else 0)
+        vp = None
+        if visit is not None:
+            self._visit = np.ascontiguousarray(visit, dtype=np.int64)
+            vp = _ptr(self._visit, C.c_int64)
+        rc = lib().orc_sweeps(C.byref(self._p), C.byref(self._s), int(nsweeps), flags, vp,
+                              int(nthreads))
+        if rc != 0:
+            raise FloatingPointError("oracle: Gamma attempt cap hit or non-finite draw")
+        return self
+
+    def hyper(self):
+        if self._s.sweep < 1:
+            raise RuntimeError("hyper needs a completed sweep")
+        if lib().orc_hyper(C.byref(self._p), C.byref(self._s)) != 0:
+            raise FloatingPointError("oracle: Gamma attempt cap hit or non-finite draw")
+
+    def quadratic_terms(self, x=None):
+        xx = self.x if x is None else np.ascontiguousarray(x, dtype=np.float64)
+        q, s = C.c_double(), C.c_double()
+        lib().orc_quadratic_terms(C.byref(self._p), _ptr(xx, C.c_double), C.byref(q), C.byref(s))
+        return q.value, s.value
+
+    def stats(self):
+        mean = np.zeros(self.n)
+        var = np.zeros(self.n)
+        lib().orc_stats(C.byref(self._s), self.n, _ptr(mean, C.c_double), _ptr(var, C.c_double))
+        return mean, var

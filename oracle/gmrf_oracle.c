@@ -1,0 +1,375 @@
+/*
+ * gmrf_oracle.c -- CPU oracle for the chromatic Gibbs sampler of a Gaussian
+ * Markov random field with a CAR prior (Brown, McMahan & Self, "Sampling
+ * Strategies for Fast Updating of Gaussian Markov Random Fields", 2017).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain, obviously correct
+ * reference that the GPU path is checked against.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or constant generator with the HIP library.
+ *
+ * Everything is FP64, scalar loops in original site order, IEEE
+ * round-to-nearest, built without fast-math and without FP contraction.
+ *
+ * What it computes (paper references are to sections / equations /
+ * algorithms of the paper):
+ *   - Gaussian full conditional of the field given y and the precisions
+ *     (Sec. 2.2: x | y ~ N(Qp^{-1} b, Qp^{-1}), Qp = A'S^{-1}A + Q,
+ *     b = A'S^{-1}y + Q mu), specialised to A = I, S = I/lam, mu = 0 and the
+ *     CAR precision Q = tau (D - rho W) (Sec. 3.1 IAR model, rho = 1; Sec. 3.2
+ *     proper CAR).  Per site (Sec. 3.1 local characteristics, written with
+ *     precisions tau = 1/tau^2 and lam = 1/sigma^2):
+ *         Qii = tau * D_ii + lam,
+ *         m_i = (lam * y_i + tau * rho * sum_{j~i} x_j) / Qii,
+ *         x_i ~ N(m_i, 1/Qii).
+ *   - The chromatic Gibbs step (Sec. 2.3, Algorithm 1): colors in ascending
+ *     order; every site of a color is drawn from its conditional given the
+ *     other colors (lower colors already at their new values).
+ *   - The conjugate hyperparameter draws (Sec. 3.1 full conditionals of
+ *     sigma^2 and tau^2, recast as Gamma laws of the precisions, rate form):
+ *         tau | x ~ Gamma(a_tau + r/2, b_tau + x'(D - rho W)x / 2),
+ *         lam | x ~ Gamma(a_lam + n/2, b_lam + ||y - x||^2 / 2),
+ *     r = n - (#connected components) for the intrinsic prior, n otherwise.
+ *   - Running posterior mean / variance accumulators (Sec. 3.1 posterior
+ *     mean images).
+ *   - The greedy coloring of the paper's supplementary greedy algorithm
+ *     (peel maximal independent sets, always taking the smallest remaining
+ *     site).
+ *
+ * Random numbers (the paper uses R's generator; this is the reading both
+ * sides share): Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) keyed by
+ * the 64-bit seed, counter (c0, c1, c2, c3) = (site or attempt, sweep,
+ * instance, tag); Box & Muller (1958) cosine branch for normals; Marsaglia &
+ * Tsang (2000) for Gamma variates.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon et al., SC'11: multipliers and Weyl key increments) */
+/* ------------------------------------------------------------------------ */
+#define ORC_PHILOX_MUL0 0xD2511F53u
+#define ORC_PHILOX_MUL1 0xCD9E8D57u
+#define ORC_PHILOX_KEYINC0 0x9E3779B9u
+#define ORC_PHILOX_KEYINC1 0xBB67AE85u
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    int round;
+    for (round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)ORC_PHILOX_MUL0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)ORC_PHILOX_MUL1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += ORC_PHILOX_KEYINC0;   /* key schedule: Weyl sequence */
+        k1 += ORC_PHILOX_KEYINC1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static void orc_words(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                      uint32_t w[4])
+{
+    uint32_t ctr[4], key[2];
+    ctr[0] = c0; ctr[1] = c1; ctr[2] = c2; ctr[3] = c3;
+    key[0] = (uint32_t)(seed & 0xFFFFFFFFu);
+    key[1] = (uint32_t)(seed >> 32);
+    orc_philox4x32_10(ctr, key, w);
+}
+
+/* Uniform on (0,1) from two 32-bit words: the top 52 bits m give
+ * (m + 1/2) * 2^-52, which is exact in FP64 and never 0 or 1. */
+double orc_uniform52(uint32_t hi, uint32_t lo)
+{
+    uint64_t m = ((uint64_t)hi << 20) | (uint64_t)(lo >> 12);
+    return ((double)m + 0.5) * 0x1p-52;
+}
+
+#define ORC_TWO_PI 6.283185307179586
+
+/* Standard normal: Box-Muller, cosine branch, from one Philox block. */
+double orc_normal(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3)
+{
+    uint32_t w[4];
+    double u1, u2;
+    orc_words(seed, c0, c1, c2, c3, w);
+    u1 = orc_uniform52(w[0], w[1]);
+    u2 = orc_uniform52(w[2], w[3]);
+    return sqrt(-2.0 * log(u1)) * cos(ORC_TWO_PI * u2);
+}
+
+/* Gamma(shape, rate) by Marsaglia & Tsang (2000), shape >= 1, no squeeze.
+ * Attempt k uses the normal of counter (2k, sweep, instance, tag) and the
+ * uniform (first 52-bit uniform of the block) of counter (2k+1, ...).
+ * Returns the number of attempts used (>= 1), or -1 when max_attempts were
+ * all rejected, or -2 for an invalid shape / rate. */
+int orc_gamma(double shape, double rate, uint64_t seed, uint32_t sweep, uint32_t instance,
+              uint32_t tag, int max_attempts, double *out)
+{
+    double d, c;
+    int k;
+    if (!(shape >= 1.0) || !(rate > 0.0) || !isfinite(shape) || !isfinite(rate))
+        return -2;
+    d = shape - 1.0 / 3.0;
+    c = 1.0 / sqrt(9.0 * d);
+    for (k = 0; k < max_attempts; ++k) {
+        uint32_t w[4];
+        double z = orc_normal(seed, (uint32_t)(2 * k), sweep, instance, tag);
+        double cz = c * z;
+        double L, v, u, lhs, rhs;
+        if (cz <= -1.0)
+            continue;
+        L = 3.0 * log1p(cz);          /* log v, v = (1 + c z)^3 */
+        v = exp(L);
+        orc_words(seed, (uint32_t)(2 * k + 1), sweep, instance, tag, w);
+        u = orc_uniform52(w[0], w[1]);
+        lhs = log(u);
+        rhs = 0.5 * z * z + d * (L - expm1(L));   /* z^2/2 + d - d v + d log v */
+        if (lhs < rhs) {
+            *out = d * v / rate;
+            return k + 1;
+        }
+    }
+    return -1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Graph utilities                                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Greedy k-coloring (supplementary greedy algorithm): color j collects a
+ * maximal independent set of the still-uncolored sites by repeatedly taking
+ * the smallest remaining candidate and striking it and its neighbours from
+ * the candidate set.  Colors are 0-based in discovery order.  Returns k. */
+int32_t orc_greedy_coloring(int64_t n, const int64_t *row_ptr, const int32_t *col,
+                            int32_t *color)
+{
+    int64_t remaining = n, i, e;
+    int32_t j = 0;
+    int32_t *struck = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (i = 0; i < n; ++i) {
+        color[i] = -1;
+        struck[i] = -1;
+    }
+    while (remaining > 0) {
+        /* candidates of color j: uncolored sites not struck during color j;
+         * scanning in ascending order takes min of the candidate set */
+        for (i = 0; i < n; ++i) {
+            if (color[i] != -1 || struck[i] == j)
+                continue;
+            color[i] = j;
+            --remaining;
+            for (e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+                struck[col[e]] = j;
+        }
+        ++j;
+    }
+    free(struck);
+    return j;
+}
+
+/* Number of connected components (breadth-first search). */
+int64_t orc_components(int64_t n, const int64_t *row_ptr, const int32_t *col)
+{
+    int64_t comps = 0, s, head, tail, e;
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    unsigned char *seen = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    for (s = 0; s < n; ++s) {
+        if (seen[s])
+            continue;
+        ++comps;
+        head = tail = 0;
+        queue[tail++] = s;
+        seen[s] = 1;
+        while (head < tail) {
+            int64_t v = queue[head++];
+            for (e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                int64_t u = col[e];
+                if (!seen[u]) {
+                    seen[u] = 1;
+                    queue[tail++] = u;
+                }
+            }
+        }
+    }
+    free(queue);
+    free(seen);
+    return comps;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sampler                                                                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n;
+    const int64_t *row_ptr;   /* n + 1 */
+    const int32_t *col;       /* neighbours of each site, ascending */
+    const int32_t *color;     /* proper coloring, 0 .. k-1 */
+    int32_t k;
+    double rho;               /* 1 = intrinsic (IAR) prior */
+    const double *y;          /* observations, original order */
+    double a_tau, b_tau, a_lam, b_lam;
+    int64_t rank;             /* r in the tau shape a_tau + r/2 */
+    int64_t burn_in;          /* sweeps with index < burn_in are not accumulated */
+    uint64_t seed;
+    uint32_t instance;
+} orc_problem;
+
+typedef struct {
+    double *x;                /* current field, original order */
+    double *s1, *s2;          /* running sums of x and x^2 */
+    double tau, lam;          /* prior precision, noise precision */
+    int64_t sweep;            /* number of completed sweeps */
+    int64_t n_acc;            /* number of accumulated sweeps */
+    double q, sse;            /* x'(D - rho W)x and ||y - x||^2 after the last sweep */
+    int32_t status;           /* 0 ok, 1 Gamma attempt cap hit or non-finite draw */
+} orc_chain;
+
+#define ORC_WITH_HYPER 1u
+#define ORC_ZERO_NOISE 2u
+#define ORC_GAMMA_MAX_ATTEMPTS 64
+
+/* Pairwise (recursive halving) sum, a fixed summation tree. */
+static double orc_pairwise(const double *v, int64_t n)
+{
+    if (n <= 8) {
+        double s = 0.0;
+        int64_t i;
+        for (i = 0; i < n; ++i)
+            s += v[i];
+        return s;
+    }
+    return orc_pairwise(v, n / 2) + orc_pairwise(v + n / 2, n - n / 2);
+}
+
+/* q = x'(D - rho W)x written edge-wise as
+ *   (1 - rho) sum_i D_ii x_i^2 + rho sum_{i<j, i~j} (x_i - x_j)^2,
+ * and sse = sum_i (y_i - x_i)^2; each as a pairwise sum of per-site terms. */
+void orc_quadratic_terms(const orc_problem *p, const double *x, double *q, double *sse)
+{
+    int64_t n = p->n, i, e;
+    double *tq = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *ts = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (i = 0; i < n; ++i) {
+        double deg = (double)(p->row_ptr[i + 1] - p->row_ptr[i]);
+        double edge = 0.0, r;
+        for (e = p->row_ptr[i]; e < p->row_ptr[i + 1]; ++e) {
+            int64_t j = p->col[e];
+            if (j > i) {
+                double d = x[i] - x[j];
+                edge += d * d;
+            }
+        }
+        tq[i] = (1.0 - p->rho) * deg * x[i] * x[i] + p->rho * edge;
+        r = p->y[i] - x[i];
+        ts[i] = r * r;
+    }
+    *q = orc_pairwise(tq, n);
+    *sse = orc_pairwise(ts, n);
+    free(tq);
+    free(ts);
+}
+
+/* Draw tau then lam from the reductions of the last completed sweep, using
+ * sweep index (sweep - 1) in the Philox counter. */
+int orc_hyper(const orc_problem *p, orc_chain *s)
+{
+    uint32_t t = (uint32_t)(s->sweep - 1);
+    double tau, lam;
+    int a1 = orc_gamma(p->a_tau + 0.5 * (double)p->rank, p->b_tau + 0.5 * s->q, p->seed, t,
+                       p->instance, 1u, ORC_GAMMA_MAX_ATTEMPTS, &tau);
+    int a2 = orc_gamma(p->a_lam + 0.5 * (double)p->n, p->b_lam + 0.5 * s->sse, p->seed, t,
+                       p->instance, 2u, ORC_GAMMA_MAX_ATTEMPTS, &lam);
+    if (a1 < 0 || a2 < 0 || !isfinite(tau) || !isfinite(lam)) {
+        s->status = 1;
+        return 1;
+    }
+    s->tau = tau;
+    s->lam = lam;
+    return 0;
+}
+
+/* One site of Algorithm 1: conditional mean and precision, then the draw. */
+static void orc_update_site(const orc_problem *p, orc_chain *s, int64_t i, uint32_t t,
+                            uint32_t flags)
+{
+    double sum = 0.0, deg, Qii, m, z;
+    int64_t e;
+    for (e = p->row_ptr[i]; e < p->row_ptr[i + 1]; ++e)
+        sum += s->x[p->col[e]];
+    deg = (double)(p->row_ptr[i + 1] - p->row_ptr[i]);
+    Qii = s->tau * deg + s->lam;
+    m = (s->lam * p->y[i] + s->tau * p->rho * sum) / Qii;
+    z = (flags & ORC_ZERO_NOISE) ? 0.0 : orc_normal(p->seed, (uint32_t)i, t, p->instance, 0u);
+    s->x[i] = m + z / sqrt(Qii);
+}
+
+/* Run nsweeps sweeps.  visit (optional, length n) lists the sites in the
+ * order they are visited inside each color; NULL means ascending id.  The
+ * result does not depend on it because a color's sites never read one
+ * another.  nthreads > 1 spreads the sites of one color over threads. */
+int orc_sweeps(const orc_problem *p, orc_chain *s, int64_t nsweeps, uint32_t flags,
+               const int64_t *visit, int32_t nthreads)
+{
+    int64_t it, n = p->n;
+#ifdef _OPENMP
+    if (nthreads < 1)
+        nthreads = 1;
+#else
+    (void)nthreads;
+#endif
+    for (it = 0; it < nsweeps; ++it) {
+        uint32_t t = (uint32_t)s->sweep;
+        int32_t c;
+        int64_t i;
+        for (c = 0; c < p->k; ++c) {
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+#endif
+            for (i = 0; i < n; ++i) {
+                int64_t site = visit ? visit[i] : i;
+                if (p->color[site] == c)
+                    orc_update_site(p, s, site, t, flags);
+            }
+        }
+        orc_quadratic_terms(p, s->x, &s->q, &s->sse);
+        if ((int64_t)t >= p->burn_in) {
+            for (i = 0; i < n; ++i) {
+                s->s1[i] += s->x[i];
+                s->s2[i] += s->x[i] * s->x[i];
+            }
+            s->n_acc += 1;
+        }
+        s->sweep += 1;
+        if (flags & ORC_WITH_HYPER) {
+            if (orc_hyper(p, s))
+                return 1;
+        }
+    }
+    return 0;
+}
+
+/* Posterior mean S1/N and unbiased variance (S2 - S1^2/N)/(N-1). */
+void orc_stats(const orc_chain *s, int64_t n, double *mean, double *var)
+{
+    int64_t i;
+    double N = (double)s->n_acc;
+    for (i = 0; i < n; ++i) {
+        mean[i] = s->s1[i] / N;
+        var[i] = (s->s2[i] - s->s1[i] * s->s1[i] / N) / (N - 1.0);
+    }
+}
