@@ -1,0 +1,225 @@
+/*
+ * gmrf.h -- C ABI of libgmrf: chromatic Gibbs sampling of a Gaussian Markov
+ * random field (GMRF) with a conditional autoregressive (CAR) prior on an
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Model (Brown, McMahan & Self 2017, Sec. 3.1 image model without intercept,
+ * Sec. 3.2 proper CAR), written with precisions tau (prior) and lam = 1/sigma^2
+ * (noise):
+ *     y | x, lam  ~ N(x, I / lam)
+ *     x | tau     ~ N(0, (tau (D - rho W))^-)   rho = 1: intrinsic CAR (IAR)
+ *     tau ~ Gamma(a_tau, rate b_tau),  lam ~ Gamma(a_lam, rate b_lam)
+ * W is the 0/1 adjacency of an undirected graph (w_ij = I(i ~ j)) and
+ * D = diag(row sums of W).
+ *
+ * One sweep (Sec. 2.3, Algorithm 1) visits the colors 0..k-1 of a proper
+ * coloring in order; every site i of the current color is drawn at once from
+ * its full conditional (Sec. 2.2 with A = I, Sigma = I/lam; Sec. 3.1 local
+ * characteristics):
+ *     Qii = tau * D_ii + lam
+ *     m_i = (lam * y_i + tau * rho * sum_{j~i} x_j) / Qii
+ *     x_i = m_i + z_{t,i} / sqrt(Qii)
+ * and then, with hyperparameter updates on, tau and lam are redrawn from
+ * their conjugate conditionals (Sec. 3.1, as Gamma laws of the precisions):
+ *     tau ~ Gamma(a_tau + r/2, b_tau + x'(D - rho W)x / 2),
+ *     lam ~ Gamma(a_lam + n/2, b_lam + ||y - x||^2 / 2),
+ * r = n - #connected components (intrinsic) or n (proper).  Sweeps with index
+ * t >= burn_in add x and x^2 to FP64 running sums (posterior mean/variance).
+ *
+ * Random numbers: Philox4x32-10 keyed by the 64-bit seed with counter
+ * (site id, sweep t, instance, tag); tag 0 = site normal (Box-Muller, cosine
+ * branch), tags 1/2 = the tau/lam Gamma draws (Marsaglia-Tsang).  Site ids are
+ * the caller's ORIGINAL ids, so results do not depend on the internal layout,
+ * the thread mapping or the color permutation.
+ *
+ * Conventions
+ *   - Every function returns gmrf_status (0 = GMRF_OK).  No C++ exception
+ *     crosses the ABI.  gmrf_last_error() returns a thread-local message for
+ *     the last failing call on the calling thread.
+ *   - Device work is asynchronous on the caller's stream; a kernel fault
+ *     surfaces at the next synchronising call.  A chain must be driven from
+ *     one stream at a time.
+ *   - The library allocates no device memory.  Graphs and chains live in
+ *     device workspaces the caller allocates (size from the footprint
+ *     queries) and keeps alive until the handle is destroyed.  Workspaces
+ *     must be 256-byte aligned.
+ *   - "Host" arrays are read during the call and may be freed on return.
+ */
+#ifndef GMRF_H
+#define GMRF_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GMRF_OK = 0,
+    GMRF_E_INVALID_ARG = 1, /* NULL pointer, bad size, bad flag, bad model value */
+    GMRF_E_GRAPH = 2,       /* malformed CSR: non-monotone, out of range, self-loop,
+                               duplicate or asymmetric edge, too large for int32 */
+    GMRF_E_COLORING = 3,    /* improper coloring; the message names the first bad edge */
+    GMRF_E_WORKSPACE = 4,   /* workspace NULL, misaligned or smaller than the footprint */
+    GMRF_E_DEVICE = 5,      /* HIP runtime error (message carries hipGetErrorString) */
+    GMRF_E_NUMERIC = 6      /* non-finite tau/lam or Gamma attempt cap hit on the device;
+                               reported by the next synchronising call */
+} gmrf_status;
+
+typedef enum {
+    GMRF_FP64 = 0,          /* FP64 state, draws, neighbour sums */
+    GMRF_FP32_ACC64 = 1     /* FP32 state, y, draws and neighbour sums; FP64 posterior
+                               accumulators, FP64 q/sse reductions, FP64 tau/lam */
+} gmrf_precision;
+
+/* gmrf_sweep flags */
+#define GMRF_WITH_HYPER 1u  /* draw tau, lam after every sweep (normal MCMC mode) */
+#define GMRF_CAPTURE 2u     /* record the nsweeps sweeps once as a HIP graph and replay it */
+
+/* gmrf_posterior_stats flags */
+#define GMRF_PTR_HOST 0u    /* mean / var are host pointers; the call synchronises */
+#define GMRF_PTR_DEVICE 1u  /* mean / var are device pointers; asynchronous */
+
+/* Graph description.  Either a general graph (lat_stencil = 0) given as a CSR
+ * adjacency plus a proper coloring, or a rows x cols pixel lattice with free
+ * boundary (lat_stencil = 4: edge neighbours, checkerboard coloring
+ * (r + c) mod 2, k = 2; lat_stencil = 8: edge and diagonal neighbours, 2x2
+ * parity coloring 2 (r mod 2) + (c mod 2), k = 4), site id r * cols + c.
+ * Lattice colorings are the ones found by inspection (Sec. 2.3, Fig. 1); for a
+ * lattice, row_ptr / col_idx / color may be NULL, and if color is given it must
+ * equal the parity coloring. */
+typedef struct {
+    int64_t n;              /* number of sites (lattice: rows * cols) */
+    const int64_t *row_ptr; /* host, n + 1 offsets into col_idx (general graph) */
+    const int32_t *col_idx; /* host, row_ptr[n] neighbour ids; each row ascending,
+                               no self loops, no duplicates, symmetric */
+    const int32_t *color;   /* host, n colors in 0 .. num_colors - 1 */
+    int32_t num_colors;     /* k (lattice: 2 or 4, or 0 to imply it) */
+    int32_t lat_rows, lat_cols;
+    int32_t lat_stencil;    /* 0 = general graph, 4 or 8 = lattice */
+    double rho;             /* 1 = intrinsic CAR; 0 <= rho < 1 proper CAR */
+} gmrf_graph_desc;
+
+/* Model constants of one chain. */
+typedef struct {
+    double a_tau, b_tau;    /* Gamma(shape, rate) prior of the prior precision tau */
+    double a_lam, b_lam;    /* Gamma(shape, rate) prior of the noise precision lam */
+    double tau0, lam0;      /* initial tau, lam (> 0) */
+    int64_t burn_in;        /* sweeps t < burn_in are not accumulated */
+} gmrf_model;
+
+typedef struct gmrf_graph gmrf_graph;
+typedef struct gmrf_chain gmrf_chain;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *gmrf_last_error(void);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int gmrf_version(void);
+
+/* ---- graphs (Sec. 2.3: coloring and the per-color site lists) ------------- */
+
+/* Device workspace bytes that gmrf_graph_create needs for d (host arithmetic
+ * only; 0 for a lattice, which needs no structure on the device).  Returns 0
+ * and sets the error message if d is invalid in a way visible from sizes. */
+size_t gmrf_graph_footprint(const gmrf_graph_desc *d);
+
+/* Validate d and build the device form of the graph: for a general graph the
+ * sites are permuted so that each color is a contiguous slab (color, then
+ * ascending original id), with a permuted CSR (int32) whose neighbour lists
+ * stay in ascending ORIGINAL-id order, plus the slab-to-original map.  The
+ * arrays are uploaded to d_ws (ws_bytes >= gmrf_graph_footprint(d)) on stream
+ * and the call synchronises the stream before returning.  Checks: CSR shape,
+ * ranges, symmetry, no self loops / duplicates, proper coloring (Sec. 2.3: no
+ * edge inside a color class), 0 <= rho <= 1.  Errors: GMRF_E_INVALID_ARG,
+ * GMRF_E_GRAPH, GMRF_E_COLORING, GMRF_E_WORKSPACE, GMRF_E_DEVICE. */
+int gmrf_graph_create(const gmrf_graph_desc *d, void *d_ws, size_t ws_bytes, hipStream_t stream,
+                      gmrf_graph **out);
+int gmrf_graph_destroy(gmrf_graph *g);
+
+/* Shape of a created graph: n, number of colors k, number of connected
+ * components (sets the rank r = n - components of the intrinsic prior),
+ * number of directed adjacency entries (2 |E|). */
+int gmrf_graph_info(const gmrf_graph *g, int64_t *n, int32_t *k, int64_t *components,
+                    int64_t *nnz);
+
+/* Greedy coloring of the supplementary greedy algorithm (host only): color j
+ * is a maximal independent set of the still-uncolored sites grown from the
+ * smallest id upward; colors are 0-based in discovery order.  Equivalent to
+ * first-fit in ascending id order.  color_out has n entries. */
+int gmrf_greedy_coloring(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                         int32_t *color_out, int32_t *k_out);
+
+/* ---- chains -------------------------------------------------------------- */
+
+/* Device workspace bytes of one chain of precision p on g. */
+size_t gmrf_chain_footprint(const gmrf_graph *g, gmrf_precision p);
+
+/* Create a chain: upload y (host, n values in original order, FP64; stored as
+ * FP32 for GMRF_FP32_ACC64) and x0 (host, original order, or NULL for zeros),
+ * set tau = m->tau0, lam = m->lam0, sweep = 0, clear the accumulators.  seed
+ * and instance key the chain's random numbers.  Synchronises the stream.
+ * Errors: GMRF_E_INVALID_ARG (bad model or precision, non-finite y or x0),
+ * GMRF_E_WORKSPACE, GMRF_E_DEVICE. */
+int gmrf_chain_create(const gmrf_graph *g, const gmrf_model *m, const double *y, const double *x0,
+                      gmrf_precision p, uint64_t seed, uint32_t instance, void *d_ws,
+                      size_t ws_bytes, hipStream_t stream, gmrf_chain **out);
+int gmrf_chain_destroy(gmrf_chain *c);
+
+/* Enqueue nsweeps sweeps (Algorithm 1 over all colors, with the fused
+ * x'(D - rho W)x and ||y - x||^2 reductions and the posterior accumulators).
+ * flags: GMRF_WITH_HYPER draws tau and lam after every sweep on the device;
+ * without it tau and lam stay fixed.  GMRF_CAPTURE records the nsweeps sweeps
+ * as a HIP graph the first time a (nsweeps, flags) pair is seen on this chain
+ * and replays it afterwards.  No host synchronisation. */
+int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream);
+
+/* Draw tau and lam (Sec. 3.1 conjugate conditionals) from the reductions of
+ * the last completed sweep, with that sweep's index in the random counter;
+ * sweeping without GMRF_WITH_HYPER and then calling this is bitwise the same
+ * as sweeping with it.  Asynchronous.  Errors: GMRF_E_INVALID_ARG if no sweep
+ * has completed. */
+int gmrf_hyper_update(gmrf_chain *c, hipStream_t stream);
+
+/* Set tau and lam (> 0, finite).  Asynchronous. */
+int gmrf_set_hyper(gmrf_chain *c, double tau, double lam, hipStream_t stream);
+
+/* Posterior mean S1/N and variance (S2 - S1^2/N)/(N - 1) over the N
+ * accumulated sweeps, in original site order, FP64.  With GMRF_PTR_HOST the
+ * call synchronises and mean / var / n_acc are host pointers (n_acc may be
+ * NULL); with GMRF_PTR_DEVICE mean / var are device buffers of n doubles and
+ * n_acc must be NULL.  Returns GMRF_E_NUMERIC if a device draw failed. */
+int gmrf_posterior_stats(gmrf_chain *c, double *mean, double *var, int64_t *n_acc,
+                         uint32_t flags, hipStream_t stream);
+
+/* Read the chain state: x (host, n doubles, original order), tau, lam and the
+ * number of completed sweeps; any output pointer may be NULL.  Synchronises.
+ * Returns GMRF_E_NUMERIC if a device draw failed. */
+int gmrf_get_state(gmrf_chain *c, double *x, double *tau, double *lam, uint64_t *sweep,
+                   hipStream_t stream);
+
+/* Overwrite the chain state (checkpoint resume, tests).  x: host, original
+ * order, or NULL to keep x.  The random streams are keyed by (seed, instance,
+ * sweep, site), so resuming from a saved state continues the same chain
+ * bitwise.  Synchronises. */
+int gmrf_set_state(gmrf_chain *c, const double *x, double tau, double lam, uint64_t sweep,
+                   hipStream_t stream);
+
+/* Read / write the posterior accumulators (host, original order, n doubles
+ * each) and the accumulated-sweep count, for checkpointing.  Synchronise. */
+int gmrf_get_accumulators(gmrf_chain *c, double *s1, double *s2, int64_t *n_acc,
+                          hipStream_t stream);
+int gmrf_set_accumulators(gmrf_chain *c, const double *s1, const double *s2, int64_t n_acc,
+                          hipStream_t stream);
+
+/* Reductions of the last completed sweep: q = x'(D - rho W)x and
+ * sse = ||y - x||^2 (FP64).  Synchronises. */
+int gmrf_last_reductions(gmrf_chain *c, double *q, double *sse, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMRF_H */

@@ -1,0 +1,1104 @@
+// gmrf.hip -- HIP kernels and C ABI of libgmrf (gfx950).
+//
+// Hot path (Sec. 2.3, Algorithm 1, with the full conditionals of Sec. 3.1 /
+// 3.2 and the conjugate precision draws of Sec. 3.1):
+//
+//   * Lattice graphs (4- and 8-neighbour stencils, parity colorings): ONE
+//     kernel per sweep.  Each workgroup owns a TH x TW tile of the lattice,
+//     stages the tile plus a halo of depth k (the number of colors) in LDS,
+//     and runs the k color phases in LDS.  Phase j updates the sites of color
+//     j on the tile grown by k-1-j rings, so the values that later phases read
+//     at the tile border are recomputed locally instead of being exchanged:
+//     the random numbers are keyed by (site, sweep), so a recomputed halo site
+//     is bitwise the value its owning tile computes.  The lattice state is
+//     ping-ponged between two buffers (sweep t reads buffer t&1 and writes the
+//     other), so tiles never see a neighbour's new values through memory.
+//   * General graphs (CSR): one kernel per color over a contiguous color slab
+//     of a color-permuted CSR; sites of one color never read each other, so
+//     the slab is updated in place.
+//   * Every sweep kernel fuses the reductions q = x'(D - rho W)x (each edge
+//     counted once, by its higher-colored endpoint, after both ends are final)
+//     and sse = ||y - x||^2 in FP64, and the posterior accumulators.  Blocks
+//     leave FP64 partials; the last block of the sweep (atomic ticket) sums
+//     them in fixed slot order and draws tau and lam on the device, so a sweep
+//     has one global dependency and no host round trip.
+//   * The sweep index t lives in device memory, so a captured HIP graph of
+//     sweeps can be replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "gmrf.h"
+#include "internal.hpp"
+#include "rng.hpp"
+
+namespace gmrf {
+
+const char *error_cstr();
+
+// ---------------------------------------------------------------------------
+// device-side chain state
+// ---------------------------------------------------------------------------
+struct DevState {
+    double tau, lam;            // current precisions
+    double q, sse;              // reductions of the last completed sweep
+    unsigned long long sweep;   // completed sweeps
+    long long n_acc;            // accumulated sweeps
+    unsigned int ticket;        // blocks of the running sweep that finished
+    unsigned int status;        // bit 0: Gamma draw failed / non-finite
+};
+
+constexpr unsigned kStatusGamma = 1u;
+
+struct SweepArgs {
+    DevState *st;
+    double *partials;           // two doubles per block slot
+    double *s1, *s2;            // posterior accumulators (layout of x)
+    double shape_tau, b_tau, shape_lam, b_lam;
+    double rho;
+    long long burn_in;
+    unsigned long long seed;
+    unsigned int instance;
+    int with_hyper;
+    int total_slots;            // blocks per sweep (all color passes)
+};
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Block sum of two values in a fixed tree; the result is valid in thread 0.
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *red)
+{
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[wid] = a;
+        red[kWaves + wid] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = red[0];
+        b = red[kWaves];
+        for (int w = 1; w < kWaves; ++w) {
+            a += red[w];
+            b += red[kWaves + w];
+        }
+    }
+}
+
+// Draw tau (lane 0) and lam (lane 1) after sweep t from the reductions q, sse
+// (Sec. 3.1 conjugate conditionals; precisions, rate form).
+__device__ __forceinline__ void draw_hyper(const SweepArgs &a, unsigned t, double q, double sse,
+                                           int lane)
+{
+    if (lane < 2) {
+        const double shape = lane == 0 ? a.shape_tau : a.shape_lam;
+        const double rate = lane == 0 ? a.b_tau + 0.5 * q : a.b_lam + 0.5 * sse;
+        double v = 0.0;
+        const bool ok = gamma_draw(shape, rate, a.seed, t, a.instance, (unsigned)(lane + 1), &v);
+        if (ok && isfinite(v) && v > 0.0) {
+            if (lane == 0)
+                a.st->tau = v;
+            else
+                a.st->lam = v;
+        } else {
+            atomicOr(&a.st->status, kStatusGamma);
+        }
+    }
+}
+
+// End of a sweep block: publish the block's partials; the last block of the
+// sweep sums all partials in slot order, stores q / sse, draws tau / lam,
+// counts the accumulated sweep and advances the sweep index.
+__device__ void finish_block(const SweepArgs &a, double q, double sse, int slot, unsigned t)
+{
+    __shared__ double red[2 * kWaves];
+    __shared__ int is_last;
+    block_sum2(q, sse, red);
+    if (threadIdx.x == 0) {
+        a.partials[2 * slot] = q;
+        a.partials[2 * slot + 1] = sse;
+        __threadfence();
+        const unsigned prev = atomicAdd(&a.st->ticket, 1u);
+        is_last = (prev == (unsigned)a.total_slots - 1u);
+    }
+    __syncthreads();
+    if (!is_last)
+        return;
+    __threadfence();
+    double tq = 0.0, ts = 0.0;
+    const volatile double *p = a.partials;
+    for (int i = threadIdx.x; i < a.total_slots; i += kThreads) {
+        tq += p[2 * i];
+        ts += p[2 * i + 1];
+    }
+    __syncthreads();
+    block_sum2(tq, ts, red);
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        tq = __shfl(tq, 0, 64);
+        ts = __shfl(ts, 0, 64);
+        if (a.with_hyper)
+            draw_hyper(a, t, tq, ts, lane);
+        if (lane == 0) {
+            a.st->q = tq;
+            a.st->sse = ts;
+            if ((long long)t >= a.burn_in)
+                a.st->n_acc += 1;
+            a.st->sweep = (unsigned long long)t + 1ull;
+            a.st->ticket = 0u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// lattice: fused all-colors sweep
+// ---------------------------------------------------------------------------
+template <typename Real> struct LatArgs {
+    Real *x0, *x1;              // ping-pong state buffers, row-major
+    const Real *y;
+    int rows, cols;
+    int tiles_c;                // tiles per lattice row
+};
+
+// Color of a lattice site under the parity coloring of the stencil.
+template <int ST> __host__ __device__ constexpr int parity_color(int pr, int pc)
+{
+    return ST == 4 ? ((pr + pc) & 1) : (2 * (pr & 1) + (pc & 1));
+}
+
+// Does the neighbour at offset (dr, dc) of a color-J site have a lower color?
+// (J's parities: 8-neighbour: row parity J>>1, column parity J&1;
+// 4-neighbour: r + c parity J, represented as row parity 0, column parity J.)
+template <int ST, int J> __host__ __device__ constexpr bool lower_nb(int dr, int dc)
+{
+    return ST == 4 ? (parity_color<4>(0, J + dr + dc) < J)
+                   : (parity_color<8>((J >> 1) + dr, (J & 1) + dc) < J);
+}
+
+template <typename Real> struct SiteCtx {
+    Real tau, lam, tau_rho;
+    double one_minus_rho, rho;
+    unsigned t;
+    unsigned long long seed;
+    unsigned instance;
+};
+
+// One site of Algorithm 1 on the LDS tile: neighbour sum in ascending
+// original-id order, conditional mean and precision, the draw; for interior
+// sites also the q / sse terms.
+template <typename Real, int ST, int TH, int TW, int J>
+__device__ __forceinline__ void lattice_site(Real *xs, const Real *__restrict__ y, int r, int c,
+                                             int r0, int c0, int rows, int cols,
+                                             const SiteCtx<Real> &sc, double &q, double &sse)
+{
+    constexpr int K = ST == 4 ? 2 : 4;
+    constexpr int H = K;
+    constexpr int LW = TW + 2 * H;
+    Real *p = xs + (r - r0 + H) * LW + (c - c0 + H);
+    const bool up = r > 0, dn = r + 1 < rows, lf = c > 0, rt = c + 1 < cols;
+    Real s = (Real)0;
+    int deg = 0;
+    if (ST == 8 && up && lf) { s += p[-LW - 1]; ++deg; }
+    if (up) { s += p[-LW]; ++deg; }
+    if (ST == 8 && up && rt) { s += p[-LW + 1]; ++deg; }
+    if (lf) { s += p[-1]; ++deg; }
+    if (rt) { s += p[1]; ++deg; }
+    if (ST == 8 && dn && lf) { s += p[LW - 1]; ++deg; }
+    if (dn) { s += p[LW]; ++deg; }
+    if (ST == 8 && dn && rt) { s += p[LW + 1]; ++deg; }
+
+    const unsigned site = (unsigned)r * (unsigned)cols + (unsigned)c;
+    const Real yv = y[(size_t)r * cols + c];
+    const Words4 w = draw_words(sc.seed, site, sc.t, sc.instance, 0u);
+    const Real z = site_normal<Real>(w);
+    const Real Q = sc.tau * (Real)deg + sc.lam;
+    const Real m = (sc.lam * yv + sc.tau_rho * s) / Q;
+    Real xn;
+    if constexpr (sizeof(Real) == 8)
+        xn = m + z / sqrt(Q);
+    else
+        xn = m + z * rsqrtf(Q);
+    *p = xn;
+
+    if (r >= r0 && r < r0 + TH && c >= c0 && c < c0 + TW) {
+        const double xd = (double)xn;
+        double edge = 0.0;
+#define GMRF_EDGE(cond, dr, dc, off)                                                  \
+    if (lower_nb<ST, J>(dr, dc) && (cond)) {                                          \
+        const double d = xd - (double)p[off];                                         \
+        edge += d * d;                                                                \
+    }
+        if (ST == 8) GMRF_EDGE(up && lf, -1, -1, -LW - 1)
+        GMRF_EDGE(up, -1, 0, -LW)
+        if (ST == 8) GMRF_EDGE(up && rt, -1, 1, -LW + 1)
+        GMRF_EDGE(lf, 0, -1, -1)
+        GMRF_EDGE(rt, 0, 1, 1)
+        if (ST == 8) GMRF_EDGE(dn && lf, 1, -1, LW - 1)
+        GMRF_EDGE(dn, 1, 0, LW)
+        if (ST == 8) GMRF_EDGE(dn && rt, 1, 1, LW + 1)
+#undef GMRF_EDGE
+        q += sc.one_minus_rho * (double)deg * xd * xd + sc.rho * edge;
+        const double rr = (double)yv - xd;
+        sse += rr * rr;
+    }
+}
+
+// Phase J: every color-J site of the tile grown by E = k-1-J rings.
+template <typename Real, int ST, int TH, int TW, int J>
+__device__ __forceinline__ void lattice_phase(Real *xs, const Real *__restrict__ y, int r0, int c0,
+                                              int rows, int cols, const SiteCtx<Real> &sc,
+                                              double &q, double &sse)
+{
+    constexpr int K = ST == 4 ? 2 : 4;
+    constexpr int E = K - 1 - J;
+    int ra = max(r0 - E, 0);
+    const int rb = min(r0 + TH + E, rows);
+    int ca = max(c0 - E, 0);
+    const int cb = min(c0 + TW + E, cols);
+    if constexpr (ST == 8) {
+        constexpr int PR = J >> 1, PC = J & 1;
+        ra += ((ra & 1) != PR);
+        ca += ((ca & 1) != PC);
+        const int nR = rb > ra ? (rb - ra + 1) >> 1 : 0;
+        const int nC = cb > ca ? (cb - ca + 1) >> 1 : 0;
+        const int total = nR * nC;
+        for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+            const int R = idx / nC, C = idx - R * nC;
+            lattice_site<Real, ST, TH, TW, J>(xs, y, ra + 2 * R, ca + 2 * C, r0, c0, rows, cols,
+                                              sc, q, sse);
+        }
+    } else {
+        const int nR = rb > ra ? rb - ra : 0;
+        const int nC = cb > ca ? (cb - ca + 1) >> 1 : 0;
+        const int total = nR * nC;
+        for (int idx = threadIdx.x; idx < total; idx += kThreads) {
+            const int R = idx / nC, C = idx - R * nC;
+            const int r = ra + R;
+            const int c = ca + ((r + ca + J) & 1) + 2 * C;
+            if (c < cb)
+                lattice_site<Real, ST, TH, TW, J>(xs, y, r, c, r0, c0, rows, cols, sc, q, sse);
+        }
+    }
+}
+
+// XCD-aware tile order: the hardware hands block b to XCD b mod 8, so give
+// each XCD a contiguous run of tiles (rows of the lattice) to keep the halo
+// re-reads of neighbouring tiles inside one L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int per = nb >> 3, rem = nb & 7, x = b & 7;
+    return x * per + min(x, rem) + (b >> 3);
+}
+
+template <typename Real, int ST, int TH, int TW>
+__global__ __launch_bounds__(kThreads) void lattice_sweep_kernel(LatArgs<Real> la, SweepArgs a)
+{
+    constexpr int K = ST == 4 ? 2 : 4;
+    constexpr int H = K;
+    constexpr int LH = TH + 2 * H, LW = TW + 2 * H;
+    __shared__ Real xs[LH * LW];
+
+    const unsigned t = (unsigned)a.st->sweep;
+    SiteCtx<Real> sc;
+    const double tau = a.st->tau, lam = a.st->lam;
+    sc.tau = (Real)tau;
+    sc.lam = (Real)lam;
+    sc.tau_rho = (Real)(tau * a.rho);
+    sc.one_minus_rho = 1.0 - a.rho;
+    sc.rho = a.rho;
+    sc.t = t;
+    sc.seed = a.seed;
+    sc.instance = a.instance;
+
+    const Real *src = (t & 1u) ? la.x1 : la.x0;
+    Real *dst = (t & 1u) ? la.x0 : la.x1;
+    const int rows = la.rows, cols = la.cols;
+    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int tr = tile / la.tiles_c, tc = tile - tr * la.tiles_c;
+    const int r0 = tr * TH, c0 = tc * TW;
+
+    for (int idx = threadIdx.x; idx < LH * LW; idx += kThreads) {
+        const int lr = idx / LW, lc = idx - lr * LW;
+        const int r = r0 - H + lr, c = c0 - H + lc;
+        if (r >= 0 && r < rows && c >= 0 && c < cols)
+            xs[idx] = src[(size_t)r * cols + c];
+    }
+    __syncthreads();
+
+    double q = 0.0, sse = 0.0;
+    lattice_phase<Real, ST, TH, TW, 0>(xs, la.y, r0, c0, rows, cols, sc, q, sse);
+    __syncthreads();
+    lattice_phase<Real, ST, TH, TW, 1>(xs, la.y, r0, c0, rows, cols, sc, q, sse);
+    __syncthreads();
+    if constexpr (K == 4) {
+        lattice_phase<Real, ST, TH, TW, 2>(xs, la.y, r0, c0, rows, cols, sc, q, sse);
+        __syncthreads();
+        lattice_phase<Real, ST, TH, TW, 3>(xs, la.y, r0, c0, rows, cols, sc, q, sse);
+        __syncthreads();
+    }
+
+    const bool acc = (long long)t >= a.burn_in;
+    for (int idx = threadIdx.x; idx < TH * TW; idx += kThreads) {
+        const int ir = idx / TW, ic = idx - ir * TW;
+        const int r = r0 + ir, c = c0 + ic;
+        if (r < rows && c < cols) {
+            const Real v = xs[(ir + H) * LW + ic + H];
+            const size_t g = (size_t)r * cols + c;
+            dst[g] = v;
+            if (acc) {
+                const double dv = (double)v;
+                a.s1[g] += dv;
+                a.s2[g] += dv * dv;
+            }
+        }
+    }
+    finish_block(a, q, sse, (int)blockIdx.x, t);
+}
+
+// ---------------------------------------------------------------------------
+// general graphs: one color slab per launch
+// ---------------------------------------------------------------------------
+template <typename Real> struct CsrArgs {
+    const int *row_ptr;         // permuted CSR (slab positions)
+    const int *col;
+    const int *orig;            // slab position -> original id (random-number key)
+    Real *x;
+    const Real *y;
+};
+
+template <typename Real>
+__global__ __launch_bounds__(kThreads) void csr_pass_kernel(CsrArgs<Real> ca, SweepArgs a, int lo,
+                                                            int cnt, int slot_base)
+{
+    const unsigned t = (unsigned)a.st->sweep;
+    const double tau_d = a.st->tau, lam_d = a.st->lam;
+    const Real tau = (Real)tau_d, lam = (Real)lam_d, tau_rho = (Real)(tau_d * a.rho);
+    const int p = lo + (int)blockIdx.x * kThreads + (int)threadIdx.x;
+    double q = 0.0, sse = 0.0;
+    if (p < lo + cnt) {
+        const int e0 = ca.row_ptr[p], e1 = ca.row_ptr[p + 1];
+        Real s = (Real)0;
+        for (int e = e0; e < e1; ++e)
+            s += ca.x[ca.col[e]];
+        const int deg = e1 - e0;
+        const Real yv = ca.y[p];
+        const Words4 w = draw_words(a.seed, (unsigned)ca.orig[p], t, a.instance, 0u);
+        const Real z = site_normal<Real>(w);
+        const Real Q = tau * (Real)deg + lam;
+        const Real m = (lam * yv + tau_rho * s) / Q;
+        Real xn;
+        if constexpr (sizeof(Real) == 8)
+            xn = m + z / sqrt(Q);
+        else
+            xn = m + z * rsqrtf(Q);
+        ca.x[p] = xn;
+        const double xd = (double)xn;
+        double edge = 0.0;
+        for (int e = e0; e < e1; ++e) {
+            const int j = ca.col[e];
+            if (j < lo) {                  // lower color: already final this sweep
+                const double d = xd - (double)ca.x[j];
+                edge += d * d;
+            }
+        }
+        q = (1.0 - a.rho) * (double)deg * xd * xd + a.rho * edge;
+        const double rr = (double)yv - xd;
+        sse = rr * rr;
+        if ((long long)t >= a.burn_in) {
+            a.s1[p] += xd;
+            a.s2[p] += xd * xd;
+        }
+    }
+    finish_block(a, q, sse, slot_base + (int)blockIdx.x, t);
+}
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+__global__ void hyper_kernel(SweepArgs a)
+{
+    const unsigned t = (unsigned)(a.st->sweep - 1ull);
+    draw_hyper(a, t, a.st->q, a.st->sse, (int)threadIdx.x);
+}
+
+__global__ void set_hyper_kernel(DevState *st, double tau, double lam)
+{
+    st->tau = tau;
+    st->lam = lam;
+}
+
+__global__ void stats_kernel(const double *s1, const double *s2, const int *orig, long long n,
+                             const DevState *st, double *mean, double *var)
+{
+    const double N = (double)st->n_acc;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x) {
+        const long long o = orig ? (long long)orig[p] : p;
+        mean[o] = s1[p] / N;
+        var[o] = (s2[p] - s1[p] * s1[p] / N) / (N - 1.0);
+    }
+}
+
+} // namespace gmrf
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+using namespace gmrf;
+
+struct gmrf_graph {
+    HostGraph h;
+    int *d_row_ptr = nullptr, *d_col = nullptr, *d_orig = nullptr;
+};
+
+struct gmrf_chain {
+    const gmrf_graph *g = nullptr;
+    gmrf_precision prec = GMRF_FP64;
+    gmrf_model model{};
+    uint64_t seed = 0;
+    uint32_t instance = 0;
+    int64_t rank = 0;
+    DevState *d_state = nullptr;
+    void *d_x[2] = {nullptr, nullptr};
+    void *d_y = nullptr;
+    double *d_s1 = nullptr, *d_s2 = nullptr;
+    double *d_partials = nullptr;
+    double *d_stats = nullptr;
+    int total_slots = 0;
+    std::vector<int> pass_blocks;     // CSR: blocks per color pass
+    uint64_t host_sweeps = 0;         // sweeps enqueued (host view)
+    hipStream_t capture_stream = nullptr;
+    std::map<std::pair<int, unsigned>, hipGraphExec_t> graphs;
+    std::vector<hipGraph_t> graph_defs;
+};
+
+namespace {
+
+constexpr int kLatTH = 64, kLatTW = 64;
+
+#define GMRF_HIP(expr)                                                                    \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(GMRF_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool is_lattice(const gmrf_graph *g) { return g->h.stencil != 0; }
+
+size_t real_size(gmrf_precision p) { return p == GMRF_FP64 ? 8 : 4; }
+
+int lattice_blocks(const HostGraph &h)
+{
+    const int tr = (h.rows + kLatTH - 1) / kLatTH, tc = (h.cols + kLatTW - 1) / kLatTW;
+    return tr * tc;
+}
+
+// Chain workspace layout; ptrs may be NULL to only compute the size.
+size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chain *c)
+{
+    const int64_t n = g->h.n;
+    const size_t rs = real_size(p);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += align_up(bytes);
+        return base ? base + at : nullptr;
+    };
+    int slots = 0;
+    std::vector<int> pass_blocks;
+    if (is_lattice(g)) {
+        slots = lattice_blocks(g->h);
+    } else {
+        for (int32_t col = 0; col < g->h.k; ++col) {
+            const int cnt = g->h.slab_offsets[col + 1] - g->h.slab_offsets[col];
+            const int nb = (cnt + kThreads - 1) / kThreads;
+            pass_blocks.push_back(nb);
+            slots += nb;
+        }
+    }
+    char *st = take(sizeof(DevState));
+    char *x0 = take(rs * n);
+    char *x1 = is_lattice(g) ? take(rs * n) : nullptr;
+    char *y = take(rs * n);
+    char *s1 = take(8 * n);
+    char *s2 = take(8 * n);
+    char *part = take(16 * (size_t)std::max(slots, 1));
+    char *stats = take(16 * n);
+    if (c) {
+        c->d_state = reinterpret_cast<DevState *>(st);
+        c->d_x[0] = x0;
+        c->d_x[1] = x1;
+        c->d_y = y;
+        c->d_s1 = reinterpret_cast<double *>(s1);
+        c->d_s2 = reinterpret_cast<double *>(s2);
+        c->d_partials = reinterpret_cast<double *>(part);
+        c->d_stats = reinterpret_cast<double *>(stats);
+        c->total_slots = slots;
+        c->pass_blocks = pass_blocks;
+    }
+    return off;
+}
+
+SweepArgs make_args(const gmrf_chain *c, unsigned flags)
+{
+    SweepArgs a{};
+    a.st = c->d_state;
+    a.partials = c->d_partials;
+    a.s1 = c->d_s1;
+    a.s2 = c->d_s2;
+    a.shape_tau = c->model.a_tau + 0.5 * (double)c->rank;
+    a.b_tau = c->model.b_tau;
+    a.shape_lam = c->model.a_lam + 0.5 * (double)c->g->h.n;
+    a.b_lam = c->model.b_lam;
+    a.rho = c->g->h.rho;
+    a.burn_in = (long long)c->model.burn_in;
+    a.seed = c->seed;
+    a.instance = c->instance;
+    a.with_hyper = (flags & GMRF_WITH_HYPER) ? 1 : 0;
+    a.total_slots = c->total_slots;
+    return a;
+}
+
+template <typename Real, int ST> void launch_lattice(const gmrf_chain *c, const SweepArgs &a,
+                                                     hipStream_t s)
+{
+    const HostGraph &h = c->g->h;
+    LatArgs<Real> la;
+    la.x0 = static_cast<Real *>(c->d_x[0]);
+    la.x1 = static_cast<Real *>(c->d_x[1]);
+    la.y = static_cast<const Real *>(c->d_y);
+    la.rows = h.rows;
+    la.cols = h.cols;
+    la.tiles_c = (h.cols + kLatTW - 1) / kLatTW;
+    hipLaunchKernelGGL((lattice_sweep_kernel<Real, ST, kLatTH, kLatTW>), dim3(c->total_slots),
+                       dim3(kThreads), 0, s, la, a);
+}
+
+template <typename Real> void launch_csr(const gmrf_chain *c, const SweepArgs &a, hipStream_t s)
+{
+    const HostGraph &h = c->g->h;
+    CsrArgs<Real> ca;
+    ca.row_ptr = c->g->d_row_ptr;
+    ca.col = c->g->d_col;
+    ca.orig = c->g->d_orig;
+    ca.x = static_cast<Real *>(c->d_x[0]);
+    ca.y = static_cast<const Real *>(c->d_y);
+    int slot = 0;
+    for (int32_t col = 0; col < h.k; ++col) {
+        const int nb = c->pass_blocks[col];
+        if (nb == 0)
+            continue;
+        const int lo = h.slab_offsets[col], cnt = h.slab_offsets[col + 1] - lo;
+        hipLaunchKernelGGL((csr_pass_kernel<Real>), dim3(nb), dim3(kThreads), 0, s, ca, a, lo,
+                           cnt, slot);
+        slot += nb;
+    }
+}
+
+void launch_one_sweep(const gmrf_chain *c, const SweepArgs &a, hipStream_t s)
+{
+    const bool f64 = c->prec == GMRF_FP64;
+    if (is_lattice(c->g)) {
+        if (c->g->h.stencil == 4)
+            f64 ? launch_lattice<double, 4>(c, a, s) : launch_lattice<float, 4>(c, a, s);
+        else
+            f64 ? launch_lattice<double, 8>(c, a, s) : launch_lattice<float, 8>(c, a, s);
+    } else {
+        f64 ? launch_csr<double>(c, a, s) : launch_csr<float>(c, a, s);
+    }
+}
+
+int read_state(gmrf_chain *c, DevState *out, hipStream_t s)
+{
+    GMRF_HIP(hipMemcpyAsync(out, c->d_state, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    GMRF_HIP(hipStreamSynchronize(s));
+    return GMRF_OK;
+}
+
+int check_status(const DevState &st)
+{
+    if (st.status & kStatusGamma)
+        return fail(GMRF_E_NUMERIC,
+                    "device: a tau/lam Gamma draw hit the attempt cap or was not finite");
+    return GMRF_OK;
+}
+
+// Current state buffer: lattice chains ping-pong on the sweep parity.
+void *current_x(const gmrf_chain *c, uint64_t sweep)
+{
+    return is_lattice(c->g) ? c->d_x[sweep & 1u] : c->d_x[0];
+}
+
+// x in layout order (Real) <-> original-order doubles.
+template <typename Real>
+void to_layout(const gmrf_chain *c, const double *x, std::vector<char> &buf)
+{
+    const int64_t n = c->g->h.n;
+    buf.resize(sizeof(Real) * n);
+    Real *o = reinterpret_cast<Real *>(buf.data());
+    for (int64_t p = 0; p < n; ++p)
+        o[p] = (Real)x[is_lattice(c->g) ? p : c->g->h.orig_of_slab[p]];
+}
+
+template <typename Real>
+void from_layout(const gmrf_chain *c, const std::vector<char> &buf, double *x)
+{
+    const int64_t n = c->g->h.n;
+    const Real *o = reinterpret_cast<const Real *>(buf.data());
+    for (int64_t p = 0; p < n; ++p)
+        x[is_lattice(c->g) ? p : c->g->h.orig_of_slab[p]] = (double)o[p];
+}
+
+int upload_real(const gmrf_chain *c, void *dst, const double *x, hipStream_t s)
+{
+    std::vector<char> buf;
+    if (c->prec == GMRF_FP64)
+        to_layout<double>(c, x, buf);
+    else
+        to_layout<float>(c, x, buf);
+    GMRF_HIP(hipMemcpyAsync(dst, buf.data(), buf.size(), hipMemcpyHostToDevice, s));
+    GMRF_HIP(hipStreamSynchronize(s));
+    return GMRF_OK;
+}
+
+int upload_doubles_layout(const gmrf_chain *c, double *dst, const double *x, hipStream_t s)
+{
+    const int64_t n = c->g->h.n;
+    std::vector<double> buf(n);
+    for (int64_t p = 0; p < n; ++p)
+        buf[p] = x[is_lattice(c->g) ? p : c->g->h.orig_of_slab[p]];
+    GMRF_HIP(hipMemcpyAsync(dst, buf.data(), 8 * n, hipMemcpyHostToDevice, s));
+    GMRF_HIP(hipStreamSynchronize(s));
+    return GMRF_OK;
+}
+
+int download_doubles_layout(const gmrf_chain *c, const double *src, double *x, hipStream_t s)
+{
+    const int64_t n = c->g->h.n;
+    std::vector<double> buf(n);
+    GMRF_HIP(hipMemcpyAsync(buf.data(), src, 8 * n, hipMemcpyDeviceToHost, s));
+    GMRF_HIP(hipStreamSynchronize(s));
+    for (int64_t p = 0; p < n; ++p)
+        x[is_lattice(c->g) ? p : c->g->h.orig_of_slab[p]] = buf[p];
+    return GMRF_OK;
+}
+
+bool finite_array(const double *v, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i]))
+            return false;
+    return true;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *gmrf_last_error(void) { return error_cstr(); }
+
+int gmrf_version(void) { return 10000; }
+
+size_t gmrf_graph_footprint(const gmrf_graph_desc *d)
+{
+    if (!d)
+        return (size_t)fail(GMRF_E_INVALID_ARG, "graph_footprint: NULL description") * 0;
+    if (d->lat_stencil != 0)
+        return 0;
+    if (d->n < 1 || !d->row_ptr) {
+        set_error("graph_footprint: n >= 1 and row_ptr are required");
+        return 0;
+    }
+    return graph_device_bytes(d->n, d->row_ptr[d->n], false);
+}
+
+int gmrf_graph_create(const gmrf_graph_desc *d, void *d_ws, size_t ws_bytes, hipStream_t stream,
+                      gmrf_graph **out)
+{
+    clear_error();
+    if (!out)
+        return fail(GMRF_E_INVALID_ARG, "graph_create: out is NULL");
+    *out = nullptr;
+    gmrf_graph *g = new gmrf_graph();
+    int rc = build_host_graph(d, &g->h);
+    if (rc != GMRF_OK) {
+        delete g;
+        return rc;
+    }
+    if (!is_lattice(g)) {
+        const size_t need = graph_device_bytes(g->h.n, g->h.nnz, false);
+        if (!d_ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0) {
+            delete g;
+            return fail(GMRF_E_WORKSPACE, "graph_create: workspace NULL, misaligned or smaller "
+                                          "than gmrf_graph_footprint (" +
+                                              std::to_string(need) + " bytes)");
+        }
+        char *b = static_cast<char *>(d_ws);
+        g->d_row_ptr = reinterpret_cast<int *>(b);
+        b += align_up(sizeof(int) * (size_t)(g->h.n + 1));
+        g->d_col = reinterpret_cast<int *>(b);
+        b += align_up(sizeof(int) * (size_t)g->h.nnz);
+        g->d_orig = reinterpret_cast<int *>(b);
+        hipError_t e = hipMemcpyAsync(g->d_row_ptr, g->h.row_ptr.data(),
+                                      sizeof(int) * (g->h.n + 1), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess && g->h.nnz > 0)
+            e = hipMemcpyAsync(g->d_col, g->h.col.data(), sizeof(int) * g->h.nnz,
+                               hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(g->d_orig, g->h.orig_of_slab.data(), sizeof(int) * g->h.n,
+                               hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            delete g;
+            return fail(GMRF_E_DEVICE, std::string("graph_create: upload: ") + hipGetErrorString(e));
+        }
+    }
+    *out = g;
+    return GMRF_OK;
+}
+
+int gmrf_graph_destroy(gmrf_graph *g)
+{
+    delete g;
+    return GMRF_OK;
+}
+
+int gmrf_graph_info(const gmrf_graph *g, int64_t *n, int32_t *k, int64_t *components,
+                    int64_t *nnz)
+{
+    if (!g)
+        return fail(GMRF_E_INVALID_ARG, "graph_info: NULL graph");
+    if (n) *n = g->h.n;
+    if (k) *k = g->h.k;
+    if (components) *components = g->h.components;
+    if (nnz) *nnz = g->h.nnz;
+    return GMRF_OK;
+}
+
+int gmrf_greedy_coloring(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                         int32_t *color_out, int32_t *k_out)
+{
+    clear_error();
+    return greedy_coloring_host(n, row_ptr, col_idx, color_out, k_out);
+}
+
+size_t gmrf_chain_footprint(const gmrf_graph *g, gmrf_precision p)
+{
+    if (!g || (p != GMRF_FP64 && p != GMRF_FP32_ACC64)) {
+        set_error("chain_footprint: NULL graph or bad precision");
+        return 0;
+    }
+    return chain_layout(g, p, nullptr, nullptr);
+}
+
+int gmrf_chain_create(const gmrf_graph *g, const gmrf_model *m, const double *y, const double *x0,
+                      gmrf_precision p, uint64_t seed, uint32_t instance, void *d_ws,
+                      size_t ws_bytes, hipStream_t stream, gmrf_chain **out)
+{
+    clear_error();
+    if (!out)
+        return fail(GMRF_E_INVALID_ARG, "chain_create: out is NULL");
+    *out = nullptr;
+    if (!g || !m || !y)
+        return fail(GMRF_E_INVALID_ARG, "chain_create: graph, model and y are required");
+    if (p != GMRF_FP64 && p != GMRF_FP32_ACC64)
+        return fail(GMRF_E_INVALID_ARG, "chain_create: bad precision");
+    const int64_t n = g->h.n;
+    const int64_t rank = g->h.rho == 1.0 ? n - g->h.components : n;
+    const double shape_tau = m->a_tau + 0.5 * (double)rank, shape_lam = m->a_lam + 0.5 * (double)n;
+    if (!(m->b_tau > 0.0) || !(m->b_lam > 0.0) || !(shape_tau >= 1.0) || !(shape_lam >= 1.0) ||
+        !std::isfinite(m->a_tau) || !std::isfinite(m->a_lam) || !std::isfinite(m->b_tau) ||
+        !std::isfinite(m->b_lam))
+        return fail(GMRF_E_INVALID_ARG, "chain_create: priors need rates > 0 and conditional "
+                                        "shapes a_tau + r/2 >= 1, a_lam + n/2 >= 1");
+    if (!(m->tau0 > 0.0) || !(m->lam0 > 0.0) || !std::isfinite(m->tau0) ||
+        !std::isfinite(m->lam0))
+        return fail(GMRF_E_INVALID_ARG, "chain_create: tau0 and lam0 must be finite and > 0");
+    if (m->burn_in < 0)
+        return fail(GMRF_E_INVALID_ARG, "chain_create: burn_in must be >= 0");
+    if (!finite_array(y, n) || (x0 && !finite_array(x0, n)))
+        return fail(GMRF_E_INVALID_ARG, "chain_create: y and x0 must be finite");
+    const size_t need = chain_layout(g, p, nullptr, nullptr);
+    if (!d_ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0)
+        return fail(GMRF_E_WORKSPACE, "chain_create: workspace NULL, misaligned or smaller than "
+                                      "gmrf_chain_footprint (" +
+                                          std::to_string(need) + " bytes)");
+    gmrf_chain *c = new gmrf_chain();
+    c->g = g;
+    c->prec = p;
+    c->model = *m;
+    c->seed = seed;
+    c->instance = instance;
+    c->rank = rank;
+    chain_layout(g, p, static_cast<char *>(d_ws), c);
+
+    auto cleanup = [&](int rc) {
+        delete c;
+        return rc;
+    };
+    DevState st{};
+    st.tau = m->tau0;
+    st.lam = m->lam0;
+    hipError_t e = hipMemcpyAsync(c->d_state, &st, sizeof st, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->d_s1, 0, 8 * n, stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->d_s2, 0, 8 * n, stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->d_partials, 0, 16 * (size_t)std::max(c->total_slots, 1), stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(stream);
+    if (e != hipSuccess)
+        return cleanup(fail(GMRF_E_DEVICE, std::string("chain_create: ") + hipGetErrorString(e)));
+    int rc = upload_real(c, c->d_y, y, stream);
+    if (rc != GMRF_OK)
+        return cleanup(rc);
+    std::vector<double> zeros;
+    if (!x0) {
+        zeros.assign(n, 0.0);
+        x0 = zeros.data();
+    }
+    rc = upload_real(c, c->d_x[0], x0, stream);
+    if (rc != GMRF_OK)
+        return cleanup(rc);
+    *out = c;
+    return GMRF_OK;
+}
+
+int gmrf_chain_destroy(gmrf_chain *c)
+{
+    if (!c)
+        return GMRF_OK;
+    for (auto &kv : c->graphs)
+        (void)hipGraphExecDestroy(kv.second);
+    for (hipGraph_t gdef : c->graph_defs)
+        (void)hipGraphDestroy(gdef);
+    if (c->capture_stream)
+        (void)hipStreamDestroy(c->capture_stream);
+    delete c;
+    return GMRF_OK;
+}
+
+int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream)
+{
+    clear_error();
+    if (!c || nsweeps < 0 || (flags & ~(GMRF_WITH_HYPER | GMRF_CAPTURE)))
+        return fail(GMRF_E_INVALID_ARG, "sweep: NULL chain, negative count or unknown flag");
+    if (nsweeps == 0)
+        return GMRF_OK;
+    const SweepArgs a = make_args(c, flags);
+    if (flags & GMRF_CAPTURE) {
+        const auto key = std::make_pair((int)nsweeps, flags & GMRF_WITH_HYPER);
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            if (!c->capture_stream)
+                GMRF_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+            GMRF_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+            for (int i = 0; i < nsweeps; ++i)
+                launch_one_sweep(c, a, c->capture_stream);
+            hipGraph_t gdef = nullptr;
+            const hipError_t le = hipGetLastError();
+            GMRF_HIP(hipStreamEndCapture(c->capture_stream, &gdef));
+            if (le != hipSuccess) {
+                (void)hipGraphDestroy(gdef);
+                return fail(GMRF_E_DEVICE, std::string("sweep: capture: ") + hipGetErrorString(le));
+            }
+            hipGraphExec_t exec = nullptr;
+            GMRF_HIP(hipGraphInstantiate(&exec, gdef, nullptr, nullptr, 0));
+            c->graph_defs.push_back(gdef);
+            it = c->graphs.emplace(key, exec).first;
+        }
+        GMRF_HIP(hipGraphLaunch(it->second, stream));
+    } else {
+        for (int i = 0; i < nsweeps; ++i)
+            launch_one_sweep(c, a, stream);
+        GMRF_HIP(hipGetLastError());
+    }
+    c->host_sweeps += (uint64_t)nsweeps;
+    return GMRF_OK;
+}
+
+int gmrf_hyper_update(gmrf_chain *c, hipStream_t stream)
+{
+    clear_error();
+    if (!c)
+        return fail(GMRF_E_INVALID_ARG, "hyper_update: NULL chain");
+    if (c->host_sweeps == 0)
+        return fail(GMRF_E_INVALID_ARG, "hyper_update: no completed sweep");
+    const SweepArgs a = make_args(c, GMRF_WITH_HYPER);
+    hipLaunchKernelGGL(hyper_kernel, dim3(1), dim3(64), 0, stream, a);
+    GMRF_HIP(hipGetLastError());
+    return GMRF_OK;
+}
+
+int gmrf_set_hyper(gmrf_chain *c, double tau, double lam, hipStream_t stream)
+{
+    clear_error();
+    if (!c || !(tau > 0.0) || !(lam > 0.0) || !std::isfinite(tau) || !std::isfinite(lam))
+        return fail(GMRF_E_INVALID_ARG, "set_hyper: NULL chain or tau / lam not finite and > 0");
+    hipLaunchKernelGGL(set_hyper_kernel, dim3(1), dim3(1), 0, stream, c->d_state, tau, lam);
+    GMRF_HIP(hipGetLastError());
+    return GMRF_OK;
+}
+
+int gmrf_posterior_stats(gmrf_chain *c, double *mean, double *var, int64_t *n_acc, uint32_t flags,
+                         hipStream_t stream)
+{
+    clear_error();
+    if (!c || !mean || !var || (flags != GMRF_PTR_HOST && flags != GMRF_PTR_DEVICE) ||
+        (flags == GMRF_PTR_DEVICE && n_acc))
+        return fail(GMRF_E_INVALID_ARG, "posterior_stats: bad arguments");
+    const int64_t n = c->g->h.n;
+    double *dm = flags == GMRF_PTR_DEVICE ? mean : c->d_stats;
+    double *dv = flags == GMRF_PTR_DEVICE ? var : c->d_stats + n;
+    const int blocks = (int)std::min<int64_t>((n + kThreads - 1) / kThreads, 4096);
+    hipLaunchKernelGGL(stats_kernel, dim3(blocks), dim3(kThreads), 0, stream, c->d_s1, c->d_s2,
+                       is_lattice(c->g) ? nullptr : c->g->d_orig, (long long)n, c->d_state, dm,
+                       dv);
+    GMRF_HIP(hipGetLastError());
+    if (flags == GMRF_PTR_DEVICE)
+        return GMRF_OK;
+    GMRF_HIP(hipMemcpyAsync(mean, dm, 8 * n, hipMemcpyDeviceToHost, stream));
+    GMRF_HIP(hipMemcpyAsync(var, dv, 8 * n, hipMemcpyDeviceToHost, stream));
+    DevState st;
+    int rc = read_state(c, &st, stream);
+    if (rc != GMRF_OK)
+        return rc;
+    if (n_acc)
+        *n_acc = st.n_acc;
+    return check_status(st);
+}
+
+int gmrf_get_state(gmrf_chain *c, double *x, double *tau, double *lam, uint64_t *sweep,
+                   hipStream_t stream)
+{
+    clear_error();
+    if (!c)
+        return fail(GMRF_E_INVALID_ARG, "get_state: NULL chain");
+    DevState st;
+    int rc = read_state(c, &st, stream);
+    if (rc != GMRF_OK)
+        return rc;
+    if (x) {
+        const int64_t n = c->g->h.n;
+        std::vector<char> buf(real_size(c->prec) * n);
+        GMRF_HIP(hipMemcpyAsync(buf.data(), current_x(c, st.sweep), buf.size(),
+                                hipMemcpyDeviceToHost, stream));
+        GMRF_HIP(hipStreamSynchronize(stream));
+        if (c->prec == GMRF_FP64)
+            from_layout<double>(c, buf, x);
+        else
+            from_layout<float>(c, buf, x);
+    }
+    if (tau) *tau = st.tau;
+    if (lam) *lam = st.lam;
+    if (sweep) *sweep = st.sweep;
+    return check_status(st);
+}
+
+int gmrf_set_state(gmrf_chain *c, const double *x, double tau, double lam, uint64_t sweep,
+                   hipStream_t stream)
+{
+    clear_error();
+    if (!c || !(tau > 0.0) || !(lam > 0.0) || !std::isfinite(tau) || !std::isfinite(lam) ||
+        sweep > 0xFFFFFFFFull)
+        return fail(GMRF_E_INVALID_ARG, "set_state: NULL chain, bad tau / lam or sweep >= 2^32");
+    if (x && !finite_array(x, c->g->h.n))
+        return fail(GMRF_E_INVALID_ARG, "set_state: x must be finite");
+    DevState st;
+    int rc = read_state(c, &st, stream);
+    if (rc != GMRF_OK)
+        return rc;
+    if (x) {
+        rc = upload_real(c, current_x(c, sweep), x, stream);
+        if (rc != GMRF_OK)
+            return rc;
+    } else if (is_lattice(c->g) && ((st.sweep ^ sweep) & 1u)) {
+        // keep x: move it to the buffer the new sweep parity reads
+        const size_t bytes = real_size(c->prec) * (size_t)c->g->h.n;
+        GMRF_HIP(hipMemcpyAsync(current_x(c, sweep), current_x(c, st.sweep), bytes,
+                                hipMemcpyDeviceToDevice, stream));
+    }
+    st.tau = tau;
+    st.lam = lam;
+    st.sweep = sweep;
+    st.ticket = 0;
+    GMRF_HIP(hipMemcpyAsync(c->d_state, &st, sizeof st, hipMemcpyHostToDevice, stream));
+    GMRF_HIP(hipStreamSynchronize(stream));
+    c->host_sweeps = sweep;
+    return GMRF_OK;
+}
+
+int gmrf_get_accumulators(gmrf_chain *c, double *s1, double *s2, int64_t *n_acc,
+                          hipStream_t stream)
+{
+    clear_error();
+    if (!c || !s1 || !s2)
+        return fail(GMRF_E_INVALID_ARG, "get_accumulators: bad arguments");
+    int rc = download_doubles_layout(c, c->d_s1, s1, stream);
+    if (rc == GMRF_OK)
+        rc = download_doubles_layout(c, c->d_s2, s2, stream);
+    if (rc != GMRF_OK)
+        return rc;
+    DevState st;
+    rc = read_state(c, &st, stream);
+    if (rc != GMRF_OK)
+        return rc;
+    if (n_acc)
+        *n_acc = st.n_acc;
+    return GMRF_OK;
+}
+
+int gmrf_set_accumulators(gmrf_chain *c, const double *s1, const double *s2, int64_t n_acc,
+                          hipStream_t stream)
+{
+    clear_error();
+    if (!c || !s1 || !s2 || n_acc < 0)
+        return fail(GMRF_E_INVALID_ARG, "set_accumulators: bad arguments");
+    int rc = upload_doubles_layout(c, c->d_s1, s1, stream);
+    if (rc == GMRF_OK)
+        rc = upload_doubles_layout(c, c->d_s2, s2, stream);
+    if (rc != GMRF_OK)
+        return rc;
+    DevState st;
+    rc = read_state(c, &st, stream);
+    if (rc != GMRF_OK)
+        return rc;
+    st.n_acc = n_acc;
+    GMRF_HIP(hipMemcpyAsync(c->d_state, &st, sizeof st, hipMemcpyHostToDevice, stream));
+    GMRF_HIP(hipStreamSynchronize(stream));
+    return GMRF_OK;
+}
+
+int gmrf_last_reductions(gmrf_chain *c, double *q, double *sse, hipStream_t stream)
+{
+    clear_error();
+    if (!c)
+        return fail(GMRF_E_INVALID_ARG, "last_reductions: NULL chain");
+    DevState st;
+    int rc = read_state(c, &st, stream);
+    if (rc != GMRF_OK)
+        return rc;
+    if (q) *q = st.q;
+    if (sse) *sse = st.sse;
+    return GMRF_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,121 @@
+// rng.hpp -- device random numbers of the sampler.
+//
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC'11): a counter-based generator, so every draw is a pure
+// function of (key, counter) and needs no state in memory.  Key = the chain's
+// 64-bit seed; counter = (site or attempt, sweep, instance, tag).
+//
+// Normals: Box & Muller (1958), cosine branch.  Gamma: Marsaglia & Tsang
+// (2000), "A simple method for generating gamma variables", without the
+// squeeze test (the squeeze accepts a subset of the full test, so leaving it
+// out changes no decision).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gmrf {
+
+struct Words4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+// Ten Philox rounds.  Each round multiplies two counter words by the Philox
+// multipliers, mixes the high halves with the other two words and the key,
+// and advances the key by the Weyl increments.
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                               uint32_t c3, uint32_t k0, uint32_t k1)
+{
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kIncA = 0x9E3779B9u, kIncB = 0xBB67AE85u;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t pa = (uint64_t)kMulA * c0;
+        const uint64_t pb = (uint64_t)kMulB * c2;
+        const uint32_t a_hi = (uint32_t)(pa >> 32), a_lo = (uint32_t)pa;
+        const uint32_t b_hi = (uint32_t)(pb >> 32), b_lo = (uint32_t)pb;
+        c0 = b_hi ^ c1 ^ k0;
+        c1 = b_lo;
+        c2 = a_hi ^ c3 ^ k1;
+        c3 = a_lo;
+        k0 += kIncA;
+        k1 += kIncB;
+    }
+    return Words4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ Words4 draw_words(uint64_t seed, uint32_t c0, uint32_t c1,
+                                             uint32_t c2, uint32_t c3)
+{
+    return philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// (0,1) uniform from the top 52 bits of a word pair: (m + 1/2) 2^-52, exact
+// in FP64, never 0 or 1.
+__device__ __forceinline__ double open_uniform_f64(uint32_t hi, uint32_t lo)
+{
+    const uint64_t m = ((uint64_t)hi << 20) | (uint64_t)(lo >> 12);
+    return ((double)m + 0.5) * 0x1p-52;
+}
+
+constexpr double kTwoPi = 6.283185307179586;
+
+// FP64 standard normal of one Philox block.
+__device__ __forceinline__ double normal_f64(const Words4 &w)
+{
+    const double u1 = open_uniform_f64(w.w0, w.w1);
+    const double u2 = open_uniform_f64(w.w2, w.w3);
+    return sqrt(-2.0 * log(u1)) * cos(kTwoPi * u2);
+}
+
+// FP32 standard normal of the same block: the same two uniforms carried to
+// FP32 precision (u1 keeps its relative precision down to 2^-56 so the tail
+// tracks the FP64 draw), then Box-Muller in FP32.
+__device__ __forceinline__ float normal_f32(const Words4 &w)
+{
+    const float u1 = fmaf((float)w.w0, 0x1p-32f, fmaf((float)(w.w1 >> 8), 0x1p-56f, 0x1p-57f));
+    const float u2 = (float)w.w2 * 0x1p-32f;
+    return sqrtf(-2.0f * __logf(u1)) * cospif(2.0f * u2);
+}
+
+template <typename Real> __device__ __forceinline__ Real site_normal(const Words4 &w);
+template <> __device__ __forceinline__ double site_normal<double>(const Words4 &w)
+{
+    return normal_f64(w);
+}
+template <> __device__ __forceinline__ float site_normal<float>(const Words4 &w)
+{
+    return normal_f32(w);
+}
+
+constexpr int kGammaMaxAttempts = 64;
+
+// Gamma(shape >= 1, rate) for the hyperparameter draw after sweep `sweep`.
+// Attempt k takes its normal from counter (2k, sweep, instance, tag) and its
+// uniform from counter (2k + 1, ...).  Returns false when every attempt was
+// rejected (the caller flags a numeric error).
+__device__ inline bool gamma_draw(double shape, double rate, uint64_t seed, uint32_t sweep,
+                                  uint32_t instance, uint32_t tag, double *out)
+{
+    const double d = shape - 1.0 / 3.0;
+    const double c = 1.0 / sqrt(9.0 * d);
+    for (int k = 0; k < kGammaMaxAttempts; ++k) {
+        const double z = normal_f64(draw_words(seed, (uint32_t)(2 * k), sweep, instance, tag));
+        const double cz = c * z;
+        if (cz <= -1.0)
+            continue;
+        const double L = 3.0 * log1p(cz);        // log of v = (1 + c z)^3
+        const double v = exp(L);
+        const Words4 wu = draw_words(seed, (uint32_t)(2 * k + 1), sweep, instance, tag);
+        const double u = open_uniform_f64(wu.w0, wu.w1);
+        // accept iff log u < z^2/2 + d - d v + d log v, with 1 - v + log v
+        // evaluated as L - expm1(L) to avoid cancellation at large d
+        if (log(u) < 0.5 * z * z + d * (L - expm1(L))) {
+            *out = d * v / rate;
+            return true;
+        }
+    }
+    return false;
+}
+
+} // namespace gmrf

@@ -1,0 +1,284 @@
+"""GPU parity: the HIP sampler (through the C ABI) against the CPU oracle.
+
+FP64 results must match the oracle within 1e-12 relative (max-norm over the
+field, and per scalar for tau, lam, q, sse); FP32 results are compared with
+the FP64 oracle at the stated accuracy (posterior-mean max abs error <= 1e-4
+after 1000 sweeps).  Inputs are seeded and synthetic (see inputs.py).
+"""
+import numpy as np
+import pytest
+
+from paper_1702_05518_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+RTOL64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1702_05518_amd import gmrf
+
+    gmrf.lib()
+    return gmrf
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def lattice_case(rows, cols, st, noise=0.1, data_seed=1):
+    return inputs.lattice_workload(rows, cols, st, noise_sd=noise, data_seed=data_seed)
+
+
+def csr_case(n, data_seed=3, rho=0.95):
+    from paper_1702_05518_amd import gmrf
+
+    wl = inputs.delaunay_workload(n, data_seed=data_seed, rho=rho)
+    wl["color"], wl["k"] = gmrf.greedy_coloring(wl["row_ptr"], wl["col"])
+    return wl
+
+
+def gpu_graph(G, wl, force_csr=False):
+    if wl["kind"] == "lattice" and not force_csr:
+        return G.Graph(lattice=(wl["rows"], wl["cols"], wl["stencil"]), rho=wl["rho"])
+    return G.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=wl["color"],
+                   num_colors=wl["k"], rho=wl["rho"])
+
+
+def pair(G, orc, wl, precision=None, seed=1, instance=0, burn_in=0, x0=None, force_csr=False,
+         **prior):
+    prec = G.FP64 if precision is None else precision
+    g = gpu_graph(G, wl, force_csr)
+    ch = G.Chain(g, wl["y"], precision=prec, seed=seed, instance=instance, burn_in=burn_in,
+                 x0=x0, **prior)
+    oc = orc.Chain(wl["row_ptr"], wl["col"], wl["color"], wl["y"], rho=wl["rho"], seed=seed,
+                   instance=instance, burn_in=burn_in, x0=x0, **prior)
+    return g, ch, oc
+
+
+LATTICES = [(64, 64, 4), (64, 64, 8), (150, 133, 4), (150, 133, 8), (1, 1, 8), (1, 77, 4),
+            (77, 1, 8), (2, 3, 8), (129, 65, 8)]
+
+
+@pytest.mark.parametrize("rows,cols,st", LATTICES)
+def test_lattice_one_sweep_from_injected_state(G, orc, rows, cols, st):
+    wl = lattice_case(rows, cols, st)
+    n = rows * cols
+    x0 = np.random.default_rng(n).normal(size=n) * 0.3 + 0.5
+    g, ch, oc = pair(G, orc, wl, seed=7, instance=2)
+    ch.set_state(x0, 1.7, 60.0, 5)
+    oc.set_state(x0, 1.7, 60.0, 5)
+    ch.sweep(1, hyper=True)
+    oc.sweeps(1, hyper=True)
+    x, tau, lam, sw = ch.get_state()
+    q, sse = ch.last_reductions()
+    assert sw == 6
+    assert rel(x, oc.x) <= RTOL64
+    assert rel(q, oc.q) <= RTOL64 and rel(sse, oc.sse) <= RTOL64
+    assert rel(tau, oc.tau) <= RTOL64 and rel(lam, oc.lam) <= RTOL64
+
+
+@pytest.mark.parametrize("rho", [1.0, 0.95])
+def test_csr_one_sweep_from_injected_state(G, orc, rho):
+    wl = csr_case(3000, data_seed=5, rho=rho)
+    n = wl["n"]
+    x0 = np.random.default_rng(1).normal(size=n)
+    g, ch, oc = pair(G, orc, wl, seed=11, instance=4)
+    ch.set_state(x0, 2.0, 25.0, 17)
+    oc.set_state(x0, 2.0, 25.0, 17)
+    ch.sweep(1)
+    oc.sweeps(1)
+    x, tau, lam, sw = ch.get_state()
+    q, sse = ch.last_reductions()
+    assert rel(x, oc.x) <= RTOL64
+    assert rel(q, oc.q) <= RTOL64 and rel(sse, oc.sse) <= RTOL64
+    assert rel(tau, oc.tau) <= RTOL64 and rel(lam, oc.lam) <= RTOL64
+
+
+def test_lattice_trajectory_64x64_fp64(G, orc):
+    """64 x 64, 4 neighbours, checkerboard, FP64, 1000 sweeps with hyper draws:
+    tau and lam after every sweep, the field every 100 sweeps, and the
+    posterior mean / variance at the end."""
+    wl = lattice_case(64, 64, 4)
+    g, ch, oc = pair(G, orc, wl, seed=1)
+    worst = 0.0
+    for block in range(10):
+        for _ in range(100):
+            ch.sweep(1)
+            oc.sweeps(1)
+            _, tau, lam, _ = ch.get_state()
+            worst = max(worst, rel(tau, oc.tau), rel(lam, oc.lam))
+        x, tau, lam, sw = ch.get_state()
+        assert sw == 100 * (block + 1)
+        worst = max(worst, rel(x, oc.x))
+    assert worst <= RTOL64, worst
+    mean, var, nacc = ch.posterior_stats()
+    om, ov = oc.stats()
+    assert nacc == 1000
+    assert rel(mean, om) <= RTOL64
+    assert np.max(np.abs(var - ov)) <= 1e-9 * np.max(np.abs(ov))
+
+
+def test_csr_trajectory_delaunay_fp64(G, orc):
+    wl = csr_case(15000, data_seed=3)
+    g, ch, oc = pair(G, orc, wl, seed=3, burn_in=10)
+    ch.sweep(50)
+    oc.sweeps(50)
+    x, tau, lam, sw = ch.get_state()
+    assert sw == 50
+    assert rel(x, oc.x) <= RTOL64
+    assert rel(tau, oc.tau) <= RTOL64 and rel(lam, oc.lam) <= RTOL64
+    mean, var, nacc = ch.posterior_stats()
+    om, ov = oc.stats()
+    assert nacc == 40
+    assert rel(mean, om) <= RTOL64
+    assert np.max(np.abs(var - ov)) <= 1e-9 * np.max(np.abs(ov))
+
+
+@pytest.mark.parametrize("st", [4, 8])
+def test_lattice_path_equals_csr_path(G, orc, st):
+    wl = lattice_case(97, 130, st)
+    _, a, _ = pair(G, orc, wl, seed=5)
+    gc = gpu_graph(G, wl, force_csr=True)
+    b = G.Chain(gc, wl["y"], precision=G.FP64, seed=5)
+    a.sweep(20)
+    b.sweep(20)
+    xa, ta, la, _ = a.get_state()
+    xb, tb, lb, _ = b.get_state()
+    assert rel(xa, xb) <= 1e-13 and rel(ta, tb) <= 1e-13 and rel(la, lb) <= 1e-13
+
+
+def test_fp32_lattice_posterior_mean_against_fp64_oracle(G, orc):
+    wl = lattice_case(64, 64, 8)
+    g, ch, oc = pair(G, orc, wl, precision=G.FP32_ACC64, seed=2)
+    ch.sweep(1000)
+    oc.sweeps(1000)
+    mean, var, nacc = ch.posterior_stats()
+    om, ov = oc.stats()
+    _, tau, lam, _ = ch.get_state()
+    assert nacc == 1000
+    assert np.max(np.abs(mean - om)) <= 1e-4
+    assert np.max(np.abs(var - ov)) <= 1e-4 * max(1.0, np.max(ov))
+    assert rel(tau, oc.tau) <= 1e-3 and rel(lam, oc.lam) <= 1e-3
+
+
+def test_fp32_csr_posterior_mean_against_fp64_oracle(G, orc):
+    wl = csr_case(15000, data_seed=3)
+    g, ch, oc = pair(G, orc, wl, precision=G.FP32_ACC64, seed=4)
+    ch.sweep(300)
+    oc.sweeps(300)
+    mean, var, nacc = ch.posterior_stats()
+    om, ov = oc.stats()
+    assert np.max(np.abs(mean - om)) <= 1e-4
+
+
+def test_run_to_run_bitwise_and_capture(G, orc):
+    wl = lattice_case(200, 190, 8)
+    g = gpu_graph(G, wl)
+    runs = []
+    for capture in (False, False, True):
+        ch = G.Chain(g, wl["y"], precision=G.FP32_ACC64, seed=9)
+        if capture:
+            for _ in range(3):
+                ch.sweep(10, capture=True)
+        else:
+            ch.sweep(30)
+        runs.append((ch.get_state(), ch.posterior_stats()))
+    for other in runs[1:]:
+        assert np.array_equal(runs[0][0][0], other[0][0])
+        assert runs[0][0][1:] == other[0][1:]
+        assert np.array_equal(runs[0][1][0], other[1][0])
+
+
+def test_hyper_update_equals_fused_draw(G, orc):
+    wl = csr_case(2000, data_seed=8)
+    g = gpu_graph(G, wl)
+    a = G.Chain(g, wl["y"], seed=3)
+    b = G.Chain(g, wl["y"], seed=3)
+    a.sweep(5)
+    for _ in range(5):
+        b.sweep(1, hyper=False)
+        b.hyper_update()
+    sa, sb = a.get_state(), b.get_state()
+    assert np.array_equal(sa[0], sb[0]) and sa[1:] == sb[1:]
+
+
+def test_fixed_hyper_and_set_hyper(G, orc):
+    wl = lattice_case(40, 50, 8)
+    g, ch, oc = pair(G, orc, wl, seed=6)
+    ch.set_hyper(3.0, 80.0)
+    oc.set_state(oc.x, 3.0, 80.0, 0)
+    ch.sweep(7, hyper=False)
+    oc.sweeps(7, hyper=False)
+    x, tau, lam, sw = ch.get_state()
+    assert tau == 3.0 and lam == 80.0 and sw == 7
+    assert rel(x, oc.x) <= RTOL64
+
+
+def test_checkpoint_resume_bitwise(G, orc):
+    wl = csr_case(2500, data_seed=9)
+    g = gpu_graph(G, wl)
+    full = G.Chain(g, wl["y"], seed=21, instance=3)
+    full.sweep(12)
+    part = G.Chain(g, wl["y"], seed=21, instance=3)
+    part.sweep(5)
+    x, tau, lam, sw = part.get_state()
+    s1, s2, nacc = part.get_accumulators()
+    res = G.Chain(g, wl["y"], seed=21, instance=3)
+    res.set_state(x, tau, lam, sw)
+    res.set_accumulators(s1, s2, nacc)
+    res.sweep(7)
+    a, b = full.get_state(), res.get_state()
+    assert np.array_equal(a[0], b[0]) and a[1:] == b[1:]
+    assert np.array_equal(full.posterior_stats()[0], res.posterior_stats()[0])
+
+
+def test_device_pointer_stats(G, orc):
+    import torch
+
+    wl = lattice_case(33, 47, 4)
+    g, ch, oc = pair(G, orc, wl, seed=2)
+    ch.sweep(9)
+    m = torch.empty(wl["n"], dtype=torch.float64, device="cuda")
+    v = torch.empty_like(m)
+    ch.posterior_stats_device(m, v)
+    mean, var, _ = ch.posterior_stats()
+    assert np.array_equal(m.cpu().numpy(), mean) and np.array_equal(v.cpu().numpy(), var)
+
+
+def test_isolated_sites_and_empty_color(G, orc):
+    # 3 components (one isolated site) and a coloring that leaves color 2 empty
+    rp, cl = inputs.edges_to_csr(6, [0, 1, 3], [1, 2, 4])
+    color = np.array([0, 1, 0, 0, 1, 3], dtype=np.int32)
+    y = np.array([0.1, 0.5, -0.2, 1.0, 0.3, -0.7])
+    g = G.Graph(row_ptr=rp, col_idx=cl, color=color, num_colors=4)
+    assert g.components == 3
+    ch = G.Chain(g, y, seed=4)
+    oc = orc.Chain(rp, cl, color, y, seed=4)
+    ch.sweep(25)
+    oc.sweeps(25)
+    x, tau, lam, _ = ch.get_state()
+    assert rel(x, oc.x) <= RTOL64 and rel(tau, oc.tau) <= RTOL64 and rel(lam, oc.lam) <= RTOL64
+
+
+def test_chain_argument_errors(G):
+    wl = lattice_case(8, 8, 4)
+    g = gpu_graph(G, wl)
+    with pytest.raises(G.GmrfError) as e:
+        G.Chain(g, np.full(64, np.nan))
+    assert e.value.status == G.E_INVALID_ARG
+    with pytest.raises(G.GmrfError):
+        G.Chain(g, wl["y"], tau0=-1.0)
+    with pytest.raises(G.GmrfError):
+        G.Chain(g, wl["y"], b_tau=0.0)
+    ch = G.Chain(g, wl["y"])
+    with pytest.raises(G.GmrfError):
+        ch.hyper_update()          # no completed sweep
+    with pytest.raises(G.GmrfError):
+        ch.set_hyper(0.0, 1.0)
