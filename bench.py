@@ -89,7 +89,7 @@ def solve_latencies(torch, chain, sweeps, reps):
     return out
 
 
-def cpu_baseline(wl, seconds_budget=20.0):
+def cpu_baseline(wl, seconds_budget=15.0):
     """The oracle (C, FP64) on the same workload, a bounded number of sweeps."""
     import oracle
 
@@ -99,7 +99,7 @@ def cpu_baseline(wl, seconds_budget=20.0):
     t0 = time.perf_counter()
     ch.sweeps(1, nthreads=threads)
     one = time.perf_counter() - t0
-    reps = max(1, min(50, int(seconds_budget / max(one, 1e-3))))
+    reps = max(1, min(2000, int(seconds_budget / max(one, 1e-3))))
     t0 = time.perf_counter()
     ch.sweeps(reps, nthreads=threads)
     dt = time.perf_counter() - t0
@@ -120,6 +120,25 @@ def cpu_baseline(wl, seconds_budget=20.0):
             "seconds": dt}
 
 
+def probe(torch, gmrf, inputs, steps):
+    """A plain device copy of 512 MiB (its counters give the scale factor of
+    FETCH_SIZE / WRITE_SIZE), then warm-up and `steps` FP32 sweeps, one launch
+    each, of the benchmark workload."""
+    src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    wl = inputs.lattice_workload(ROWS, COLS, STENCIL, noise_sd=0.1, data_seed=1, with_csr=False)
+    graph = gmrf.Graph(lattice=(ROWS, COLS, STENCIL))
+    chain = gmrf.Chain(graph, wl["y"], precision=gmrf.FP32_ACC64, seed=1)
+    chain.sweep(5, hyper=True)
+    for _ in range(steps):
+        chain.sweep(1, hyper=True)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "copy 512 MiB + sweeps", "sweeps": steps + 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +147,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--reps", type=int, default=10, help="solves for p50/p99 latency")
+    ap.add_argument("--probe", action="store_true",
+                    help="counter probe for rocprofv3 --pmc: a 512 MiB device copy (the "
+                         "scale reference for FETCH_SIZE / WRITE_SIZE), then --steps sweeps")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on exactly one GPU (independent chains shard across "
@@ -143,6 +165,9 @@ def main():
         sys.exit(1)
     gmrf.lib()
     n = ROWS * COLS
+    if args.probe:
+        probe(torch, gmrf, inputs, args.steps)
+        return
     log(f"[bench] building workload {ROWS}x{COLS} stencil {STENCIL}")
     wl = inputs.lattice_workload(ROWS, COLS, STENCIL, noise_sd=0.1, data_seed=1,
                                  with_csr=not args.no_cpu)

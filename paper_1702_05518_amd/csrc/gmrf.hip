@@ -19,9 +19,11 @@
 //   * Every sweep kernel fuses the reductions q = x'(D - rho W)x (each edge
 //     counted once, by its higher-colored endpoint, after both ends are final)
 //     and sse = ||y - x||^2 in FP64, and the posterior accumulators.  Blocks
-//     leave FP64 partials; the last block of the sweep (atomic ticket) sums
-//     them in fixed slot order and draws tau and lam on the device, so a sweep
-//     has one global dependency and no host round trip.
+//     leave FP64 partials; a one-block finish kernel sums them in fixed slot
+//     order and draws tau and lam on the device, so a sweep has no host round
+//     trip.  (The Gamma draw lives in its own kernel because its FP64
+//     transcendentals would otherwise set the register budget, and so the
+//     occupancy, of the sweep kernel.)
 //   * The sweep index t lives in device memory, so a captured HIP graph of
 //     sweeps can be replayed.
 #include <hip/hip_runtime.h>
@@ -50,15 +52,15 @@ struct DevState {
     double q, sse;              // reductions of the last completed sweep
     unsigned long long sweep;   // completed sweeps
     long long n_acc;            // accumulated sweeps
-    unsigned int ticket;        // blocks of the running sweep that finished
     unsigned int status;        // bit 0: Gamma draw failed / non-finite
+    unsigned int pad;
 };
 
 constexpr unsigned kStatusGamma = 1u;
 
 struct SweepArgs {
     DevState *st;
-    double *partials;           // two doubles per block slot
+    double *partials;           // two doubles (q, sse) per block slot
     double *s1, *s2;            // posterior accumulators (layout of x)
     double shape_tau, b_tau, shape_lam, b_lam;
     double rho;
@@ -69,8 +71,7 @@ struct SweepArgs {
     int total_slots;            // blocks per sweep (all color passes)
 };
 
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
+constexpr int kThreads = 256;   // CSR passes, finish and stats kernels
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -80,24 +81,46 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Block sum of two values in a fixed tree; the result is valid in thread 0.
-__device__ __forceinline__ void block_sum2(double &a, double &b, double *red)
+// Barrier that orders LDS only: global loads issued before it stay in flight
+// (a plain __syncthreads() would also wait for every outstanding global load).
+__device__ __forceinline__ void lds_barrier()
 {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Block sum of two values in a fixed tree; the result is valid in thread 0.
+template <int NT> __device__ __forceinline__ void block_sum2(double &a, double &b, double *red)
+{
+    constexpr int W = NT / 64;
     a = wave_sum(a);
     b = wave_sum(b);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) {
         red[wid] = a;
-        red[kWaves + wid] = b;
+        red[W + wid] = b;
     }
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0) {
         a = red[0];
-        b = red[kWaves];
-        for (int w = 1; w < kWaves; ++w) {
+        b = red[W];
+        for (int w = 1; w < W; ++w) {
             a += red[w];
-            b += red[kWaves + w];
+            b += red[W + w];
         }
+    }
+}
+
+// A sweep block's FP64 partials of q and sse, summed later in slot order.
+template <int NT>
+__device__ __forceinline__ void write_partials(const SweepArgs &a, double q, double sse, int slot)
+{
+    __shared__ double red[2 * (NT / 64)];
+    block_sum2<NT>(q, sse, red);
+    if (threadIdx.x == 0) {
+        a.partials[2 * slot] = q;
+        a.partials[2 * slot + 1] = sse;
     }
 }
 
@@ -122,33 +145,19 @@ __device__ __forceinline__ void draw_hyper(const SweepArgs &a, unsigned t, doubl
     }
 }
 
-// End of a sweep block: publish the block's partials; the last block of the
-// sweep sums all partials in slot order, stores q / sse, draws tau / lam,
-// counts the accumulated sweep and advances the sweep index.
-__device__ void finish_block(const SweepArgs &a, double q, double sse, int slot, unsigned t)
+// End of a sweep (one block): sum the partials of every block of the sweep
+// in slot order, store q / sse, draw tau / lam, count the accumulated sweep
+// and advance the sweep index.
+__global__ __launch_bounds__(kThreads) void finish_sweep_kernel(SweepArgs a)
 {
-    __shared__ double red[2 * kWaves];
-    __shared__ int is_last;
-    block_sum2(q, sse, red);
-    if (threadIdx.x == 0) {
-        a.partials[2 * slot] = q;
-        a.partials[2 * slot + 1] = sse;
-        __threadfence();
-        const unsigned prev = atomicAdd(&a.st->ticket, 1u);
-        is_last = (prev == (unsigned)a.total_slots - 1u);
-    }
-    __syncthreads();
-    if (!is_last)
-        return;
-    __threadfence();
+    __shared__ double red[2 * (kThreads / 64)];
+    const unsigned t = (unsigned)a.st->sweep;
     double tq = 0.0, ts = 0.0;
-    const volatile double *p = a.partials;
     for (int i = threadIdx.x; i < a.total_slots; i += kThreads) {
-        tq += p[2 * i];
-        ts += p[2 * i + 1];
+        tq += a.partials[2 * i];
+        ts += a.partials[2 * i + 1];
     }
-    __syncthreads();
-    block_sum2(tq, ts, red);
+    block_sum2<kThreads>(tq, ts, red);
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
         tq = __shfl(tq, 0, 64);
@@ -161,9 +170,37 @@ __device__ void finish_block(const SweepArgs &a, double q, double sse, int slot,
             if ((long long)t >= a.burn_in)
                 a.st->n_acc += 1;
             a.st->sweep = (unsigned long long)t + 1ull;
-            a.st->ticket = 0u;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// the site update shared by every sweep kernel
+// ---------------------------------------------------------------------------
+// Conditional precision Qii = tau D_ii + lam (Sec. 3.1 local characteristics
+// in precision form) and its scales 1/Qii and Qii^-1/2.  Every kernel computes
+// them with this one instruction sequence, so a site recomputed in a tile
+// halo is bitwise the value its owner computes.
+template <typename Real>
+__device__ __forceinline__ void site_scales(Real tau, Real lam, int deg, Real &inv_q, Real &isd)
+{
+    const Real Q = fma(tau, (Real)deg, lam);
+    if constexpr (sizeof(Real) == 8) {
+        inv_q = 1.0 / Q;
+        isd = 1.0 / sqrt(Q);
+    } else {
+        inv_q = 1.0f / Q;
+        isd = __builtin_amdgcn_rsqf(Q);
+    }
+}
+
+// x_i = m_i + z / sqrt(Qii), m_i = (lam y_i + tau rho s_i) / Qii.
+template <typename Real>
+__device__ __forceinline__ Real site_draw(Real yv, Real s, Real z, Real lam, Real tau_rho,
+                                          Real inv_q, Real isd)
+{
+    const Real m = fma(tau_rho, s, lam * yv) * inv_q;
+    return fma(z, isd, m);
 }
 
 // ---------------------------------------------------------------------------
@@ -193,25 +230,38 @@ template <int ST, int J> __host__ __device__ constexpr bool lower_nb(int dr, int
 
 template <typename Real> struct SiteCtx {
     Real tau, lam, tau_rho;
+    Real inv_q_full, isd_full;  // 1/Qii and Qii^-1/2 of a site with all k neighbours
     double one_minus_rho, rho;
     unsigned t;
     unsigned long long seed;
     unsigned instance;
 };
 
+// Tile geometry of the fused lattice kernel: TH x TW interior sites, NT
+// threads, halo of depth k (= number of colors); the accumulator
+// read-modify-write of the interior is issued CH sites per thread at a time.
+template <int ST_, int TH_, int TW_, int NT_, int CH_> struct LatCfg {
+    static constexpr int ST = ST_, TH = TH_, TW = TW_, NT = NT_, CH = CH_;
+    static constexpr int K = ST == 4 ? 2 : 4;
+    static constexpr int H = K;
+    static constexpr int LH = TH + 2 * H, LW = TW + 2 * H;
+    static_assert(TH % 2 == 0 && TW % 2 == 0, "tile sides must be even");
+    static_assert(NT % 64 == 0, "whole wavefronts");
+};
+
 // One site of Algorithm 1 on the LDS tile: neighbour sum in ascending
 // original-id order, conditional mean and precision, the draw; for interior
 // sites also the q / sse terms.
-template <typename Real, int ST, int TH, int TW, int J>
-__device__ __forceinline__ void lattice_site(Real *xs, const Real *__restrict__ y, int r, int c,
-                                             int r0, int c0, int rows, int cols,
-                                             const SiteCtx<Real> &sc, double &q, double &sse)
+template <typename Real, typename Cfg, int J, bool INTERIOR>
+__device__ __forceinline__ void lattice_site(Real *xs, Real yv, int r, int c, int r0, int c0,
+                                             int rows, int cols, const SiteCtx<Real> &sc,
+                                             double &q, double &sse)
 {
-    constexpr int K = ST == 4 ? 2 : 4;
-    constexpr int H = K;
-    constexpr int LW = TW + 2 * H;
+    constexpr int ST = Cfg::ST, H = Cfg::H, LW = Cfg::LW;
     Real *p = xs + (r - r0 + H) * LW + (c - c0 + H);
-    const bool up = r > 0, dn = r + 1 < rows, lf = c > 0, rt = c + 1 < cols;
+    // on an interior tile every computed site has all its neighbours
+    const bool up = INTERIOR || r > 0, dn = INTERIOR || r + 1 < rows;
+    const bool lf = INTERIOR || c > 0, rt = INTERIOR || c + 1 < cols;
     Real s = (Real)0;
     int deg = 0;
     if (ST == 8 && up && lf) { s += p[-LW - 1]; ++deg; }
@@ -224,19 +274,19 @@ __device__ __forceinline__ void lattice_site(Real *xs, const Real *__restrict__ 
     if (ST == 8 && dn && rt) { s += p[LW + 1]; ++deg; }
 
     const unsigned site = (unsigned)r * (unsigned)cols + (unsigned)c;
-    const Real yv = y[(size_t)r * cols + c];
     const Words4 w = draw_words(sc.seed, site, sc.t, sc.instance, 0u);
     const Real z = site_normal<Real>(w);
-    const Real Q = sc.tau * (Real)deg + sc.lam;
-    const Real m = (sc.lam * yv + sc.tau_rho * s) / Q;
-    Real xn;
-    if constexpr (sizeof(Real) == 8)
-        xn = m + z / sqrt(Q);
-    else
-        xn = m + z * rsqrtf(Q);
+    Real inv_q, isd;
+    if constexpr (INTERIOR) {
+        inv_q = sc.inv_q_full;
+        isd = sc.isd_full;
+    } else {
+        site_scales<Real>(sc.tau, sc.lam, deg, inv_q, isd);
+    }
+    const Real xn = site_draw<Real>(yv, s, z, sc.lam, sc.tau_rho, inv_q, isd);
     *p = xn;
 
-    if (r >= r0 && r < r0 + TH && c >= c0 && c < c0 + TW) {
+    if (r >= r0 && r < r0 + Cfg::TH && c >= c0 && c < c0 + Cfg::TW) {
         const double xd = (double)xn;
         double edge = 0.0;
 #define GMRF_EDGE(cond, dr, dc, off)                                                  \
@@ -259,41 +309,90 @@ __device__ __forceinline__ void lattice_site(Real *xs, const Real *__restrict__ 
     }
 }
 
-// Phase J: every color-J site of the tile grown by E = k-1-J rings.
-template <typename Real, int ST, int TH, int TW, int J>
-__device__ __forceinline__ void lattice_phase(Real *xs, const Real *__restrict__ y, int r0, int c0,
-                                              int rows, int cols, const SiteCtx<Real> &sc,
+// Quotient and remainder of idx by d (0 <= idx < 2^24, d >= 1) through an FP32
+// reciprocal with a one-step correction.
+__device__ __forceinline__ int div_small(int idx, int d, float rcp, int &rem)
+{
+    int qt = (int)((float)idx * rcp);
+    qt -= (qt * d > idx);
+    qt += ((qt + 1) * d <= idx);
+    rem = idx - qt * d;
+    return qt;
+}
+
+// Phase J: every color-J site of the tile grown by E = k-1-J rings.  The
+// iteration count per thread has a compile-time bound, so the y loads of all
+// of a thread's sites are issued before the first site is computed.
+template <typename Real, typename Cfg, int J, bool INTERIOR>
+__device__ __forceinline__ void lattice_phase(Real *xs, const Real *__restrict__ y, int r0,
+                                              int c0, int rows, int cols, const SiteCtx<Real> &sc,
                                               double &q, double &sse)
 {
-    constexpr int K = ST == 4 ? 2 : 4;
-    constexpr int E = K - 1 - J;
+    constexpr int E = Cfg::K - 1 - J;
+    constexpr int NT = Cfg::NT;
+    constexpr int MAXS = Cfg::ST == 8 ? (Cfg::TH / 2 + E) * (Cfg::TW / 2 + E)
+                                      : (Cfg::TH + 2 * E) * ((Cfg::TW + 2 * E + 1) / 2);
+    constexpr int NI = (MAXS + NT - 1) / NT;
     int ra = max(r0 - E, 0);
-    const int rb = min(r0 + TH + E, rows);
+    const int rb = min(r0 + Cfg::TH + E, rows);
     int ca = max(c0 - E, 0);
-    const int cb = min(c0 + TW + E, cols);
-    if constexpr (ST == 8) {
-        constexpr int PR = J >> 1, PC = J & 1;
-        ra += ((ra & 1) != PR);
-        ca += ((ca & 1) != PC);
-        const int nR = rb > ra ? (rb - ra + 1) >> 1 : 0;
-        const int nC = cb > ca ? (cb - ca + 1) >> 1 : 0;
-        const int total = nR * nC;
-        for (int idx = threadIdx.x; idx < total; idx += kThreads) {
-            const int R = idx / nC, C = idx - R * nC;
-            lattice_site<Real, ST, TH, TW, J>(xs, y, ra + 2 * R, ca + 2 * C, r0, c0, rows, cols,
-                                              sc, q, sse);
-        }
+    const int cb = min(c0 + Cfg::TW + E, cols);
+    int nR, nC;
+    if constexpr (Cfg::ST == 8) {
+        ra += ((ra & 1) != (J >> 1));
+        ca += ((ca & 1) != (J & 1));
+        nR = rb > ra ? (rb - ra + 1) >> 1 : 0;
+        nC = cb > ca ? (cb - ca + 1) >> 1 : 0;
     } else {
-        const int nR = rb > ra ? rb - ra : 0;
-        const int nC = cb > ca ? (cb - ca + 1) >> 1 : 0;
-        const int total = nR * nC;
-        for (int idx = threadIdx.x; idx < total; idx += kThreads) {
-            const int R = idx / nC, C = idx - R * nC;
-            const int r = ra + R;
-            const int c = ca + ((r + ca + J) & 1) + 2 * C;
-            if (c < cb)
-                lattice_site<Real, ST, TH, TW, J>(xs, y, r, c, r0, c0, rows, cols, sc, q, sse);
+        nR = rb > ra ? rb - ra : 0;
+        nC = cb > ca ? (cb - ca + 1) >> 1 : 0;
+    }
+    const int total = nR * nC;
+    const float rcp = 1.0f / (float)max(nC, 1);
+    int rr[NI], cc[NI];
+    Real yv[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int idx = (int)threadIdx.x + k * NT;
+        int C;
+        const int R = div_small(idx, max(nC, 1), rcp, C);
+        int r, c;
+        if constexpr (Cfg::ST == 8) {
+            r = ra + 2 * R;
+            c = ca + 2 * C;
+        } else {
+            r = ra + R;
+            c = ca + ((r + ca + J) & 1) + 2 * C;
         }
+        const bool ok = idx < total && c < cb;
+        rr[k] = ok ? r : -1;
+        cc[k] = c;
+        // clamped address: always inside the lattice, used only when ok
+        const int rc = min(max(r, 0), rows - 1), ccl = min(max(c, 0), cols - 1);
+        yv[k] = y[(size_t)rc * cols + ccl];
+    }
+#pragma unroll
+    for (int k = 0; k < NI; ++k)
+        if (rr[k] >= 0)
+            lattice_site<Real, Cfg, J, INTERIOR>(xs, yv[k], rr[k], cc[k], r0, c0, rows, cols, sc, q,
+                                                 sse);
+}
+
+// The k color phases of one tile, separated by LDS barriers.
+template <typename Real, typename Cfg, bool INTERIOR>
+__device__ __forceinline__ void lattice_phases(Real *xs, const Real *__restrict__ y, int r0,
+                                               int c0, int rows, int cols, const SiteCtx<Real> &sc,
+                                               double &q, double &sse)
+{
+    lattice_phase<Real, Cfg, 0, INTERIOR>(xs, y, r0, c0, rows, cols, sc, q, sse);
+    lds_barrier();
+    lattice_phase<Real, Cfg, 1, INTERIOR>(xs, y, r0, c0, rows, cols, sc, q, sse);
+    lds_barrier();
+    if constexpr (Cfg::K == 4) {
+        lattice_phase<Real, Cfg, 2, INTERIOR>(xs, y, r0, c0, rows, cols, sc, q, sse);
+        lds_barrier();
+        lattice_phase<Real, Cfg, 3, INTERIOR>(xs, y, r0, c0, rows, cols, sc, q, sse);
+        lds_barrier();
     }
 }
 
@@ -306,12 +405,14 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     return x * per + min(x, rem) + (b >> 3);
 }
 
-template <typename Real, int ST, int TH, int TW>
-__global__ __launch_bounds__(kThreads) void lattice_sweep_kernel(LatArgs<Real> la, SweepArgs a)
+template <typename Real, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void lattice_sweep_kernel(LatArgs<Real> la, SweepArgs a)
 {
-    constexpr int K = ST == 4 ? 2 : 4;
-    constexpr int H = K;
-    constexpr int LH = TH + 2 * H, LW = TW + 2 * H;
+    constexpr int H = Cfg::H, LH = Cfg::LH, LW = Cfg::LW, NT = Cfg::NT;
+    constexpr int TH = Cfg::TH, TW = Cfg::TW;
+    constexpr int NL = (LH * LW + NT - 1) / NT;        // tile loads per thread
+    constexpr int NPT = (TH * TW + NT - 1) / NT;       // interior sites per thread
+    constexpr int CH = Cfg::CH < NPT ? Cfg::CH : NPT;  // accumulator batch
     __shared__ Real xs[LH * LW];
 
     const unsigned t = (unsigned)a.st->sweep;
@@ -320,6 +421,7 @@ __global__ __launch_bounds__(kThreads) void lattice_sweep_kernel(LatArgs<Real> l
     sc.tau = (Real)tau;
     sc.lam = (Real)lam;
     sc.tau_rho = (Real)(tau * a.rho);
+    site_scales<Real>(sc.tau, sc.lam, Cfg::ST, sc.inv_q_full, sc.isd_full);
     sc.one_minus_rho = 1.0 - a.rho;
     sc.rho = a.rho;
     sc.t = t;
@@ -332,43 +434,72 @@ __global__ __launch_bounds__(kThreads) void lattice_sweep_kernel(LatArgs<Real> l
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int tr = tile / la.tiles_c, tc = tile - tr * la.tiles_c;
     const int r0 = tr * TH, c0 = tc * TW;
+    const bool acc = (long long)t >= a.burn_in;
 
-    for (int idx = threadIdx.x; idx < LH * LW; idx += kThreads) {
-        const int lr = idx / LW, lc = idx - lr * LW;
-        const int r = r0 - H + lr, c = c0 - H + lc;
-        if (r >= 0 && r < rows && c >= 0 && c < cols)
-            xs[idx] = src[(size_t)r * cols + c];
+    // Stage the tile and its halo: all loads of a thread are issued before
+    // the first LDS store.  Addresses are clamped into the lattice; cells
+    // outside the lattice are never read by the phases.
+    {
+        Real v[NL];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int idx = (int)threadIdx.x + k * NT;
+            const int lr = idx / LW, lc = idx - (idx / LW) * LW;
+            const int r = min(max(r0 - H + lr, 0), rows - 1);
+            const int c = min(max(c0 - H + lc, 0), cols - 1);
+            v[k] = src[(size_t)r * cols + c];
+        }
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int idx = (int)threadIdx.x + k * NT;
+            if (k < NL - 1 || idx < LH * LW)
+                xs[idx] = v[k];
+        }
     }
-    __syncthreads();
+    lds_barrier();
 
     double q = 0.0, sse = 0.0;
-    lattice_phase<Real, ST, TH, TW, 0>(xs, la.y, r0, c0, rows, cols, sc, q, sse);
-    __syncthreads();
-    lattice_phase<Real, ST, TH, TW, 1>(xs, la.y, r0, c0, rows, cols, sc, q, sse);
-    __syncthreads();
-    if constexpr (K == 4) {
-        lattice_phase<Real, ST, TH, TW, 2>(xs, la.y, r0, c0, rows, cols, sc, q, sse);
-        __syncthreads();
-        lattice_phase<Real, ST, TH, TW, 3>(xs, la.y, r0, c0, rows, cols, sc, q, sse);
-        __syncthreads();
-    }
+    const bool interior = r0 >= H && c0 >= H && r0 + TH + H <= rows && c0 + TW + H <= cols;
+    if (interior)
+        lattice_phases<Real, Cfg, true>(xs, la.y, r0, c0, rows, cols, sc, q, sse);
+    else
+        lattice_phases<Real, Cfg, false>(xs, la.y, r0, c0, rows, cols, sc, q, sse);
 
-    const bool acc = (long long)t >= a.burn_in;
-    for (int idx = threadIdx.x; idx < TH * TW; idx += kThreads) {
-        const int ir = idx / TW, ic = idx - ir * TW;
-        const int r = r0 + ir, c = c0 + ic;
-        if (r < rows && c < cols) {
-            const Real v = xs[(ir + H) * LW + ic + H];
-            const size_t g = (size_t)r * cols + c;
-            dst[g] = v;
+    // Write the interior back and update the accumulators, CH sites per
+    // thread per batch so their loads are in flight together.
+#pragma unroll
+    for (int k0 = 0; k0 < NPT; k0 += CH) {
+        double o1[CH], o2[CH];
+        size_t g[CH];
+        bool ok[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int idx = (int)threadIdx.x + (k0 + j) * NT;
+            const int r = r0 + idx / TW, c = c0 + idx % TW;
+            ok[j] = (k0 + j < NPT) && idx < TH * TW && r < rows && c < cols;
+            g[j] = (size_t)min(r, rows - 1) * cols + min(c, cols - 1);
+            o1[j] = 0.0;
+            o2[j] = 0.0;
             if (acc) {
-                const double dv = (double)v;
-                a.s1[g] += dv;
-                a.s2[g] += dv * dv;
+                o1[j] = a.s1[g[j]];
+                o2[j] = a.s2[g[j]];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            if (ok[j]) {
+                const int idx = (int)threadIdx.x + (k0 + j) * NT;
+                const Real v = xs[(idx / TW + H) * LW + idx % TW + H];
+                dst[g[j]] = v;
+                if (acc) {
+                    const double dv = (double)v;
+                    a.s1[g[j]] = o1[j] + dv;
+                    a.s2[g[j]] = o2[j] + dv * dv;
+                }
             }
         }
     }
-    finish_block(a, q, sse, (int)blockIdx.x, t);
+    write_partials<NT>(a, q, sse, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -400,13 +531,9 @@ __global__ __launch_bounds__(kThreads) void csr_pass_kernel(CsrArgs<Real> ca, Sw
         const Real yv = ca.y[p];
         const Words4 w = draw_words(a.seed, (unsigned)ca.orig[p], t, a.instance, 0u);
         const Real z = site_normal<Real>(w);
-        const Real Q = tau * (Real)deg + lam;
-        const Real m = (lam * yv + tau_rho * s) / Q;
-        Real xn;
-        if constexpr (sizeof(Real) == 8)
-            xn = m + z / sqrt(Q);
-        else
-            xn = m + z * rsqrtf(Q);
+        Real inv_q, isd;
+        site_scales<Real>(tau, lam, deg, inv_q, isd);
+        const Real xn = site_draw<Real>(yv, s, z, lam, tau_rho, inv_q, isd);
         ca.x[p] = xn;
         const double xd = (double)xn;
         double edge = 0.0;
@@ -425,7 +552,7 @@ __global__ __launch_bounds__(kThreads) void csr_pass_kernel(CsrArgs<Real> ca, Sw
             a.s2[p] += xd * xd;
         }
     }
-    finish_block(a, q, sse, slot_base + (int)blockIdx.x, t);
+    write_partials<kThreads>(a, q, sse, slot_base + (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -490,7 +617,21 @@ struct gmrf_chain {
 
 namespace {
 
-constexpr int kLatTH = 64, kLatTW = 64;
+// Lattice tile configuration (tuned on MI355X; see the benchmark notes).
+#ifndef GMRF_LAT_TH
+#define GMRF_LAT_TH 64
+#endif
+#ifndef GMRF_LAT_TW
+#define GMRF_LAT_TW 64
+#endif
+#ifndef GMRF_LAT_NT
+#define GMRF_LAT_NT 512
+#endif
+#ifndef GMRF_LAT_CH
+#define GMRF_LAT_CH 4
+#endif
+constexpr int kLatTH = GMRF_LAT_TH, kLatTW = GMRF_LAT_TW;
+template <int ST> using LatticeCfg = LatCfg<ST, kLatTH, kLatTW, GMRF_LAT_NT, GMRF_LAT_CH>;
 
 #define GMRF_HIP(expr)                                                                    \
     do {                                                                                  \
@@ -586,8 +727,8 @@ template <typename Real, int ST> void launch_lattice(const gmrf_chain *c, const 
     la.rows = h.rows;
     la.cols = h.cols;
     la.tiles_c = (h.cols + kLatTW - 1) / kLatTW;
-    hipLaunchKernelGGL((lattice_sweep_kernel<Real, ST, kLatTH, kLatTW>), dim3(c->total_slots),
-                       dim3(kThreads), 0, s, la, a);
+    hipLaunchKernelGGL((lattice_sweep_kernel<Real, LatticeCfg<ST>>), dim3(c->total_slots),
+                       dim3(LatticeCfg<ST>::NT), 0, s, la, a);
 }
 
 template <typename Real> void launch_csr(const gmrf_chain *c, const SweepArgs &a, hipStream_t s)
@@ -622,6 +763,7 @@ void launch_one_sweep(const gmrf_chain *c, const SweepArgs &a, hipStream_t s)
     } else {
         f64 ? launch_csr<double>(c, a, s) : launch_csr<float>(c, a, s);
     }
+    hipLaunchKernelGGL(finish_sweep_kernel, dim3(1), dim3(kThreads), 0, s, a);
 }
 
 int read_state(gmrf_chain *c, DevState *out, hipStream_t s)
@@ -1039,7 +1181,6 @@ int gmrf_set_state(gmrf_chain *c, const double *x, double tau, double lam, uint6
     st.tau = tau;
     st.lam = lam;
     st.sweep = sweep;
-    st.ticket = 0;
     GMRF_HIP(hipMemcpyAsync(c->d_state, &st, sizeof st, hipMemcpyHostToDevice, stream));
     GMRF_HIP(hipStreamSynchronize(stream));
     c->host_sweeps = sweep;

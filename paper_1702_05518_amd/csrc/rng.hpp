@@ -70,12 +70,16 @@ __device__ __forceinline__ double normal_f64(const Words4 &w)
 
 // FP32 standard normal of the same block: the same two uniforms carried to
 // FP32 precision (u1 keeps its relative precision down to 2^-56 so the tail
-// tracks the FP64 draw), then Box-Muller in FP32.
+// tracks the FP64 draw), then Box-Muller on the hardware transcendental
+// units: log2, square root, and the cosine whose argument is in revolutions,
+// so cos(2 pi u2) is a single instruction.
 __device__ __forceinline__ float normal_f32(const Words4 &w)
 {
     const float u1 = fmaf((float)w.w0, 0x1p-32f, fmaf((float)(w.w1 >> 8), 0x1p-56f, 0x1p-57f));
     const float u2 = (float)w.w2 * 0x1p-32f;
-    return sqrtf(-2.0f * __logf(u1)) * cospif(2.0f * u2);
+    constexpr float kMinus2Ln2 = -1.38629436111989061883f;   // -2 ln 2
+    return __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(u1)) *
+           __builtin_amdgcn_cosf(u2);
 }
 
 template <typename Real> __device__ __forceinline__ Real site_normal(const Words4 &w);
