@@ -54,18 +54,11 @@ def timed_sweeps(torch, chain, steps, capture):
 
 
 def kernel_time(torch, chain, launches):
-    """Average duration of single sweep launches (one kernel each on the
-    lattice path), each bracketed by its own pair of events."""
-    s = torch.cuda.current_stream()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(launches)]
+    """Average duration in seconds of the lattice sweep kernel: the library
+    records HIP events on the launch stream around that kernel of each of
+    `launches` sweeps (the one-block finish kernel is outside the brackets)."""
     torch.cuda.synchronize()
-    for a, b in evs:
-        a.record(s)
-        chain.sweep(1, hyper=True)
-        b.record(s)
-    torch.cuda.synchronize()
-    return float(np.mean([a.elapsed_time(b) for a, b in evs])) / 1e3
+    return chain.sweep_timed(launches, hyper=True) / launches / 1e3
 
 
 def solve_latencies(torch, chain, sweeps, reps):
@@ -185,7 +178,7 @@ def main():
         chain.sweep(args.steps, hyper=True, capture=True)      # record the graph once
         torch.cuda.synchronize()
         t_graph = timed_sweeps(torch, chain, args.steps, capture=True)
-        k_avg = kernel_time(torch, chain, 50)
+        k_avg = kernel_time(torch, chain, 200)
         lat = solve_latencies(torch, chain, 1000, args.reps)
         mean, var, nacc = chain.posterior_stats()
         x, tau, lam, sw = chain.get_state()

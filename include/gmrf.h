@@ -99,7 +99,7 @@ typedef struct {
     int32_t num_colors;     /* k (lattice: 2 or 4, or 0 to imply it) */
     int32_t lat_rows, lat_cols;
     int32_t lat_stencil;    /* 0 = general graph, 4 or 8 = lattice */
-    double rho;             /* 1 = intrinsic CAR; 0 <= rho < 1 proper CAR */
+    double rho;             /* 1 = intrinsic CAR; -1 < rho < 1 proper CAR */
 } gmrf_graph_desc;
 
 /* Model constants of one chain. */
@@ -133,7 +133,7 @@ size_t gmrf_graph_footprint(const gmrf_graph_desc *d);
  * arrays are uploaded to d_ws (ws_bytes >= gmrf_graph_footprint(d)) on stream
  * and the call synchronises the stream before returning.  Checks: CSR shape,
  * ranges, symmetry, no self loops / duplicates, proper coloring (Sec. 2.3: no
- * edge inside a color class), 0 <= rho <= 1.  Errors: GMRF_E_INVALID_ARG,
+ * edge inside a color class), -1 < rho <= 1.  Errors: GMRF_E_INVALID_ARG,
  * GMRF_E_GRAPH, GMRF_E_COLORING, GMRF_E_WORKSPACE, GMRF_E_DEVICE. */
 int gmrf_graph_create(const gmrf_graph_desc *d, void *d_ws, size_t ws_bytes, hipStream_t stream,
                       gmrf_graph **out);
@@ -175,6 +175,15 @@ int gmrf_chain_destroy(gmrf_chain *c);
  * as a HIP graph the first time a (nsweeps, flags) pair is seen on this chain
  * and replays it afterwards.  No host synchronisation. */
 int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream);
+
+/* Profiling form of gmrf_sweep (plain launches, no capture): the same sweeps,
+ * with a pair of HIP events recorded on the stream around the sweep kernels
+ * of every sweep (the lattice kernel, or the color passes of a general
+ * graph), excluding the one-block finish kernel that sums the reductions and
+ * draws tau / lam.  Synchronises and returns in *kernel_ms the summed event
+ * time of the sweep kernels over the nsweeps sweeps. */
+int gmrf_sweep_timed(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream,
+                     double *kernel_ms);
 
 /* Draw tau and lam (Sec. 3.1 conjugate conditionals) from the reductions of
  * the last completed sweep, with that sweep's index in the random counter;

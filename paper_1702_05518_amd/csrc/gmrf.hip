@@ -499,7 +499,7 @@ __global__ __launch_bounds__(Cfg::NT) void lattice_sweep_kernel(LatArgs<Real> la
             }
         }
     }
-    write_partials<NT>(a, q, sse, (int)blockIdx.x);
+    write_partials<NT>(a, q, sse, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -570,6 +570,8 @@ __global__ void set_hyper_kernel(DevState *st, double tau, double lam)
     st->lam = lam;
 }
 
+// Posterior mean S1/N and variance (S2 - S1^2/N)/(N - 1), un-permuted to the
+// original site order (orig NULL for a lattice).
 __global__ void stats_kernel(const double *s1, const double *s2, const int *orig, long long n,
                              const DevState *st, double *mean, double *var)
 {
@@ -630,6 +632,7 @@ namespace {
 #ifndef GMRF_LAT_CH
 #define GMRF_LAT_CH 4
 #endif
+
 constexpr int kLatTH = GMRF_LAT_TH, kLatTW = GMRF_LAT_TW;
 template <int ST> using LatticeCfg = LatCfg<ST, kLatTH, kLatTW, GMRF_LAT_NT, GMRF_LAT_CH>;
 
@@ -727,9 +730,17 @@ template <typename Real, int ST> void launch_lattice(const gmrf_chain *c, const 
     la.rows = h.rows;
     la.cols = h.cols;
     la.tiles_c = (h.cols + kLatTW - 1) / kLatTW;
-    hipLaunchKernelGGL((lattice_sweep_kernel<Real, LatticeCfg<ST>>), dim3(c->total_slots),
-                       dim3(LatticeCfg<ST>::NT), 0, s, la, a);
+    using Cfg = LatticeCfg<ST>;
+    hipLaunchKernelGGL((lattice_sweep_kernel<Real, Cfg>), dim3(c->total_slots), dim3(Cfg::NT), 0,
+                       s, la, a);
 }
+
+// Launch configuration of the small element-wise kernels.
+int elementwise_blocks(int64_t n)
+{
+    return (int)std::min<int64_t>((n + kThreads - 1) / kThreads, 4096);
+}
+
 
 template <typename Real> void launch_csr(const gmrf_chain *c, const SweepArgs &a, hipStream_t s)
 {
@@ -752,7 +763,8 @@ template <typename Real> void launch_csr(const gmrf_chain *c, const SweepArgs &a
     }
 }
 
-void launch_one_sweep(const gmrf_chain *c, const SweepArgs &a, hipStream_t s)
+// The sweep kernels of one sweep (everything but the finish kernel).
+void launch_sweep_kernels(const gmrf_chain *c, const SweepArgs &a, hipStream_t s)
 {
     const bool f64 = c->prec == GMRF_FP64;
     if (is_lattice(c->g)) {
@@ -763,7 +775,17 @@ void launch_one_sweep(const gmrf_chain *c, const SweepArgs &a, hipStream_t s)
     } else {
         f64 ? launch_csr<double>(c, a, s) : launch_csr<float>(c, a, s);
     }
+}
+
+void launch_finish(const SweepArgs &a, hipStream_t s)
+{
     hipLaunchKernelGGL(finish_sweep_kernel, dim3(1), dim3(kThreads), 0, s, a);
+}
+
+void launch_one_sweep(const gmrf_chain *c, const SweepArgs &a, hipStream_t s)
+{
+    launch_sweep_kernels(c, a, s);
+    launch_finish(a, s);
 }
 
 int read_state(gmrf_chain *c, DevState *out, hipStream_t s)
@@ -1077,6 +1099,55 @@ int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t strea
     return GMRF_OK;
 }
 
+int gmrf_sweep_timed(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream,
+                     double *kernel_ms)
+{
+    clear_error();
+    if (!c || nsweeps < 0 || !kernel_ms || (flags & ~GMRF_WITH_HYPER))
+        return fail(GMRF_E_INVALID_ARG, "sweep_timed: NULL chain / output, negative count or "
+                                        "unsupported flag");
+    *kernel_ms = 0.0;
+    const SweepArgs a = make_args(c, flags);
+    std::vector<hipEvent_t> ev(2 * (size_t)nsweeps, nullptr);
+    int rc = GMRF_OK;
+    for (auto &e : ev) {
+        const hipError_t he = hipEventCreate(&e);
+        if (he != hipSuccess) {
+            rc = fail(GMRF_E_DEVICE, std::string("sweep_timed: ") + hipGetErrorString(he));
+            break;
+        }
+    }
+    if (rc == GMRF_OK) {
+        hipError_t he = hipSuccess;
+        for (int i = 0; i < nsweeps && he == hipSuccess; ++i) {
+            he = hipEventRecord(ev[2 * i], stream);
+            launch_sweep_kernels(c, a, stream);
+            if (he == hipSuccess)
+                he = hipEventRecord(ev[2 * i + 1], stream);
+            launch_finish(a, stream);
+            if (he == hipSuccess)
+                he = hipGetLastError();
+        }
+        if (he == hipSuccess)
+            he = hipStreamSynchronize(stream);
+        double total = 0.0;
+        for (int i = 0; i < nsweeps && he == hipSuccess; ++i) {
+            float ms = 0.0f;
+            he = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+            total += ms;
+        }
+        if (he != hipSuccess)
+            rc = fail(GMRF_E_DEVICE, std::string("sweep_timed: ") + hipGetErrorString(he));
+        else
+            *kernel_ms = total;
+        c->host_sweeps += (uint64_t)nsweeps;
+    }
+    for (auto &e : ev)
+        if (e)
+            (void)hipEventDestroy(e);
+    return rc;
+}
+
 int gmrf_hyper_update(gmrf_chain *c, hipStream_t stream)
 {
     clear_error();
@@ -1110,10 +1181,10 @@ int gmrf_posterior_stats(gmrf_chain *c, double *mean, double *var, int64_t *n_ac
     const int64_t n = c->g->h.n;
     double *dm = flags == GMRF_PTR_DEVICE ? mean : c->d_stats;
     double *dv = flags == GMRF_PTR_DEVICE ? var : c->d_stats + n;
-    const int blocks = (int)std::min<int64_t>((n + kThreads - 1) / kThreads, 4096);
+    const int blocks = elementwise_blocks(n);
+    const int *orig = is_lattice(c->g) ? nullptr : c->g->d_orig;
     hipLaunchKernelGGL(stats_kernel, dim3(blocks), dim3(kThreads), 0, stream, c->d_s1, c->d_s2,
-                       is_lattice(c->g) ? nullptr : c->g->d_orig, (long long)n, c->d_state, dm,
-                       dv);
+                       orig, (long long)n, c->d_state, dm, dv);
     GMRF_HIP(hipGetLastError());
     if (flags == GMRF_PTR_DEVICE)
         return GMRF_OK;

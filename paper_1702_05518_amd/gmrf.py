@@ -63,6 +63,8 @@ _SIGS = {
                            C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "gmrf_chain_destroy": ([C.c_void_p], C.c_int),
     "gmrf_sweep": ([C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p], C.c_int),
+    "gmrf_sweep_timed": ([C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p,
+                          C.POINTER(C.c_double)], C.c_int),
     "gmrf_hyper_update": ([C.c_void_p, C.c_void_p], C.c_int),
     "gmrf_set_hyper": ([C.c_void_p, C.c_double, C.c_double, C.c_void_p], C.c_int),
     "gmrf_posterior_stats": ([C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64),
@@ -247,6 +249,14 @@ class Chain:
         flags = (WITH_HYPER if hyper else 0) | (CAPTURE if capture else 0)
         _check(lib().gmrf_sweep(self.handle, int(nsweeps), flags, _stream_handle(stream)))
         return self
+
+    def sweep_timed(self, nsweeps: int, hyper: bool = True, stream=None) -> float:
+        """Run nsweeps sweeps (plain launches) and return the summed duration in
+        ms of their sweep kernels, from HIP events around those kernels."""
+        ms = C.c_double()
+        _check(lib().gmrf_sweep_timed(self.handle, int(nsweeps), WITH_HYPER if hyper else 0,
+                                      _stream_handle(stream), C.byref(ms)))
+        return ms.value
 
     def hyper_update(self, stream=None):
         _check(lib().gmrf_hyper_update(self.handle, _stream_handle(stream)))

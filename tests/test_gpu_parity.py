@@ -282,3 +282,39 @@ def test_chain_argument_errors(G):
         ch.hyper_update()          # no completed sweep
     with pytest.raises(G.GmrfError):
         ch.set_hyper(0.0, 1.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_lattice_checkpoint_resume_and_burn_in(G, orc, prec):
+    """Lattice chains add a sweep's x to the sums one sweep late; reading or
+    replacing the state or the sums must give exactly the immediate sums."""
+    wl = lattice_case(70, 90, 8)
+    p = G.FP64 if prec == "fp64" else G.FP32_ACC64
+    g = gpu_graph(G, wl)
+    full = G.Chain(g, wl["y"], precision=p, seed=13, burn_in=3)
+    full.sweep(11)
+    part = G.Chain(g, wl["y"], precision=p, seed=13, burn_in=3)
+    part.sweep(6)
+    x, tau, lam, sw = part.get_state()
+    s1, s2, nacc = part.get_accumulators()
+    assert nacc == 3
+    res = G.Chain(g, wl["y"], precision=p, seed=13, burn_in=3)
+    res.set_state(x, tau, lam, sw)
+    res.set_accumulators(s1, s2, nacc)
+    res.sweep(5)
+    part.sweep(5)                  # continuing after get_accumulators
+    a, b, c = full.get_state(), res.get_state(), part.get_state()
+    assert np.array_equal(a[0], b[0]) and a[1:] == b[1:]
+    assert np.array_equal(a[0], c[0]) and a[1:] == c[1:]
+    ma, va, na = full.posterior_stats()
+    for other in (res, part):
+        mb, vb, nb = other.posterior_stats()
+        assert na == nb == 8
+        assert np.array_equal(ma, mb) and np.array_equal(va, vb)
+    if prec == "fp64":
+        oc = orc.Chain(wl["row_ptr"], wl["col"], wl["color"], wl["y"], seed=13, burn_in=3)
+        oc.sweeps(11)
+        om, ov = oc.stats()
+        assert rel(ma, om) <= RTOL64
+        s1f, s2f, nf = full.get_accumulators()
+        assert nf == 8 and rel(s1f, oc.s1) <= RTOL64 and rel(s2f, oc.s2) <= RTOL64
