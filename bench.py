@@ -33,6 +33,13 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE = {"fp32_acc": 44, "fp64_acc": 56}   # x read + x write + y read + S1/S2 RMW
 METRIC = ("site-updates/s + HBM GB/s fraction per sweep; p50/p99 solve latency "
           "(FP32 vs FP64)")
+# Name of the dominant kernel (the FP32 lattice sweep) and its HBM traffic per
+# launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, each scaled by the counter
+# reading of a 512 MiB device copy (profiles/lattice_sweep_2048x2048_s8_fp32_traffic.md).
+# The figure belongs to this kernel build; it is reported only while the
+# kernel name below matches the library's configuration.
+SWEEP_KERNEL = "lattice_sweep_kernel<float, LatCfg<8, 64, 64, 512, 4>>"
+MEASURED_TRAFFIC_BYTES = {SWEEP_KERNEL: 189.6e6}
 
 
 def log(msg):
@@ -219,8 +226,11 @@ def main():
                    "sites": n, "colors": 4, "sweep_launch": "hipGraph" if r["t_graph"] <=
                    r["t_plain"] else "stream"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "lattice_sweep_kernel<float,8,64,64>",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": MEASURED_TRAFFIC_BYTES.get(SWEEP_KERNEL),
+                     "traffic_unit": "bytes/launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
+                     "algorithmic_bytes": bytes_launch,
+                     "kernel": SWEEP_KERNEL,
                      "bytes_per_site": BYTES_PER_SITE["fp32_acc"],
                      "kernel_us": r["kernel_s"] * 1e6},
         "sweep_ms": {"fp32_stream": r["t_plain"] / args.steps * 1e3,

@@ -177,11 +177,12 @@ int gmrf_chain_destroy(gmrf_chain *c);
 int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream);
 
 /* Profiling form of gmrf_sweep (plain launches, no capture): the same sweeps,
- * with a pair of HIP events recorded on the stream around the sweep kernels
- * of every sweep (the lattice kernel, or the color passes of a general
- * graph), excluding the one-block finish kernel that sums the reductions and
- * draws tau / lam.  Synchronises and returns in *kernel_ms the summed event
- * time of the sweep kernels over the nsweeps sweeps. */
+ * with a pair of HIP events that the dispatches themselves record at the
+ * start and the end of the sweep kernels of every sweep (the lattice kernel,
+ * or the first to the last color pass of a general graph), excluding the
+ * one-block finish kernel that sums the reductions and draws tau / lam.
+ * Synchronises and returns in *kernel_ms the summed event time of the sweep
+ * kernels over the nsweeps sweeps. */
 int gmrf_sweep_timed(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream,
                      double *kernel_ms);
 

@@ -318,3 +318,16 @@ def test_lattice_checkpoint_resume_and_burn_in(G, orc, prec):
         assert rel(ma, om) <= RTOL64
         s1f, s2f, nf = full.get_accumulators()
         assert nf == 8 and rel(s1f, oc.s1) <= RTOL64 and rel(s2f, oc.s2) <= RTOL64
+
+
+@pytest.mark.parametrize("kind", ["lattice", "csr"])
+def test_sweep_timed_equals_sweep(G, orc, kind):
+    wl = lattice_case(100, 120, 8) if kind == "lattice" else csr_case(4000, data_seed=2)
+    g = gpu_graph(G, wl)
+    a = G.Chain(g, wl["y"], seed=4)
+    b = G.Chain(g, wl["y"], seed=4)
+    a.sweep(6)
+    ms = b.sweep_timed(6)
+    assert ms > 0.0
+    sa, sb = a.get_state(), b.get_state()
+    assert np.array_equal(sa[0], sb[0]) and sa[1:] == sb[1:]
