@@ -127,9 +127,10 @@ int gmrf_version(void);
 size_t gmrf_graph_footprint(const gmrf_graph_desc *d);
 
 /* Validate d and build the device form of the graph: for a general graph the
- * sites are permuted so that each color is a contiguous slab (color, then
- * ascending original id), with a permuted CSR (int32) whose neighbour lists
- * stay in ascending ORIGINAL-id order, plus the slab-to-original map.  The
+ * sites are permuted so that each color is a contiguous slab (color, then a
+ * breadth-first locality order), with a permuted CSR (int32) whose neighbour
+ * lists stay in ascending ORIGINAL-id order, plus the slab-to-original map.
+ * The permutation is internal: results are keyed by original ids.  The
  * arrays are uploaded to d_ws (ws_bytes >= gmrf_graph_footprint(d)) on stream
  * and the call synchronises the stream before returning.  Checks: CSR shape,
  * ranges, symmetry, no self loops / duplicates, proper coloring (Sec. 2.3: no

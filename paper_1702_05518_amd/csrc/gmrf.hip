@@ -63,7 +63,8 @@ struct SweepArgs {
     DevState *st;
     double *partials;           // two doubles (q, sse) per block slot
     double *s1, *s2;            // posterior accumulators (layout of x)
-    double shape_tau, b_tau, shape_lam, b_lam;
+    GammaShape g_tau, g_lam;    // Marsaglia-Tsang constants of a_tau + r/2, a_lam + n/2
+    double b_tau, b_lam;
     double rho;
     long long burn_in;
     unsigned long long seed;
@@ -131,10 +132,10 @@ __device__ __forceinline__ void draw_hyper(const SweepArgs &a, unsigned t, doubl
                                            int lane)
 {
     if (lane < 2) {
-        const double shape = lane == 0 ? a.shape_tau : a.shape_lam;
+        const GammaShape g = lane == 0 ? a.g_tau : a.g_lam;
         const double rate = lane == 0 ? a.b_tau + 0.5 * q : a.b_lam + 0.5 * sse;
         double v = 0.0;
-        const bool ok = gamma_draw(shape, rate, a.seed, t, a.instance, (unsigned)(lane + 1), &v);
+        const bool ok = gamma_draw(g, rate, a.seed, t, a.instance, (unsigned)(lane + 1), &v);
         if (ok && isfinite(v) && v > 0.0) {
             if (lane == 0)
                 a.st->tau = v;
@@ -149,16 +150,18 @@ __device__ __forceinline__ void draw_hyper(const SweepArgs &a, unsigned t, doubl
 // End of a sweep (one block): sum the partials of every block of the sweep
 // in slot order, store q / sse, draw tau / lam, count the accumulated sweep
 // and advance the sweep index.
-__global__ __launch_bounds__(kThreads) void finish_sweep_kernel(SweepArgs a)
+constexpr int kFinishThreads = 1024;
+
+__global__ __launch_bounds__(kFinishThreads) void finish_sweep_kernel(SweepArgs a)
 {
-    __shared__ double red[2 * (kThreads / 64)];
+    __shared__ double red[2 * (kFinishThreads / 64)];
     const unsigned t = (unsigned)a.st->sweep;
     double tq = 0.0, ts = 0.0;
-    for (int i = threadIdx.x; i < a.total_slots; i += kThreads) {
+    for (int i = threadIdx.x; i < a.total_slots; i += kFinishThreads) {
         tq += a.partials[2 * i];
         ts += a.partials[2 * i + 1];
     }
-    block_sum2<kThreads>(tq, ts, red);
+    block_sum2<kFinishThreads>(tq, ts, red);
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
         tq = __shfl(tq, 0, 64);
@@ -514,6 +517,12 @@ template <typename Real> struct CsrArgs {
     const Real *y;
 };
 
+// One site per thread.  The first kCsrBatch neighbours are gathered in one
+// batch (all column indices, then all values) and kept in registers for the
+// q terms; longer rows continue in a plain loop.  The summation order is the
+// row order, i.e. ascending original neighbour id.
+constexpr int kCsrBatch = 8;
+
 template <typename Real>
 __global__ __launch_bounds__(kThreads) void csr_pass_kernel(CsrArgs<Real> ca, SweepArgs a, int lo,
                                                             int cnt, int slot_base)
@@ -525,12 +534,31 @@ __global__ __launch_bounds__(kThreads) void csr_pass_kernel(CsrArgs<Real> ca, Sw
     double q = 0.0, sse = 0.0;
     if (p < lo + cnt) {
         const int e0 = ca.row_ptr[p], e1 = ca.row_ptr[p + 1];
-        Real s = (Real)0;
-        for (int e = e0; e < e1; ++e)
-            s += ca.x[ca.col[e]];
         const int deg = e1 - e0;
         const Real yv = ca.y[p];
-        const Words4 w = draw_words(a.seed, (unsigned)ca.orig[p], t, a.instance, 0u);
+        const unsigned id = (unsigned)ca.orig[p];
+        const bool acc = (long long)t >= a.burn_in;
+        double o1 = 0.0, o2 = 0.0;
+        if (acc) {
+            o1 = a.s1[p];
+            o2 = a.s2[p];
+        }
+        int cj[kCsrBatch];
+        Real nb[kCsrBatch];
+#pragma unroll
+        for (int k = 0; k < kCsrBatch; ++k)
+            cj[k] = ca.col[min(e0 + k, max(e1 - 1, 0))];   // clamped; used only if k < deg
+#pragma unroll
+        for (int k = 0; k < kCsrBatch; ++k)
+            nb[k] = ca.x[cj[k]];
+        Real s = (Real)0;
+#pragma unroll
+        for (int k = 0; k < kCsrBatch; ++k)
+            if (k < deg)
+                s += nb[k];
+        for (int e = e0 + kCsrBatch; e < e1; ++e)
+            s += ca.x[ca.col[e]];
+        const Words4 w = draw_words(a.seed, id, t, a.instance, 0u);
         const Real z = site_normal<Real>(w);
         Real inv_q, isd;
         site_scales<Real>(tau, lam, deg, inv_q, isd);
@@ -538,9 +566,15 @@ __global__ __launch_bounds__(kThreads) void csr_pass_kernel(CsrArgs<Real> ca, Sw
         ca.x[p] = xn;
         const double xd = (double)xn;
         double edge = 0.0;
-        for (int e = e0; e < e1; ++e) {
+#pragma unroll
+        for (int k = 0; k < kCsrBatch; ++k)
+            if (k < deg && cj[k] < lo) {   // lower color: already final this sweep
+                const double d = xd - (double)nb[k];
+                edge += d * d;
+            }
+        for (int e = e0 + kCsrBatch; e < e1; ++e) {
             const int j = ca.col[e];
-            if (j < lo) {                  // lower color: already final this sweep
+            if (j < lo) {
                 const double d = xd - (double)ca.x[j];
                 edge += d * d;
             }
@@ -548,9 +582,9 @@ __global__ __launch_bounds__(kThreads) void csr_pass_kernel(CsrArgs<Real> ca, Sw
         q = (1.0 - a.rho) * (double)deg * xd * xd + a.rho * edge;
         const double rr = (double)yv - xd;
         sse = rr * rr;
-        if ((long long)t >= a.burn_in) {
-            a.s1[p] += xd;
-            a.s2[p] += xd * xd;
+        if (acc) {
+            a.s1[p] = o1 + xd;
+            a.s2[p] = o2 + xd * xd;
         }
     }
     write_partials<kThreads>(a, q, sse, slot_base + (int)blockIdx.x);
@@ -707,9 +741,13 @@ SweepArgs make_args(const gmrf_chain *c, unsigned flags)
     a.partials = c->d_partials;
     a.s1 = c->d_s1;
     a.s2 = c->d_s2;
-    a.shape_tau = c->model.a_tau + 0.5 * (double)c->rank;
+    const double shape_tau = c->model.a_tau + 0.5 * (double)c->rank;
+    const double shape_lam = c->model.a_lam + 0.5 * (double)c->g->h.n;
+    a.g_tau.d = shape_tau - 1.0 / 3.0;
+    a.g_tau.c = 1.0 / std::sqrt(9.0 * a.g_tau.d);
+    a.g_lam.d = shape_lam - 1.0 / 3.0;
+    a.g_lam.c = 1.0 / std::sqrt(9.0 * a.g_lam.d);
     a.b_tau = c->model.b_tau;
-    a.shape_lam = c->model.a_lam + 0.5 * (double)c->g->h.n;
     a.b_lam = c->model.b_lam;
     a.rho = c->g->h.rho;
     a.burn_in = (long long)c->model.burn_in;
@@ -800,7 +838,7 @@ void launch_sweep_kernels(const gmrf_chain *c, const SweepArgs &a, hipStream_t s
 
 void launch_finish(const SweepArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(finish_sweep_kernel, dim3(1), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL(finish_sweep_kernel, dim3(1), dim3(kFinishThreads), 0, s, a);
 }
 
 void launch_one_sweep(const gmrf_chain *c, const SweepArgs &a, hipStream_t s)
@@ -902,8 +940,11 @@ int gmrf_version(void) { return 10000; }
 
 size_t gmrf_graph_footprint(const gmrf_graph_desc *d)
 {
-    if (!d)
-        return (size_t)fail(GMRF_E_INVALID_ARG, "graph_footprint: NULL description") * 0;
+    clear_error();
+    if (!d) {
+        set_error("graph_footprint: NULL description");
+        return 0;
+    }
     if (d->lat_stencil != 0)
         return 0;
     if (d->n < 1 || !d->row_ptr) {

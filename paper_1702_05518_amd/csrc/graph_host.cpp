@@ -51,6 +51,34 @@ int64_t count_components(int64_t n, const std::vector<int64_t> &rp, const int32_
     return comps;
 }
 
+// Breadth-first visit order of all sites: each component from its smallest
+// unvisited id, neighbours queued in ascending id order.
+std::vector<int64_t> breadth_first_order(int64_t n, const std::vector<int64_t> &rp,
+                                         const int32_t *col)
+{
+    std::vector<int64_t> order;
+    order.reserve(n);
+    std::vector<unsigned char> seen(n, 0);
+    for (int64_t s = 0; s < n; ++s) {
+        if (seen[s])
+            continue;
+        seen[s] = 1;
+        size_t head = order.size();
+        order.push_back(s);
+        while (head < order.size()) {
+            const int64_t v = order[head++];
+            for (int64_t e = rp[v]; e < rp[v + 1]; ++e) {
+                const int64_t u = col[e];
+                if (!seen[u]) {
+                    seen[u] = 1;
+                    order.push_back(u);
+                }
+            }
+        }
+    }
+    return order;
+}
+
 int build_lattice(const gmrf_graph_desc *d, HostGraph *g)
 {
     const int64_t rows = d->lat_rows, cols = d->lat_cols;
@@ -176,7 +204,12 @@ int build_host_graph(const gmrf_graph_desc *d, HostGraph *g)
     std::vector<int64_t> rpv(rp, rp + n + 1);
     g->components = count_components(n, rpv, col);
 
-    // color slabs: stable counting sort of the sites by color
+    // Color slabs.  Inside a slab the sites follow a breadth-first order of
+    // the graph (components by smallest id, neighbours by ascending id), so
+    // the threads of one wavefront touch nearby sites and their neighbour
+    // gathers share cache lines.  The order is internal: random numbers are
+    // keyed by original ids and neighbour sums run in original-id order.
+    const std::vector<int64_t> visit = breadth_first_order(n, rpv, col);
     g->slab_offsets.assign(k + 1, 0);
     for (int64_t i = 0; i < n; ++i)
         g->slab_offsets[d->color[i] + 1]++;
@@ -185,7 +218,8 @@ int build_host_graph(const gmrf_graph_desc *d, HostGraph *g)
     g->orig_of_slab.resize(n);
     g->slab_of_orig.resize(n);
     std::vector<int32_t> fill(g->slab_offsets.begin(), g->slab_offsets.end() - 1);
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t i = visit[v];
         const int32_t pos = fill[d->color[i]]++;
         g->orig_of_slab[pos] = (int32_t)i;
         g->slab_of_orig[i] = pos;

@@ -25,8 +25,9 @@ struct HostGraph {
     double rho = 1.0;
     int32_t rows = 0, cols = 0;   // lattice shape
     int32_t stencil = 0;          // 0 = general graph, 4 or 8 = lattice
-    // General graphs: sites permuted into color slabs (color, then original
-    // id).  slab_offsets[c] .. slab_offsets[c+1] is color c.
+    // General graphs: sites permuted into color slabs (color, then a
+    // breadth-first locality order).  slab_offsets[c] .. slab_offsets[c+1] is
+    // color c.
     std::vector<int32_t> slab_offsets;   // k + 1
     std::vector<int32_t> orig_of_slab;   // slab position -> original id
     std::vector<int32_t> slab_of_orig;   // original id -> slab position

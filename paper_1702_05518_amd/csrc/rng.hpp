@@ -94,15 +94,21 @@ template <> __device__ __forceinline__ float site_normal<float>(const Words4 &w)
 
 constexpr int kGammaMaxAttempts = 64;
 
-// Gamma(shape >= 1, rate) for the hyperparameter draw after sweep `sweep`.
+// Marsaglia-Tsang constants of a shape >= 1: d = shape - 1/3, c = 1/sqrt(9 d)
+// (the shapes depend only on n and the priors, so they are computed once per
+// chain on the host, with the same operations).
+struct GammaShape {
+    double d, c;
+};
+
+// Gamma(shape, rate) for the hyperparameter draw after sweep `sweep`.
 // Attempt k takes its normal from counter (2k, sweep, instance, tag) and its
 // uniform from counter (2k + 1, ...).  Returns false when every attempt was
 // rejected (the caller flags a numeric error).
-__device__ inline bool gamma_draw(double shape, double rate, uint64_t seed, uint32_t sweep,
+__device__ inline bool gamma_draw(GammaShape g, double rate, uint64_t seed, uint32_t sweep,
                                   uint32_t instance, uint32_t tag, double *out)
 {
-    const double d = shape - 1.0 / 3.0;
-    const double c = 1.0 / sqrt(9.0 * d);
+    const double d = g.d, c = g.c;
     for (int k = 0; k < kGammaMaxAttempts; ++k) {
         const double z = normal_f64(draw_words(seed, (uint32_t)(2 * k), sweep, instance, tag));
         const double cz = c * z;
