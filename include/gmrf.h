@@ -229,6 +229,36 @@ int gmrf_set_accumulators(gmrf_chain *c, const double *s1, const double *s2, int
  * sse = ||y - x||^2 (FP64).  Synchronises. */
 int gmrf_last_reductions(gmrf_chain *c, double *q, double *sse, hipStream_t stream);
 
+/* ---- batches: many chains advanced by shared launches -------------------- */
+
+typedef struct gmrf_batch gmrf_batch;
+
+/* Device workspace bytes of a batch over `count` chains (the job tables of
+ * the shared launches).  Returns 0 and sets the error message if the chains
+ * cannot form a batch. */
+size_t gmrf_batch_footprint(gmrf_chain *const *chains, int32_t count);
+
+/* Group `count` distinct chains of one precision, each on its own graph or
+ * sharing graphs, so that gmrf_batch_sweep advances all of them with shared
+ * launches: one lattice launch per stencil covering the tiles of every
+ * lattice chain, one launch per color index covering that color's slab of
+ * every general-graph chain, and one finish launch with a block per chain
+ * (Sec. 2.3, Algorithm 1, for every chain; the independent chains need no
+ * communication).  Each chain keeps its own workspace, state, reductions and
+ * random streams, so its results equal those of gmrf_sweep on that chain bit
+ * for bit.  The tables are uploaded to d_ws (ws_bytes >=
+ * gmrf_batch_footprint) and the call synchronises the stream.  The chains
+ * must outlive the batch and must not be swept on their own while the batch
+ * is in use on another stream.  Errors: GMRF_E_INVALID_ARG (count < 1, NULL
+ * or repeated chain, mixed precisions), GMRF_E_WORKSPACE, GMRF_E_DEVICE. */
+int gmrf_batch_create(gmrf_chain *const *chains, int32_t count, void *d_ws, size_t ws_bytes,
+                      hipStream_t stream, gmrf_batch **out);
+int gmrf_batch_destroy(gmrf_batch *b);
+
+/* nsweeps sweeps of every chain of the batch; flags as for gmrf_sweep
+ * (GMRF_WITH_HYPER, GMRF_CAPTURE). */
+int gmrf_batch_sweep(gmrf_batch *b, int32_t nsweeps, uint32_t flags, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,7 +18,8 @@ LIB = os.path.join(HERE, "libgmrf.so")
 SOURCES = ["gmrf.hip", "graph_host.cpp"]
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
                 "-packed-fp32-ops"]
-COMMON_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-command-line-argument"]
+COMMON_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-command-line-argument",
+                "-ffp-contract=on"]
 
 
 def hipcc() -> str:

@@ -152,7 +152,7 @@ __device__ __forceinline__ void draw_hyper(const SweepArgs &a, unsigned t, doubl
 // and advance the sweep index.
 constexpr int kFinishThreads = 1024;
 
-__global__ __launch_bounds__(kFinishThreads) void finish_sweep_kernel(SweepArgs a)
+__device__ __forceinline__ void finish_sweep_block(const SweepArgs &a)
 {
     __shared__ double red[2 * (kFinishThreads / 64)];
     const unsigned t = (unsigned)a.st->sweep;
@@ -176,6 +176,20 @@ __global__ __launch_bounds__(kFinishThreads) void finish_sweep_kernel(SweepArgs 
             a.st->sweep = (unsigned long long)t + 1ull;
         }
     }
+}
+
+__global__ __launch_bounds__(kFinishThreads) void finish_sweep_kernel(SweepArgs a)
+{
+    finish_sweep_block(a);
+}
+
+// Batched finish: block b ends the sweep of chain b.
+__global__ __launch_bounds__(kFinishThreads) void finish_batch_kernel(const SweepArgs *args,
+                                                                     int with_hyper)
+{
+    SweepArgs a = args[blockIdx.x];
+    a.with_hyper = with_hyper;
+    finish_sweep_block(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -410,7 +424,8 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
 }
 
 template <typename Real, typename Cfg>
-__global__ __launch_bounds__(Cfg::NT) void lattice_sweep_kernel(LatArgs<Real> la, SweepArgs a)
+__device__ __forceinline__ void lattice_sweep_block(const LatArgs<Real> &la, const SweepArgs &a,
+                                                    const int tile)
 {
     constexpr int H = Cfg::H, LH = Cfg::LH, LW = Cfg::LW, NT = Cfg::NT;
     constexpr int TH = Cfg::TH, TW = Cfg::TW;
@@ -435,7 +450,6 @@ __global__ __launch_bounds__(Cfg::NT) void lattice_sweep_kernel(LatArgs<Real> la
     const Real *src = (t & 1u) ? la.x1 : la.x0;
     Real *dst = (t & 1u) ? la.x0 : la.x1;
     const int rows = la.rows, cols = la.cols;
-    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int tr = tile / la.tiles_c, tc = tile - tr * la.tiles_c;
     const int r0 = tr * TH, c0 = tc * TW;
     const bool acc = (long long)t >= a.burn_in;
@@ -506,6 +520,32 @@ __global__ __launch_bounds__(Cfg::NT) void lattice_sweep_kernel(LatArgs<Real> la
     write_partials<NT>(a, q, sse, tile);
 }
 
+template <typename Real, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void lattice_sweep_kernel(LatArgs<Real> la, SweepArgs a)
+{
+    lattice_sweep_block<Real, Cfg>(la, a, xcd_tile((int)blockIdx.x, (int)gridDim.x));
+}
+
+// Batched lattice sweep: the tile table lists the tiles of every lattice
+// chain of the batch, chain by chain; each chain's partial slots are its own
+// tile indices, as in a standalone sweep.
+template <typename Real> struct LatJob {
+    LatArgs<Real> la;
+    SweepArgs a;
+};
+struct LatTile {
+    int job, tile;
+};
+
+template <typename Real, typename Cfg>
+__global__ __launch_bounds__(Cfg::NT) void lattice_batch_kernel(const LatJob<Real> *jobs,
+                                                                const LatTile *tiles)
+{
+    const LatTile tl = tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
+    const LatJob<Real> &j = jobs[tl.job];
+    lattice_sweep_block<Real, Cfg>(j.la, j.a, tl.tile);
+}
+
 // ---------------------------------------------------------------------------
 // general graphs: one color slab per launch
 // ---------------------------------------------------------------------------
@@ -523,14 +563,16 @@ template <typename Real> struct CsrArgs {
 // row order, i.e. ascending original neighbour id.
 constexpr int kCsrBatch = 8;
 
+// Sites p0 + threadIdx.x of the color slab [lo, lo + cnt); partial slot `slot`.
 template <typename Real>
-__global__ __launch_bounds__(kThreads) void csr_pass_kernel(CsrArgs<Real> ca, SweepArgs a, int lo,
-                                                            int cnt, int slot_base)
+__device__ __forceinline__ void csr_pass_block(const CsrArgs<Real> &ca, const SweepArgs &a,
+                                               const int lo, const int cnt, const int p0,
+                                               const int slot)
 {
     const unsigned t = (unsigned)a.st->sweep;
     const double tau_d = a.st->tau, lam_d = a.st->lam;
     const Real tau = (Real)tau_d, lam = (Real)lam_d, tau_rho = (Real)(tau_d * a.rho);
-    const int p = lo + (int)blockIdx.x * kThreads + (int)threadIdx.x;
+    const int p = p0 + (int)threadIdx.x;
     double q = 0.0, sse = 0.0;
     if (p < lo + cnt) {
         const int e0 = ca.row_ptr[p], e1 = ca.row_ptr[p + 1];
@@ -587,7 +629,34 @@ __global__ __launch_bounds__(kThreads) void csr_pass_kernel(CsrArgs<Real> ca, Sw
             a.s2[p] = o2 + xd * xd;
         }
     }
-    write_partials<kThreads>(a, q, sse, slot_base + (int)blockIdx.x);
+    write_partials<kThreads>(a, q, sse, slot);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kThreads) void csr_pass_kernel(CsrArgs<Real> ca, SweepArgs a, int lo,
+                                                            int cnt, int slot_base)
+{
+    csr_pass_block<Real>(ca, a, lo, cnt, lo + (int)blockIdx.x * kThreads,
+                         slot_base + (int)blockIdx.x);
+}
+
+// Batched color pass: one entry per block over the color-c slabs of every
+// general-graph chain of the batch.
+template <typename Real> struct CsrJob {
+    CsrArgs<Real> ca;
+    SweepArgs a;
+};
+struct CsrBlock {
+    int job, lo, cnt, p0, slot;
+};
+
+template <typename Real>
+__global__ __launch_bounds__(kThreads) void csr_batch_kernel(const CsrJob<Real> *jobs,
+                                                             const CsrBlock *blocks)
+{
+    const CsrBlock bk = blocks[blockIdx.x];
+    const CsrJob<Real> &j = jobs[bk.job];
+    csr_pass_block<Real>(j.ca, j.a, bk.lo, bk.cnt, bk.p0, bk.slot);
 }
 
 // ---------------------------------------------------------------------------
@@ -647,6 +716,22 @@ struct gmrf_chain {
     int total_slots = 0;
     std::vector<int> pass_blocks;     // CSR: blocks per color pass
     uint64_t host_sweeps = 0;         // sweeps enqueued (host view)
+    hipStream_t capture_stream = nullptr;
+    std::map<std::pair<int, unsigned>, hipGraphExec_t> graphs;
+    std::vector<hipGraph_t> graph_defs;
+};
+
+struct gmrf_batch {
+    std::vector<gmrf_chain *> chains;
+    gmrf_precision prec = GMRF_FP64;
+    // device job tables (inside the batch workspace)
+    void *lat_jobs[2] = {nullptr, nullptr};       // stencil 4, stencil 8
+    LatTile *lat_tiles[2] = {nullptr, nullptr};
+    int lat_tile_count[2] = {0, 0};
+    void *csr_jobs = nullptr;
+    CsrBlock *csr_blocks = nullptr;
+    std::vector<int> csr_color_off;               // per color index: first block
+    SweepArgs *fin_args = nullptr;
     hipStream_t capture_stream = nullptr;
     std::map<std::pair<int, unsigned>, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_defs;
@@ -758,11 +843,7 @@ SweepArgs make_args(const gmrf_chain *c, unsigned flags)
     return a;
 }
 
-// ev0 / ev1 (optional): events the dispatch itself records at the start and
-// the end of the sweep kernel(s), for the profiling entry point.
-template <typename Real, int ST>
-void launch_lattice(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent_t ev0,
-                    hipEvent_t ev1)
+template <typename Real> LatArgs<Real> lattice_args(const gmrf_chain *c)
 {
     const HostGraph &h = c->g->h;
     LatArgs<Real> la;
@@ -772,6 +853,27 @@ void launch_lattice(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipE
     la.rows = h.rows;
     la.cols = h.cols;
     la.tiles_c = (h.cols + kLatTW - 1) / kLatTW;
+    return la;
+}
+
+template <typename Real> CsrArgs<Real> csr_args(const gmrf_chain *c)
+{
+    CsrArgs<Real> ca;
+    ca.row_ptr = c->g->d_row_ptr;
+    ca.col = c->g->d_col;
+    ca.orig = c->g->d_orig;
+    ca.x = static_cast<Real *>(c->d_x[0]);
+    ca.y = static_cast<const Real *>(c->d_y);
+    return ca;
+}
+
+// ev0 / ev1 (optional): events the dispatch itself records at the start and
+// the end of the sweep kernel(s), for the profiling entry point.
+template <typename Real, int ST>
+void launch_lattice(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent_t ev0,
+                    hipEvent_t ev1)
+{
+    const LatArgs<Real> la = lattice_args<Real>(c);
     using Cfg = LatticeCfg<ST>;
     if (ev0 || ev1)
         hipExtLaunchKernelGGL((lattice_sweep_kernel<Real, Cfg>), dim3(c->total_slots),
@@ -793,12 +895,7 @@ void launch_csr(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent
                 hipEvent_t ev1)
 {
     const HostGraph &h = c->g->h;
-    CsrArgs<Real> ca;
-    ca.row_ptr = c->g->d_row_ptr;
-    ca.col = c->g->d_col;
-    ca.orig = c->g->d_orig;
-    ca.x = static_cast<Real *>(c->d_x[0]);
-    ca.y = static_cast<const Real *>(c->d_y);
+    const CsrArgs<Real> ca = csr_args<Real>(c);
     int slot = 0, last = -1;
     for (int32_t col = 0; col < h.k; ++col)
         if (c->pass_blocks[col] > 0)
@@ -928,6 +1025,135 @@ bool finite_array(const double *v, int64_t n)
         if (!std::isfinite(v[i]))
             return false;
     return true;
+}
+
+// Host image of a batch's job tables and the offsets of its sections.
+struct BatchImage {
+    std::vector<char> bytes;
+    size_t off_lat_jobs[2] = {0, 0}, off_lat_tiles[2] = {0, 0};
+    size_t off_csr_jobs = 0, off_csr_blocks = 0, off_fin = 0;
+    int lat_tile_count[2] = {0, 0};
+    std::vector<int> csr_color_off;
+};
+
+template <typename T> size_t append(std::vector<char> &img, const std::vector<T> &v)
+{
+    const size_t at = align_up(img.size());
+    img.resize(at + align_up(sizeof(T) * std::max<size_t>(v.size(), 1)));
+    if (!v.empty())
+        std::memcpy(img.data() + at, v.data(), sizeof(T) * v.size());
+    return at;
+}
+
+template <typename Real>
+void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im)
+{
+    std::vector<LatJob<Real>> ljobs[2];
+    std::vector<LatTile> ltiles[2];
+    std::vector<CsrJob<Real>> cjobs;
+    std::vector<std::vector<CsrBlock>> cblocks;   // per color index
+    std::vector<SweepArgs> fin;
+    for (const gmrf_chain *c : cs) {
+        const SweepArgs a = make_args(c, 0u);
+        fin.push_back(a);
+        const HostGraph &h = c->g->h;
+        if (is_lattice(c->g)) {
+            const int w = h.stencil == 8 ? 1 : 0;
+            const int job = (int)ljobs[w].size();
+            ljobs[w].push_back(LatJob<Real>{lattice_args<Real>(c), a});
+            for (int t = 0; t < c->total_slots; ++t)
+                ltiles[w].push_back(LatTile{job, t});
+        } else {
+            const int job = (int)cjobs.size();
+            cjobs.push_back(CsrJob<Real>{csr_args<Real>(c), a});
+            if ((int)cblocks.size() < h.k)
+                cblocks.resize(h.k);
+            int slot = 0;
+            for (int32_t col = 0; col < h.k; ++col) {
+                const int lo = h.slab_offsets[col], cnt = h.slab_offsets[col + 1] - lo;
+                for (int b = 0; b < c->pass_blocks[col]; ++b)
+                    cblocks[col].push_back(CsrBlock{job, lo, cnt, lo + b * kThreads, slot + b});
+                slot += c->pass_blocks[col];
+            }
+        }
+    }
+    std::vector<CsrBlock> flat;
+    im.csr_color_off.assign(1, 0);
+    for (const auto &v : cblocks) {
+        flat.insert(flat.end(), v.begin(), v.end());
+        im.csr_color_off.push_back((int)flat.size());
+    }
+    for (int w = 0; w < 2; ++w) {
+        im.off_lat_jobs[w] = append(im.bytes, ljobs[w]);
+        im.off_lat_tiles[w] = append(im.bytes, ltiles[w]);
+        im.lat_tile_count[w] = (int)ltiles[w].size();
+    }
+    im.off_csr_jobs = append(im.bytes, cjobs);
+    im.off_csr_blocks = append(im.bytes, flat);
+    im.off_fin = append(im.bytes, fin);
+}
+
+int check_batch_chains(gmrf_chain *const *chains, int32_t count, gmrf_precision *prec)
+{
+    if (!chains || count < 1)
+        return fail(GMRF_E_INVALID_ARG, "batch: need at least one chain");
+    std::vector<const gmrf_chain *> seen;
+    for (int32_t i = 0; i < count; ++i) {
+        const gmrf_chain *c = chains[i];
+        if (!c)
+            return fail(GMRF_E_INVALID_ARG, "batch: NULL chain at index " + std::to_string(i));
+        if (std::find(seen.begin(), seen.end(), c) != seen.end())
+            return fail(GMRF_E_INVALID_ARG, "batch: chain at index " + std::to_string(i) +
+                                                " appears twice");
+        if (c->prec != chains[0]->prec)
+            return fail(GMRF_E_INVALID_ARG, "batch: all chains must have one precision");
+        seen.push_back(c);
+    }
+    *prec = chains[0]->prec;
+    return GMRF_OK;
+}
+
+int build_image(gmrf_chain *const *chains, int32_t count, BatchImage &im, gmrf_precision *prec)
+{
+    const int rc = check_batch_chains(chains, count, prec);
+    if (rc != GMRF_OK)
+        return rc;
+    const std::vector<gmrf_chain *> cs(chains, chains + count);
+    if (*prec == GMRF_FP64)
+        build_batch_image<double>(cs, im);
+    else
+        build_batch_image<float>(cs, im);
+    return GMRF_OK;
+}
+
+template <typename Real> void launch_batch_sweep_kernels(const gmrf_batch *b, hipStream_t s)
+{
+    if (b->lat_tile_count[0] > 0)
+        hipLaunchKernelGGL((lattice_batch_kernel<Real, LatticeCfg<4>>), dim3(b->lat_tile_count[0]),
+                           dim3(LatticeCfg<4>::NT), 0, s,
+                           static_cast<const LatJob<Real> *>(b->lat_jobs[0]), b->lat_tiles[0]);
+    if (b->lat_tile_count[1] > 0)
+        hipLaunchKernelGGL((lattice_batch_kernel<Real, LatticeCfg<8>>), dim3(b->lat_tile_count[1]),
+                           dim3(LatticeCfg<8>::NT), 0, s,
+                           static_cast<const LatJob<Real> *>(b->lat_jobs[1]), b->lat_tiles[1]);
+    for (size_t col = 0; col + 1 < b->csr_color_off.size(); ++col) {
+        const int nb = b->csr_color_off[col + 1] - b->csr_color_off[col];
+        if (nb > 0)
+            hipLaunchKernelGGL((csr_batch_kernel<Real>), dim3(nb), dim3(kThreads), 0, s,
+                               static_cast<const CsrJob<Real> *>(b->csr_jobs),
+                               b->csr_blocks + b->csr_color_off[col]);
+    }
+}
+
+void launch_batch_sweep(const gmrf_batch *b, unsigned flags, hipStream_t s)
+{
+    if (b->prec == GMRF_FP64)
+        launch_batch_sweep_kernels<double>(b, s);
+    else
+        launch_batch_sweep_kernels<float>(b, s);
+    hipLaunchKernelGGL(finish_batch_kernel, dim3((unsigned)b->chains.size()),
+                       dim3(kFinishThreads), 0, s, b->fin_args,
+                       (flags & GMRF_WITH_HYPER) ? 1 : 0);
 }
 
 } // namespace
@@ -1368,6 +1594,106 @@ int gmrf_last_reductions(gmrf_chain *c, double *q, double *sse, hipStream_t stre
         return rc;
     if (q) *q = st.q;
     if (sse) *sse = st.sse;
+    return GMRF_OK;
+}
+
+size_t gmrf_batch_footprint(gmrf_chain *const *chains, int32_t count)
+{
+    clear_error();
+    BatchImage im;
+    gmrf_precision prec;
+    if (build_image(chains, count, im, &prec) != GMRF_OK)
+        return 0;
+    return align_up(im.bytes.size());
+}
+
+int gmrf_batch_create(gmrf_chain *const *chains, int32_t count, void *d_ws, size_t ws_bytes,
+                      hipStream_t stream, gmrf_batch **out)
+{
+    clear_error();
+    if (!out)
+        return fail(GMRF_E_INVALID_ARG, "batch_create: out is NULL");
+    *out = nullptr;
+    BatchImage im;
+    gmrf_precision prec;
+    int rc = build_image(chains, count, im, &prec);
+    if (rc != GMRF_OK)
+        return rc;
+    const size_t need = align_up(im.bytes.size());
+    if (!d_ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0)
+        return fail(GMRF_E_WORKSPACE, "batch_create: workspace NULL, misaligned or smaller than "
+                                      "gmrf_batch_footprint (" +
+                                          std::to_string(need) + " bytes)");
+    char *base = static_cast<char *>(d_ws);
+    GMRF_HIP(hipMemcpyAsync(base, im.bytes.data(), im.bytes.size(), hipMemcpyHostToDevice, stream));
+    GMRF_HIP(hipStreamSynchronize(stream));
+    gmrf_batch *b = new gmrf_batch();
+    b->chains.assign(chains, chains + count);
+    b->prec = prec;
+    for (int w = 0; w < 2; ++w) {
+        b->lat_jobs[w] = base + im.off_lat_jobs[w];
+        b->lat_tiles[w] = reinterpret_cast<LatTile *>(base + im.off_lat_tiles[w]);
+        b->lat_tile_count[w] = im.lat_tile_count[w];
+    }
+    b->csr_jobs = base + im.off_csr_jobs;
+    b->csr_blocks = reinterpret_cast<CsrBlock *>(base + im.off_csr_blocks);
+    b->csr_color_off = im.csr_color_off;
+    b->fin_args = reinterpret_cast<SweepArgs *>(base + im.off_fin);
+    *out = b;
+    return GMRF_OK;
+}
+
+int gmrf_batch_destroy(gmrf_batch *b)
+{
+    if (!b)
+        return GMRF_OK;
+    for (auto &kv : b->graphs)
+        (void)hipGraphExecDestroy(kv.second);
+    for (hipGraph_t gdef : b->graph_defs)
+        (void)hipGraphDestroy(gdef);
+    if (b->capture_stream)
+        (void)hipStreamDestroy(b->capture_stream);
+    delete b;
+    return GMRF_OK;
+}
+
+int gmrf_batch_sweep(gmrf_batch *b, int32_t nsweeps, uint32_t flags, hipStream_t stream)
+{
+    clear_error();
+    if (!b || nsweeps < 0 || (flags & ~(GMRF_WITH_HYPER | GMRF_CAPTURE)))
+        return fail(GMRF_E_INVALID_ARG, "batch_sweep: NULL batch, negative count or unknown flag");
+    if (nsweeps == 0)
+        return GMRF_OK;
+    if (flags & GMRF_CAPTURE) {
+        const auto key = std::make_pair((int)nsweeps, flags & GMRF_WITH_HYPER);
+        auto it = b->graphs.find(key);
+        if (it == b->graphs.end()) {
+            if (!b->capture_stream)
+                GMRF_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
+            GMRF_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
+            for (int i = 0; i < nsweeps; ++i)
+                launch_batch_sweep(b, flags, b->capture_stream);
+            hipGraph_t gdef = nullptr;
+            const hipError_t le = hipGetLastError();
+            GMRF_HIP(hipStreamEndCapture(b->capture_stream, &gdef));
+            if (le != hipSuccess) {
+                (void)hipGraphDestroy(gdef);
+                return fail(GMRF_E_DEVICE, std::string("batch_sweep: capture: ") +
+                                               hipGetErrorString(le));
+            }
+            hipGraphExec_t exec = nullptr;
+            GMRF_HIP(hipGraphInstantiate(&exec, gdef, nullptr, nullptr, 0));
+            b->graph_defs.push_back(gdef);
+            it = b->graphs.emplace(key, exec).first;
+        }
+        GMRF_HIP(hipGraphLaunch(it->second, stream));
+    } else {
+        for (int i = 0; i < nsweeps; ++i)
+            launch_batch_sweep(b, flags, stream);
+        GMRF_HIP(hipGetLastError());
+    }
+    for (gmrf_chain *c : b->chains)
+        c->host_sweeps += (uint64_t)nsweeps;
     return GMRF_OK;
 }
 

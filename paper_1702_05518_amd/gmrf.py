@@ -79,6 +79,11 @@ _SIGS = {
                                C.c_int64, C.c_void_p], C.c_int),
     "gmrf_last_reductions": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                               C.c_void_p], C.c_int),
+    "gmrf_batch_footprint": ([C.POINTER(C.c_void_p), C.c_int32], C.c_size_t),
+    "gmrf_batch_create": ([C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                           C.POINTER(C.c_void_p)], C.c_int),
+    "gmrf_batch_destroy": ([C.c_void_p], C.c_int),
+    "gmrf_batch_sweep": ([C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p], C.c_int),
 }
 
 
@@ -307,3 +312,32 @@ class Chain:
         _check(lib().gmrf_last_reductions(self.handle, C.byref(q), C.byref(s),
                                           _stream_handle(stream)))
         return q.value, s.value
+
+
+class Batch:
+    """Many chains (one precision) advanced together by shared launches; each
+    chain's results equal its standalone sweeps bit for bit."""
+
+    def __init__(self, chains, stream=None):
+        L = lib()
+        self.chains = list(chains)
+        arr = (C.c_void_p * len(self.chains))(*[c.handle.value for c in self.chains])
+        need = L.gmrf_batch_footprint(arr, len(self.chains))
+        if need == 0:
+            raise GmrfError(E_INVALID_ARG, last_error())
+        self.ws = _workspace(need, self.chains[0].graph.device)
+        h = C.c_void_p()
+        _check(L.gmrf_batch_create(arr, len(self.chains), C.c_void_p(self.ws.data_ptr()), need,
+                                   _stream_handle(stream), C.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.gmrf_batch_destroy(h)
+            self.handle = None
+
+    def sweep(self, nsweeps: int = 1, hyper: bool = True, capture: bool = False, stream=None):
+        flags = (WITH_HYPER if hyper else 0) | (CAPTURE if capture else 0)
+        _check(lib().gmrf_batch_sweep(self.handle, int(nsweeps), flags, _stream_handle(stream)))
+        return self
