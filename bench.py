@@ -139,6 +139,118 @@ def probe(torch, gmrf, inputs, steps):
     print(json.dumps({"probe": "copy 512 MiB + sweeps", "sweeps": steps + 5}), flush=True)
 
 
+def bench_batch(torch, gmrf, inputs, args):
+    """The batched workload: 512 independent instances (256 lattices with side
+    U{32..512}, 4 neighbours; 256 Delaunay graphs with n U{1k..50k}, proper CAR
+    rho 0.95), FP32 state with FP64 accumulators, all advanced together by
+    shared launches in a captured graph of sweeps.  Prints one JSON line."""
+    steps = args.steps
+    t0 = time.perf_counter()
+    mix = inputs.batch_mix(512, data_seed=4)
+    log(f"[bench] batch inputs built in {time.perf_counter() - t0:.1f} s")
+    chains, sites = [], 0
+    for i, wl in enumerate(mix):
+        if wl["kind"] == "lattice":
+            g = gmrf.Graph(lattice=(wl["rows"], wl["cols"], wl["stencil"]))
+        else:
+            color, k = gmrf.greedy_coloring(wl["row_ptr"], wl["col"])
+            g = gmrf.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color, num_colors=k,
+                           rho=wl["rho"])
+        chains.append(gmrf.Chain(g, wl["y"], precision=gmrf.FP32_ACC64, seed=1 + i, instance=i))
+        sites += wl["n"]
+    batch = gmrf.Batch(chains)
+    batch.sweep(args.warmup, capture=False)
+    batch.sweep(steps, capture=True)            # record the graph once
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    batch.sweep(steps, capture=True)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t_batch = e0.elapsed_time(e1) / 1e3
+    # the same chains one by one (plain launches), a few sweeps each
+    solo_sweeps = 5
+    torch.cuda.synchronize()
+    e0.record(s)
+    for c in chains:
+        c.sweep(solo_sweeps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t_solo = e0.elapsed_time(e1) / 1e3 / solo_sweeps
+    for c in chains[:: len(chains) // 8]:
+        _, tau, lam, _ = c.get_state()
+        if not (np.isfinite(tau) and np.isfinite(lam)):
+            print("bench.py: non-finite result", file=sys.stderr)
+            sys.exit(1)
+    value = sites * steps / t_batch
+    line = {
+        "metric": "site-updates/s (batched instances)", "value": value,
+        "unit": "site-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": t_batch / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "512 instances: 256 lattices side U{32..512} 4-neighbour, "
+                               "256 Delaunay graphs n U{1k..50k}, FP32 with FP64 accumulators, "
+                               "one captured graph of shared launches per sweep block",
+                   "sites_per_sweep": sites, "instances": len(chains)},
+        "unbatched_site_updates_per_s": sites / t_solo,
+        "batching_speedup": t_solo * steps / t_batch,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(torch, gmrf, inputs, args):
+    """Serving: Poisson arrivals (mean 200 jobs/s for 2 s) of 1000-sweep jobs on
+    Delaunay graphs of the irregular workload's sizes (n = 15,000 with
+    probability 0.98, n = 1,000,000 with probability 0.02, so the offered load
+    stays below capacity), FP32 with FP64 accumulators, continuous batching;
+    against the FP64 plain form (one standalone chain at a time) on the first
+    40 arrivals.  Prints one JSON line."""
+    from paper_1702_05518_amd import serve
+
+    rng = np.random.Generator(np.random.PCG64(7))
+    pool = []
+    for n, ds in [(15000, 11), (15000, 12), (15000, 13), (1_000_000, 14)]:
+        wl = inputs.delaunay_workload(n, data_seed=ds, rho=0.95)
+        color, k = gmrf.greedy_coloring(wl["row_ptr"], wl["col"])
+        pool.append((gmrf.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color,
+                                num_colors=k, rho=0.95), wl["y"]))
+    log("[bench] serve: graph pool ready")
+    t, jobs = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / 200.0)
+        if t > 2.0:
+            break
+        g, y = pool[3] if rng.random() < 0.02 else pool[int(rng.integers(0, 3))]
+        jobs.append(serve.Job(len(jobs), g, y, seed=1000 + len(jobs), instance=len(jobs),
+                              nsweeps=1000, arrival=t, precision=gmrf.FP32_ACC64))
+    free, _ = torch.cuda.mem_get_info()
+    server = serve.Server(budget_bytes=int(0.5 * free), step_sweeps=10, max_active=1024)
+    wall = server.run(jobs, realtime=True)
+    sites = sum(j.sites * j.nsweeps for j in server.finished)
+    served = serve.latency_summary(server.finished)
+    log(f"[bench] serve: {len(jobs)} jobs in {wall:.2f} s, p50 {served['p50_ms']:.1f} ms")
+    plain_jobs = [serve.Job(j.job_id, j.graph, j.y, j.seed, j.instance, j.nsweeps, j.arrival,
+                            gmrf.FP64) for j in jobs[:40]]
+    wall_plain = serve.serve_plain(plain_jobs, precision=gmrf.FP64, realtime=True)
+    plain = serve.latency_summary(plain_jobs)
+    plain_sites = sum(j.sites * j.nsweeps for j in plain_jobs)
+    line = {
+        "metric": "p50/p99 solve latency (served, continuous batching)",
+        "value": sites / wall, "unit": "site-updates/s", "n_gpus": 1, "steps": 1000,
+        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "Poisson arrivals 200/s for 2 s of 1000-sweep jobs, Delaunay "
+                               "n=15k (p 0.98) or 1M (p 0.02), FP32 + FP64 accumulators, "
+                               "continuous batching every 10 sweeps",
+                   "jobs": len(jobs), "batch_rebuilds": server.rebuilds},
+        "served_fp32": served,
+        "plain_fp64_first40": dict(plain, site_updates_per_s=plain_sites / wall_plain),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +259,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--reps", type=int, default=10, help="solves for p50/p99 latency")
+    ap.add_argument("--workload", default="lattice2048", choices=["lattice2048", "batch512", "serve"],
+                    help="lattice2048: the 2048x2048 lattice line (default); batch512: the "
+                         "batched many-instance workload; serve: the serving workload "
+                         "(each a separate JSON line)")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe for rocprofv3 --pmc: a 512 MiB device copy (the "
                          "scale reference for FETCH_SIZE / WRITE_SIZE), then --steps sweeps")
@@ -167,6 +283,12 @@ def main():
     n = ROWS * COLS
     if args.probe:
         probe(torch, gmrf, inputs, args.steps)
+        return
+    if args.workload == "batch512":
+        bench_batch(torch, gmrf, inputs, args)
+        return
+    if args.workload == "serve":
+        bench_serve(torch, gmrf, inputs, args)
         return
     log(f"[bench] building workload {ROWS}x{COLS} stencil {STENCIL}")
     wl = inputs.lattice_workload(ROWS, COLS, STENCIL, noise_sd=0.1, data_seed=1,

@@ -176,3 +176,33 @@ def delaunay_workload(n: int, data_seed: int = 3, rho: float = 0.95, tau_true: f
     y = truth + noise_sd * rng.standard_normal(n)
     return dict(kind="csr", n=n, points=pts, row_ptr=row_ptr, col=col, y=y, truth=truth,
                 rho=rho)
+
+
+def smooth_field(points):
+    """A smooth synthetic truth on the unit square (used where an exact prior
+    draw would be too slow to generate for many graphs)."""
+    u, v = points[:, 0], points[:, 1]
+    return np.sin(2 * np.pi * 1.5 * u) * np.cos(2 * np.pi * v) + 0.5 * u
+
+
+def batch_mix(count: int = 512, data_seed: int = 4, side=(32, 512), nrange=(1000, 50000),
+              noise_lattice: float = 0.1, noise_graph: float = 0.2):
+    """Many independent instances of uneven sizes: the first half lattices with
+    side ~ U{side} (4 neighbours, checkerboard), the second half Delaunay
+    graphs with n ~ U{nrange} (smooth truth plus noise, proper CAR rho 0.95).
+    Returns a list of workload dicts (graphs without colorings)."""
+    rng = np.random.Generator(np.random.PCG64(data_seed))
+    out = []
+    nlat = count // 2
+    for i in range(nlat):
+        s = int(rng.integers(side[0], side[1] + 1))
+        wl = lattice_workload(s, s, 4, noise_sd=noise_lattice,
+                              data_seed=int(rng.integers(1 << 30)), with_csr=False)
+        out.append(wl)
+    for i in range(count - nlat):
+        n = int(rng.integers(nrange[0], nrange[1] + 1))
+        pts, row_ptr, col = delaunay_graph(n, data_seed=int(rng.integers(1 << 30)))
+        truth = smooth_field(pts)
+        y = truth + noise_graph * rng.standard_normal(n)
+        out.append(dict(kind="csr", n=n, row_ptr=row_ptr, col=col, y=y, truth=truth, rho=0.95))
+    return out

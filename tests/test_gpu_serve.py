@@ -1,0 +1,86 @@
+"""Continuous batching: jobs join and leave the shared launches at step
+boundaries, admission respects the memory budget, and every job's posterior
+mean and variance equal a standalone run of the same job bit for bit."""
+import numpy as np
+import pytest
+
+from paper_1702_05518_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1702_05518_amd import gmrf, serve
+
+    gmrf.lib()
+    return gmrf, serve
+
+
+def pool(gmrf):
+    graphs = []
+    wl = inputs.lattice_workload(40, 50, 8, data_seed=2)
+    graphs.append((gmrf.Graph(lattice=(40, 50, 8)), wl["y"]))
+    for n, ds in [(2000, 5), (700, 6)]:
+        wl = inputs.delaunay_workload(n, data_seed=ds, rho=0.95)
+        color, k = gmrf.greedy_coloring(wl["row_ptr"], wl["col"])
+        graphs.append((gmrf.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color,
+                                  num_colors=k, rho=0.95), wl["y"]))
+    return graphs
+
+
+def jobs_for(serve, graphs, prec):
+    out = []
+    for i in range(9):
+        g, y = graphs[i % len(graphs)]
+        out.append(serve.Job(i, g, y, seed=50 + i, instance=i, nsweeps=[20, 40, 30][i % 3],
+                             arrival=0.0, precision=prec))
+    return out
+
+
+@pytest.mark.parametrize("prec_name", ["fp32", "fp64"])
+def test_served_results_equal_standalone(S, prec_name):
+    gmrf, serve = S
+    prec = gmrf.FP32_ACC64 if prec_name == "fp32" else gmrf.FP64
+    graphs = pool(gmrf)
+    jobs = jobs_for(serve, graphs, prec)
+    one = serve.chain_bytes(graphs[0][0], prec)
+    server = serve.Server(budget_bytes=3 * one + 1, step_sweeps=10, max_active=3)
+    server.run(jobs, realtime=False)
+    assert len(server.finished) == len(jobs)
+    assert server.rebuilds > 2            # the mix changed while jobs were running
+    for job in jobs:
+        ch = gmrf.Chain(job.graph, job.y, precision=prec, seed=job.seed, instance=job.instance)
+        ch.sweep(job.nsweeps)
+        mean, var, nacc = ch.posterior_stats()
+        assert nacc == job.nsweeps
+        assert np.array_equal(mean, job.mean) and np.array_equal(var, job.var)
+
+
+def test_admission_respects_budget(S):
+    gmrf, serve = S
+    graphs = pool(gmrf)
+    jobs = jobs_for(serve, graphs, gmrf.FP32_ACC64)
+    budget = max(serve.chain_bytes(g, gmrf.FP32_ACC64) for g, _ in graphs) * 2
+    server = serve.Server(budget_bytes=budget, step_sweeps=10)
+    orig_step = server.step
+    seen = []
+
+    def step(clock):
+        r = orig_step(clock)
+        assert server.used <= budget
+        seen.append(len(server.active))
+        return r
+
+    server.step = step
+    server.run(jobs, realtime=False)
+    assert len(server.finished) == len(jobs)
+    assert max(seen) >= 2                  # several jobs shared the launches
+    with pytest.raises(ValueError):
+        serve.Server(budget_bytes=10).submit(jobs[0])
+    with pytest.raises(ValueError):
+        serve.Server(budget_bytes=budget, step_sweeps=7).submit(jobs[0])
