@@ -55,6 +55,7 @@ class _Problem(C.Structure):
         ("burn_in", C.c_int64),
         ("seed", C.c_uint64),
         ("instance", C.c_uint32),
+        ("intercept", C.c_int32),
     ]
 
 
@@ -70,6 +71,7 @@ class _Chain(C.Structure):
         ("q", C.c_double),
         ("sse", C.c_double),
         ("status", C.c_int32),
+        ("beta0", C.c_double),
     ]
 
 
@@ -189,7 +191,7 @@ class Chain:
 
     def __init__(self, row_ptr, col, color, y, rho=1.0, a_tau=1.0, b_tau=1.0, a_lam=1.0,
                  b_lam=1.0, tau0=1.0, lam0=1.0, burn_in=0, seed=1, instance=0, x0=None,
-                 rank=None):
+                 rank=None, intercept=False, beta0=0.0):
         self.row_ptr, self.col = _csr(row_ptr, col)
         self.n = n = self.row_ptr.size - 1
         self.color = np.ascontiguousarray(color, dtype=np.int32)
@@ -206,9 +208,10 @@ class Chain:
         self._p = _Problem(n, _ptr(self.row_ptr, C.c_int64), _ptr(self.col, C.c_int32),
                            _ptr(self.color, C.c_int32), self.k, float(rho),
                            _ptr(self.y, C.c_double), a_tau, b_tau, a_lam, b_lam, self.rank,
-                           int(burn_in), int(seed), int(instance))
+                           int(burn_in), int(seed), int(instance), 1 if intercept else 0)
         self._s = _Chain(_ptr(self.x, C.c_double), _ptr(self.s1, C.c_double),
-                         _ptr(self.s2, C.c_double), float(tau0), float(lam0), 0, 0, 0.0, 0.0, 0)
+                         _ptr(self.s2, C.c_double), float(tau0), float(lam0), 0, 0, 0.0, 0.0, 0,
+                         float(beta0))
 
     # state ----------------------------------------------------------------
     @property
@@ -239,11 +242,17 @@ class Chain:
     def status(self):
         return self._s.status
 
-    def set_state(self, x, tau, lam, sweep):
+    @property
+    def beta0(self):
+        return self._s.beta0
+
+    def set_state(self, x, tau, lam, sweep, beta0=None):
         self.x[:] = x
         self._s.tau = float(tau)
         self._s.lam = float(lam)
         self._s.sweep = int(sweep)
+        if beta0 is not None:
+            self._s.beta0 = float(beta0)
 
     def set_y(self, y):
         self.y[:] = y

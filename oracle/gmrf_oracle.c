@@ -32,6 +32,12 @@
  *     r = n - (#connected components) for the intrinsic prior, n otherwise.
  *   - Running posterior mean / variance accumulators (Sec. 3.1 posterior
  *     mean images).
+ *   - Optionally the intercept of the Sec. 3.1 image model, y = 1 b0 + x + e
+ *     with a flat prior on b0: the site mean uses y_i - b0, the iteration
+ *     draws b0 | x, lam ~ N(mean(y - x), 1 / (n lam)) before lam and tau
+ *     (the paper's order b0, sigma^2, tau^2, field), lam's sum of squares is
+ *     ||y - 1 b0 - x||^2 with the new b0, and the accumulators collect the
+ *     image b0 + x (the quantity the paper reports).
  *   - The greedy coloring of the paper's supplementary greedy algorithm
  *     (peel maximal independent sets, always taking the smallest remaining
  *     site).
@@ -227,6 +233,7 @@ typedef struct {
     int64_t burn_in;          /* sweeps with index < burn_in are not accumulated */
     uint64_t seed;
     uint32_t instance;
+    int32_t intercept;        /* 1: the image model with intercept b0 */
 } orc_problem;
 
 typedef struct {
@@ -235,8 +242,9 @@ typedef struct {
     double tau, lam;          /* prior precision, noise precision */
     int64_t sweep;            /* number of completed sweeps */
     int64_t n_acc;            /* number of accumulated sweeps */
-    double q, sse;            /* x'(D - rho W)x and ||y - x||^2 after the last sweep */
+    double q, sse;            /* x'(D - rho W)x and ||y - b0 - x||^2 after the last sweep */
     int32_t status;           /* 0 ok, 1 Gamma attempt cap hit or non-finite draw */
+    double beta0;             /* intercept (stays 0 without the intercept) */
 } orc_chain;
 
 #define ORC_WITH_HYPER 1u
@@ -258,8 +266,18 @@ static double orc_pairwise(const double *v, int64_t n)
 
 /* q = x'(D - rho W)x written edge-wise as
  *   (1 - rho) sum_i D_ii x_i^2 + rho sum_{i<j, i~j} (x_i - x_j)^2,
- * and sse = sum_i (y_i - x_i)^2; each as a pairwise sum of per-site terms. */
+ * and sse = sum_i (y_i - b0 - x_i)^2; each as a pairwise sum of per-site
+ * terms. */
+static void orc_quadratic_terms_b0(const orc_problem *p, const double *x, double b0, double *q,
+                                   double *sse);
+
 void orc_quadratic_terms(const orc_problem *p, const double *x, double *q, double *sse)
+{
+    orc_quadratic_terms_b0(p, x, 0.0, q, sse);
+}
+
+static void orc_quadratic_terms_b0(const orc_problem *p, const double *x, double b0, double *q,
+                                   double *sse)
 {
     int64_t n = p->n, i, e;
     double *tq = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
@@ -275,7 +293,7 @@ void orc_quadratic_terms(const orc_problem *p, const double *x, double *q, doubl
             }
         }
         tq[i] = (1.0 - p->rho) * deg * x[i] * x[i] + p->rho * edge;
-        r = p->y[i] - x[i];
+        r = p->y[i] - b0 - x[i];
         ts[i] = r * r;
     }
     *q = orc_pairwise(tq, n);
@@ -290,9 +308,24 @@ int orc_hyper(const orc_problem *p, orc_chain *s)
 {
     uint32_t t = (uint32_t)(s->sweep - 1);
     double tau, lam;
-    int a1 = orc_gamma(p->a_tau + 0.5 * (double)p->rank, p->b_tau + 0.5 * s->q, p->seed, t,
+    int a1, a2;
+    if (p->intercept) {
+        /* b0 | x, lam ~ N(mean(y - x), 1 / (n lam)), then lam's sum of squares
+         * with the new b0 (the x of the last sweep is unchanged) */
+        int64_t i, n = p->n;
+        double *d = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        double mean, z, qq;
+        for (i = 0; i < n; ++i)
+            d[i] = p->y[i] - s->x[i];
+        mean = orc_pairwise(d, n) / (double)n;
+        free(d);
+        z = orc_normal(p->seed, 0u, t, p->instance, 3u);
+        s->beta0 = mean + z / sqrt((double)n * s->lam);
+        orc_quadratic_terms_b0(p, s->x, s->beta0, &qq, &s->sse);
+    }
+    a1 = orc_gamma(p->a_tau + 0.5 * (double)p->rank, p->b_tau + 0.5 * s->q, p->seed, t,
                        p->instance, 1u, ORC_GAMMA_MAX_ATTEMPTS, &tau);
-    int a2 = orc_gamma(p->a_lam + 0.5 * (double)p->n, p->b_lam + 0.5 * s->sse, p->seed, t,
+    a2 = orc_gamma(p->a_lam + 0.5 * (double)p->n, p->b_lam + 0.5 * s->sse, p->seed, t,
                        p->instance, 2u, ORC_GAMMA_MAX_ATTEMPTS, &lam);
     if (a1 < 0 || a2 < 0 || !isfinite(tau) || !isfinite(lam)) {
         s->status = 1;
@@ -313,7 +346,7 @@ static void orc_update_site(const orc_problem *p, orc_chain *s, int64_t i, uint3
         sum += s->x[p->col[e]];
     deg = (double)(p->row_ptr[i + 1] - p->row_ptr[i]);
     Qii = s->tau * deg + s->lam;
-    m = (s->lam * p->y[i] + s->tau * p->rho * sum) / Qii;
+    m = (s->lam * (p->y[i] - s->beta0) + s->tau * p->rho * sum) / Qii;
     z = (flags & ORC_ZERO_NOISE) ? 0.0 : orc_normal(p->seed, (uint32_t)i, t, p->instance, 0u);
     s->x[i] = m + z / sqrt(Qii);
 }
@@ -346,11 +379,12 @@ int orc_sweeps(const orc_problem *p, orc_chain *s, int64_t nsweeps, uint32_t fla
                     orc_update_site(p, s, site, t, flags);
             }
         }
-        orc_quadratic_terms(p, s->x, &s->q, &s->sse);
+        orc_quadratic_terms_b0(p, s->x, s->beta0, &s->q, &s->sse);
         if ((int64_t)t >= p->burn_in) {
             for (i = 0; i < n; ++i) {
-                s->s1[i] += s->x[i];
-                s->s2[i] += s->x[i] * s->x[i];
+                double phi = s->x[i] + s->beta0;   /* the image b0 + x (x without b0) */
+                s->s1[i] += phi;
+                s->s2[i] += phi * phi;
             }
             s->n_acc += 1;
         }

@@ -436,3 +436,65 @@ def test_hyper_after_plain_sweep_equals_fused(orc):
         b.sweeps(1, hyper=False)
         b.hyper()
     assert np.array_equal(a.x, b.x) and a.tau == b.tau and a.lam == b.lam
+
+
+# --------------------------------------------------------------------------
+# the image model with an intercept (Sec. 3.1: y = 1 b0 + x + e, flat prior)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("gi", [0, 1, 4], ids=[IDS[0], IDS[1], IDS[4]])
+def test_intercept_sweep_equals_dense_conditional(orc, gi):
+    name, rp, cl, color = GRAPHS[gi]
+    rp, cl, color = graph_case(orc, name, rp, cl, color)
+    n = rp.size - 1
+    rng = np.random.default_rng(40 + gi)
+    y = rng.normal(size=n) + 3.0
+    x0 = rng.normal(size=n)
+    tau, lam, b0 = 1.3, 0.8, 2.4
+    ch = orc.Chain(rp, cl, color, y, tau0=tau, lam0=lam, seed=5, intercept=True)
+    ch.set_state(x0, tau, lam, sweep=3, beta0=b0)
+    ch.sweeps(1, hyper=False)
+    z = orc.site_normals(5, 3, 0, n)
+    ref = dense_sweep(dense_Qp(rp, cl, tau, lam, 1.0), lam * (y - b0), x0, color, z)
+    assert np.max(np.abs(ch.x - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+    assert ch.beta0 == b0
+
+
+def test_intercept_conditionals(orc):
+    """b0 | x, lam ~ N(mean(y - x), 1/(n lam)); then lam | x, b0 ~
+    Gamma(a + n/2, b + ||y - b0 - x||^2 / 2) with the NEW b0 (probability
+    integral transform, since the rate changes with every b0)."""
+    rp, cl = inputs.lattice_csr(6, 7, 8)
+    color, _ = inputs.lattice_coloring(6, 7, 8)
+    n = 42
+    rng = np.random.default_rng(8)
+    y = rng.normal(size=n) + 5.0
+    x = rng.normal(size=n)
+    tau, lam = 2.0, 3.0
+    ch = orc.Chain(rp, cl, color, y, intercept=True, a_lam=0.5, b_lam=0.25)
+    N = 6000
+    b0s, u = np.empty(N), np.empty(N)
+    for t in range(N):
+        ch.set_state(x, tau, lam, sweep=t + 1, beta0=0.0)
+        ch.hyper()
+        b0s[t] = ch.beta0
+        sse = np.sum((y - ch.beta0 - x) ** 2)
+        u[t] = stats.gamma(0.5 + n / 2, scale=1 / (0.25 + sse / 2)).cdf(ch.lam)
+    assert stats.kstest(b0s, stats.norm(np.mean(y - x), 1 / np.sqrt(n * lam)).cdf).pvalue > 1e-4
+    assert stats.kstest(u, "uniform").pvalue > 1e-4
+
+
+def test_intercept_accumulates_the_image(orc):
+    rp, cl = inputs.lattice_csr(5, 5, 4)
+    color, _ = inputs.lattice_coloring(5, 5, 4)
+    y = np.random.default_rng(2).normal(size=25) + 1.0
+    ch = orc.Chain(rp, cl, color, y, intercept=True, seed=9)
+    imgs = []
+    for _ in range(12):
+        b0 = ch.beta0                   # the intercept the coming sweep uses
+        ch.sweeps(1)
+        imgs.append(ch.x + b0)
+    mean, var = ch.stats()
+    imgs = np.array(imgs)
+    assert np.allclose(mean, imgs.mean(0), rtol=1e-13, atol=1e-14)
+    assert np.allclose(var, imgs.var(0, ddof=1), rtol=1e-9, atol=1e-12)
+    assert ch.beta0 != 0.0
