@@ -3,10 +3,9 @@
  * random field (GMRF) with a conditional autoregressive (CAR) prior on an
  * AMD Instinct MI355X (gfx950).
  *
- * Model (Brown, McMahan & Self 2017, Sec. 3.1 image model without intercept,
- * Sec. 3.2 proper CAR), written with precisions tau (prior) and lam = 1/sigma^2
- * (noise):
- *     y | x, lam  ~ N(x, I / lam)
+ * Model (Brown, McMahan & Self 2017, Sec. 3.1 image model, Sec. 3.2 proper
+ * CAR), written with precisions tau (prior) and lam = 1/sigma^2 (noise):
+ *     y | x, lam  ~ N(beta0 1 + x, I / lam)    beta0 = 0 without an intercept
  *     x | tau     ~ N(0, (tau (D - rho W))^-)   rho = 1: intrinsic CAR (IAR)
  *     tau ~ Gamma(a_tau, rate b_tau),  lam ~ Gamma(a_lam, rate b_lam)
  * W is the 0/1 adjacency of an undirected graph (w_ij = I(i ~ j)) and
@@ -17,18 +16,22 @@
  * its full conditional (Sec. 2.2 with A = I, Sigma = I/lam; Sec. 3.1 local
  * characteristics):
  *     Qii = tau * D_ii + lam
- *     m_i = (lam * y_i + tau * rho * sum_{j~i} x_j) / Qii
+ *     m_i = (lam * (y_i - beta0) + tau * rho * sum_{j~i} x_j) / Qii
  *     x_i = m_i + z_{t,i} / sqrt(Qii)
- * and then, with hyperparameter updates on, tau and lam are redrawn from
- * their conjugate conditionals (Sec. 3.1, as Gamma laws of the precisions):
+ * and then, with hyperparameter updates on, the hyperparameters are redrawn
+ * from their conjugate conditionals (Sec. 3.1, precisions as Gamma laws):
+ *     beta0 ~ N(mean(y - x), 1 / (n lam))       (intercept only; flat prior)
  *     tau ~ Gamma(a_tau + r/2, b_tau + x'(D - rho W)x / 2),
- *     lam ~ Gamma(a_lam + n/2, b_lam + ||y - x||^2 / 2),
+ *     lam ~ Gamma(a_lam + n/2, b_lam + ||y - beta0 1 - x||^2 / 2)  (new beta0),
  * r = n - #connected components (intrinsic) or n (proper).  Sweeps with index
- * t >= burn_in add x and x^2 to FP64 running sums (posterior mean/variance).
+ * t >= burn_in add phi = beta0 + x and phi^2 to FP64 running sums (posterior
+ * mean/variance of the image; with a flat beta0 and an intrinsic prior only
+ * phi is identified).
  *
  * Random numbers: Philox4x32-10 keyed by the 64-bit seed with counter
  * (site id, sweep t, instance, tag); tag 0 = site normal (Box-Muller, cosine
- * branch), tags 1/2 = the tau/lam Gamma draws (Marsaglia-Tsang).  Site ids are
+ * branch), tags 1/2 = the tau/lam Gamma draws (Marsaglia-Tsang), tag 3 (site
+ * id 0) = the beta0 normal.  Site ids are
  * the caller's ORIGINAL ids, so results do not depend on the internal layout,
  * the thread mapping or the color permutation.
  *
@@ -108,6 +111,10 @@ typedef struct {
     double a_lam, b_lam;    /* Gamma(shape, rate) prior of the noise precision lam */
     double tau0, lam0;      /* initial tau, lam (> 0) */
     int64_t burn_in;        /* sweeps t < burn_in are not accumulated */
+    int32_t intercept;      /* 1: y = beta0 1 + x + e with a flat prior on beta0
+                               (Sec. 3.1); 0: no intercept */
+    int32_t reserved;       /* must be 0 */
+    double beta0;           /* initial beta0 (finite; must be 0 when intercept = 0) */
 } gmrf_model;
 
 typedef struct gmrf_graph gmrf_graph;
@@ -170,11 +177,12 @@ int gmrf_chain_create(const gmrf_graph *g, const gmrf_model *m, const double *y,
 int gmrf_chain_destroy(gmrf_chain *c);
 
 /* Enqueue nsweeps sweeps (Algorithm 1 over all colors, with the fused
- * x'(D - rho W)x and ||y - x||^2 reductions and the posterior accumulators).
- * flags: GMRF_WITH_HYPER draws tau and lam after every sweep on the device;
- * without it tau and lam stay fixed.  GMRF_CAPTURE records the nsweeps sweeps
- * as a HIP graph the first time a (nsweeps, flags) pair is seen on this chain
- * and replays it afterwards.  No host synchronisation. */
+ * x'(D - rho W)x and ||y - beta0 1 - x||^2 reductions and the posterior
+ * accumulators).  flags: GMRF_WITH_HYPER draws the hyperparameters after
+ * every sweep on the device; without it they stay fixed.  GMRF_CAPTURE
+ * records the nsweeps sweeps as a HIP graph the first time a (nsweeps, flags)
+ * pair is seen on this chain and replays it afterwards.  No host
+ * synchronisation. */
 int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream);
 
 /* Profiling form of gmrf_sweep (plain launches, no capture): the same sweeps,
@@ -187,8 +195,9 @@ int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t strea
 int gmrf_sweep_timed(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream,
                      double *kernel_ms);
 
-/* Draw tau and lam (Sec. 3.1 conjugate conditionals) from the reductions of
- * the last completed sweep, with that sweep's index in the random counter;
+/* Draw beta0 (with an intercept), tau and lam (Sec. 3.1 conjugate
+ * conditionals) from the reductions of the last completed sweep, with that
+ * sweep's index in the random counter;
  * sweeping without GMRF_WITH_HYPER and then calling this is bitwise the same
  * as sweeping with it.  Asynchronous.  Errors: GMRF_E_INVALID_ARG if no sweep
  * has completed. */
@@ -197,8 +206,8 @@ int gmrf_hyper_update(gmrf_chain *c, hipStream_t stream);
 /* Set tau and lam (> 0, finite).  Asynchronous. */
 int gmrf_set_hyper(gmrf_chain *c, double tau, double lam, hipStream_t stream);
 
-/* Posterior mean S1/N and variance (S2 - S1^2/N)/(N - 1) over the N
- * accumulated sweeps, in original site order, FP64.  With GMRF_PTR_HOST the
+/* Posterior mean S1/N and variance (S2 - S1^2/N)/(N - 1) of phi = beta0 + x
+ * over the N accumulated sweeps, in original site order, FP64.  With GMRF_PTR_HOST the
  * call synchronises and mean / var / n_acc are host pointers (n_acc may be
  * NULL); with GMRF_PTR_DEVICE mean / var are device buffers of n doubles and
  * n_acc must be NULL.  Returns GMRF_E_NUMERIC if a device draw failed. */
@@ -225,8 +234,25 @@ int gmrf_get_accumulators(gmrf_chain *c, double *s1, double *s2, int64_t *n_acc,
 int gmrf_set_accumulators(gmrf_chain *c, const double *s1, const double *s2, int64_t n_acc,
                           hipStream_t stream);
 
+/* Intercept beta0 of the chain (0 without an intercept).  Synchronises. */
+int gmrf_get_intercept(gmrf_chain *c, double *beta0, hipStream_t stream);
+
+/* Set beta0 (finite) of a chain created with an intercept; the stored sse of
+ * the last sweep moves to the new beta0.  Asynchronous. */
+int gmrf_set_intercept(gmrf_chain *c, double beta0, hipStream_t stream);
+
+/* Hyperparameter trace (for autocorrelation diagnostics, Sec. 3.1 ESS / IAT):
+ * d_trace is a device buffer of 3 * capacity doubles that the chain owner
+ * keeps alive; after sweep t (0-based) with t < capacity, row t is set to
+ * (tau, lam, beta0) after that sweep's draws (a later gmrf_hyper_update
+ * rewrites it).  capacity 0 (d_trace may be NULL) turns the trace off.
+ * Drops the chain's captured sweeps; a batch reads the trace setting when it
+ * is created.  Host-only call. */
+int gmrf_set_trace(gmrf_chain *c, double *d_trace, int64_t capacity);
+
 /* Reductions of the last completed sweep: q = x'(D - rho W)x and
- * sse = ||y - x||^2 (FP64).  Synchronises. */
+ * sse = ||y - beta0 1 - x||^2 (FP64; after a draw of beta0, at the new
+ * beta0).  Synchronises. */
 int gmrf_last_reductions(gmrf_chain *c, double *q, double *sse, hipStream_t stream);
 
 /* ---- batches: many chains advanced by shared launches -------------------- */

@@ -50,18 +50,20 @@ const char *error_cstr();
 // ---------------------------------------------------------------------------
 struct DevState {
     double tau, lam;            // current precisions
-    double q, sse;              // reductions of the last completed sweep
+    double q, sse;              // reductions of the last completed sweep (sse at beta0)
     unsigned long long sweep;   // completed sweeps
     long long n_acc;            // accumulated sweeps
     unsigned int status;        // bit 0: Gamma draw failed / non-finite
     unsigned int pad;
+    double beta0;               // intercept (0 without one)
+    double rsum;                // sum_i (y_i - beta0 - x_i) of the last completed sweep
 };
 
 constexpr unsigned kStatusGamma = 1u;
 
 struct SweepArgs {
     DevState *st;
-    double *partials;           // two doubles (q, sse) per block slot
+    double *partials;           // three doubles (q, sse, rsum) per block slot
     double *s1, *s2;            // posterior accumulators (layout of x)
     GammaShape g_tau, g_lam;    // Marsaglia-Tsang constants of a_tau + r/2, a_lam + n/2
     double b_tau, b_lam;
@@ -71,7 +73,13 @@ struct SweepArgs {
     unsigned int instance;
     int with_hyper;
     int total_slots;            // blocks per sweep (all color passes)
+    int intercept;              // 1: draw beta0 before tau / lam
+    double n_sites;
+    double *trace;              // NULL, or (tau, lam, beta0) per completed sweep
+    long long trace_cap;        // rows of trace
 };
+
+constexpr int kPartials = 3;
 
 constexpr int kThreads = 256;   // CSR passes, finish and stats kernels
 
@@ -92,57 +100,103 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Block sum of two values in a fixed tree; the result is valid in thread 0.
-template <int NT> __device__ __forceinline__ void block_sum2(double &a, double &b, double *red)
+// Block sum of three values in a fixed tree; the result is valid in thread 0.
+template <int NT>
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *red)
 {
     constexpr int W = NT / 64;
     a = wave_sum(a);
     b = wave_sum(b);
+    c = wave_sum(c);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) {
         red[wid] = a;
         red[W + wid] = b;
+        red[2 * W + wid] = c;
     }
     lds_barrier();
     if (threadIdx.x == 0) {
         a = red[0];
         b = red[W];
+        c = red[2 * W];
         for (int w = 1; w < W; ++w) {
             a += red[w];
             b += red[W + w];
+            c += red[2 * W + w];
         }
     }
 }
 
-// A sweep block's FP64 partials of q and sse, summed later in slot order.
-template <int NT>
-__device__ __forceinline__ void write_partials(const SweepArgs &a, double q, double sse, int slot)
+// The FP64 sums a sweep block contributes: q = x'(D - rho W)x terms, and the
+// residuals r_i = y_i - beta0 - x_i as sse = sum r_i^2 and rsum = sum r_i.
+struct Red {
+    double q = 0.0, sse = 0.0, rsum = 0.0;
+};
+
+// A sweep block's partials, summed later in slot order.
+template <int NT> __device__ __forceinline__ void write_partials(const SweepArgs &a, Red r, int slot)
 {
-    __shared__ double red[2 * (NT / 64)];
-    block_sum2<NT>(q, sse, red);
+    __shared__ double red[kPartials * (NT / 64)];
+    block_sum3<NT>(r.q, r.sse, r.rsum, red);
     if (threadIdx.x == 0) {
-        a.partials[2 * slot] = q;
-        a.partials[2 * slot + 1] = sse;
+        a.partials[kPartials * slot] = r.q;
+        a.partials[kPartials * slot + 1] = r.sse;
+        a.partials[kPartials * slot + 2] = r.rsum;
     }
 }
 
-// Draw tau (lane 0) and lam (lane 1) after sweep t from the reductions q, sse
-// (Sec. 3.1 conjugate conditionals; precisions, rate form).
-__device__ __forceinline__ void draw_hyper(const SweepArgs &a, unsigned t, double q, double sse,
-                                           int lane)
+// Values of the chain state that the end-of-sweep draws read.
+struct HyperIn {
+    double tau, lam, beta0;
+};
+
+// The draws after sweep t (Sec. 3.1 conjugate conditionals, precisions in
+// rate form), in lanes 0 and 1 of one wavefront; `r` holds the reductions of
+// sweep t, `in` the state the sweep ran with.  With an intercept, first
+//     beta0 ~ N(mean(y - x), 1 / (n lam))      (flat prior on beta0)
+// from the tag-3 normal at counter (0, t); both lanes draw it, and sse and
+// rsum move to the new beta0:  with d = beta0' - beta0,
+//     sum (r_i - d)^2 = sse - 2 d rsum + n d^2,   sum (r_i - d) = rsum - n d.
+// Then tau (lane 0) and lam (lane 1).  Lane 0 stores the reductions and
+// beta0; the trace row t, if any, gets (tau, lam, beta0) after the draws.
+__device__ __forceinline__ void end_of_sweep_draws(const SweepArgs &a, unsigned t, Red r,
+                                                   const HyperIn &in, int lane)
 {
-    if (lane < 2) {
+    double b0 = in.beta0;
+    if (a.with_hyper && a.intercept) {
+        const double z = normal_f64(draw_words(a.seed, 0u, t, a.instance, 3u));
+        const double mean = in.beta0 + r.rsum / a.n_sites;
+        b0 = mean + z / sqrt(a.n_sites * in.lam);
+        const double d = b0 - in.beta0;
+        r.sse = r.sse - 2.0 * d * r.rsum + a.n_sites * d * d;
+        r.rsum = r.rsum - a.n_sites * d;
+    }
+    double v = lane == 0 ? in.tau : in.lam;
+    if (a.with_hyper && lane < 2) {
         const GammaShape g = lane == 0 ? a.g_tau : a.g_lam;
-        const double rate = lane == 0 ? a.b_tau + 0.5 * q : a.b_lam + 0.5 * sse;
-        double v = 0.0;
-        const bool ok = gamma_draw(g, rate, a.seed, t, a.instance, (unsigned)(lane + 1), &v);
-        if (ok && isfinite(v) && v > 0.0) {
+        const double rate = lane == 0 ? a.b_tau + 0.5 * r.q : a.b_lam + 0.5 * r.sse;
+        double draw = 0.0;
+        const bool ok = gamma_draw(g, rate, a.seed, t, a.instance, (unsigned)(lane + 1), &draw);
+        if (ok && isfinite(draw) && draw > 0.0 && isfinite(b0)) {
+            v = draw;
             if (lane == 0)
                 a.st->tau = v;
             else
                 a.st->lam = v;
         } else {
             atomicOr(&a.st->status, kStatusGamma);
+        }
+    }
+    const double other = __shfl(v, 1, 64);   // lam after the draw, from lane 1
+    if (lane == 0) {
+        a.st->q = r.q;
+        a.st->sse = r.sse;
+        a.st->rsum = r.rsum;
+        a.st->beta0 = b0;
+        if (a.trace && (long long)t < a.trace_cap) {
+            a.trace[3 * (size_t)t] = v;
+            a.trace[3 * (size_t)t + 1] = other;
+            a.trace[3 * (size_t)t + 2] = b0;
         }
     }
 }
@@ -154,23 +208,23 @@ constexpr int kFinishThreads = 1024;
 
 __device__ __forceinline__ void finish_sweep_block(const SweepArgs &a)
 {
-    __shared__ double red[2 * (kFinishThreads / 64)];
+    __shared__ double red[kPartials * (kFinishThreads / 64)];
     const unsigned t = (unsigned)a.st->sweep;
-    double tq = 0.0, ts = 0.0;
+    const HyperIn in{a.st->tau, a.st->lam, a.st->beta0};
+    Red r;
     for (int i = threadIdx.x; i < a.total_slots; i += kFinishThreads) {
-        tq += a.partials[2 * i];
-        ts += a.partials[2 * i + 1];
+        r.q += a.partials[kPartials * i];
+        r.sse += a.partials[kPartials * i + 1];
+        r.rsum += a.partials[kPartials * i + 2];
     }
-    block_sum2<kFinishThreads>(tq, ts, red);
+    block_sum3<kFinishThreads>(r.q, r.sse, r.rsum, red);
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
-        tq = __shfl(tq, 0, 64);
-        ts = __shfl(ts, 0, 64);
-        if (a.with_hyper)
-            draw_hyper(a, t, tq, ts, lane);
+        r.q = __shfl(r.q, 0, 64);
+        r.sse = __shfl(r.sse, 0, 64);
+        r.rsum = __shfl(r.rsum, 0, 64);
+        end_of_sweep_draws(a, t, r, in, lane);
         if (lane == 0) {
-            a.st->q = tq;
-            a.st->sse = ts;
             if ((long long)t >= a.burn_in)
                 a.st->n_acc += 1;
             a.st->sweep = (unsigned long long)t + 1ull;
@@ -248,6 +302,8 @@ template <int ST, int J> __host__ __device__ constexpr bool lower_nb(int dr, int
 
 template <typename Real> struct SiteCtx {
     Real tau, lam, tau_rho;
+    Real beta0_r;               // intercept in the state precision
+    double beta0;
     Real inv_q_full, isd_full;  // 1/Qii and Qii^-1/2 of a site with all k neighbours
     double one_minus_rho, rho;
     unsigned t;
@@ -270,10 +326,9 @@ template <int ST_, int TH_, int TW_, int NT_, int CH_> struct LatCfg {
 // One site of Algorithm 1 on the LDS tile: neighbour sum in ascending
 // original-id order, conditional mean and precision, the draw; for interior
 // sites also the q / sse terms.
-template <typename Real, typename Cfg, int J, bool INTERIOR>
+template <typename Real, typename Cfg, int J, bool INTERIOR, bool B0>
 __device__ __forceinline__ void lattice_site(Real *xs, Real yv, int r, int c, int r0, int c0,
-                                             int rows, int cols, const SiteCtx<Real> &sc,
-                                             double &q, double &sse)
+                                             int rows, int cols, const SiteCtx<Real> &sc, Red &rd)
 {
     constexpr int ST = Cfg::ST, H = Cfg::H, LW = Cfg::LW;
     Real *p = xs + (r - r0 + H) * LW + (c - c0 + H);
@@ -301,7 +356,8 @@ __device__ __forceinline__ void lattice_site(Real *xs, Real yv, int r, int c, in
     } else {
         site_scales<Real>(sc.tau, sc.lam, deg, inv_q, isd);
     }
-    const Real xn = site_draw<Real>(yv, s, z, sc.lam, sc.tau_rho, inv_q, isd);
+    const Real yeff = B0 ? yv - sc.beta0_r : yv;
+    const Real xn = site_draw<Real>(yeff, s, z, sc.lam, sc.tau_rho, inv_q, isd);
     *p = xn;
 
     if (r >= r0 && r < r0 + Cfg::TH && c >= c0 && c < c0 + Cfg::TW) {
@@ -321,9 +377,15 @@ __device__ __forceinline__ void lattice_site(Real *xs, Real yv, int r, int c, in
         GMRF_EDGE(dn, 1, 0, LW)
         if (ST == 8) GMRF_EDGE(dn && rt, 1, 1, LW + 1)
 #undef GMRF_EDGE
-        q += sc.one_minus_rho * (double)deg * xd * xd + sc.rho * edge;
-        const double rr = (double)yv - xd;
-        sse += rr * rr;
+        rd.q += sc.one_minus_rho * (double)deg * xd * xd + sc.rho * edge;
+        if constexpr (B0) {
+            const double rr = (double)yv - sc.beta0 - xd;
+            rd.sse += rr * rr;
+            rd.rsum += rr;
+        } else {
+            const double rr = (double)yv - xd;
+            rd.sse += rr * rr;
+        }
     }
 }
 
@@ -341,10 +403,10 @@ __device__ __forceinline__ int div_small(int idx, int d, float rcp, int &rem)
 // Phase J: every color-J site of the tile grown by E = k-1-J rings.  The
 // iteration count per thread has a compile-time bound, so the y loads of all
 // of a thread's sites are issued before the first site is computed.
-template <typename Real, typename Cfg, int J, bool INTERIOR>
+template <typename Real, typename Cfg, int J, bool INTERIOR, bool B0>
 __device__ __forceinline__ void lattice_phase(Real *xs, const Real *__restrict__ y, int r0,
                                               int c0, int rows, int cols, const SiteCtx<Real> &sc,
-                                              double &q, double &sse)
+                                              Red &rd)
 {
     constexpr int E = Cfg::K - 1 - J;
     constexpr int NT = Cfg::NT;
@@ -392,24 +454,24 @@ __device__ __forceinline__ void lattice_phase(Real *xs, const Real *__restrict__
 #pragma unroll
     for (int k = 0; k < NI; ++k)
         if (rr[k] >= 0)
-            lattice_site<Real, Cfg, J, INTERIOR>(xs, yv[k], rr[k], cc[k], r0, c0, rows, cols, sc, q,
-                                                 sse);
+            lattice_site<Real, Cfg, J, INTERIOR, B0>(xs, yv[k], rr[k], cc[k], r0, c0, rows, cols,
+                                                     sc, rd);
 }
 
 // The k color phases of one tile, separated by LDS barriers.
-template <typename Real, typename Cfg, bool INTERIOR>
+template <typename Real, typename Cfg, bool INTERIOR, bool B0>
 __device__ __forceinline__ void lattice_phases(Real *xs, const Real *__restrict__ y, int r0,
                                                int c0, int rows, int cols, const SiteCtx<Real> &sc,
-                                               double &q, double &sse)
+                                               Red &rd)
 {
-    lattice_phase<Real, Cfg, 0, INTERIOR>(xs, y, r0, c0, rows, cols, sc, q, sse);
+    lattice_phase<Real, Cfg, 0, INTERIOR, B0>(xs, y, r0, c0, rows, cols, sc, rd);
     lds_barrier();
-    lattice_phase<Real, Cfg, 1, INTERIOR>(xs, y, r0, c0, rows, cols, sc, q, sse);
+    lattice_phase<Real, Cfg, 1, INTERIOR, B0>(xs, y, r0, c0, rows, cols, sc, rd);
     lds_barrier();
     if constexpr (Cfg::K == 4) {
-        lattice_phase<Real, Cfg, 2, INTERIOR>(xs, y, r0, c0, rows, cols, sc, q, sse);
+        lattice_phase<Real, Cfg, 2, INTERIOR, B0>(xs, y, r0, c0, rows, cols, sc, rd);
         lds_barrier();
-        lattice_phase<Real, Cfg, 3, INTERIOR>(xs, y, r0, c0, rows, cols, sc, q, sse);
+        lattice_phase<Real, Cfg, 3, INTERIOR, B0>(xs, y, r0, c0, rows, cols, sc, rd);
         lds_barrier();
     }
 }
@@ -423,7 +485,9 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     return x * per + min(x, rem) + (b >> 3);
 }
 
-template <typename Real, typename Cfg>
+// B0: the chain has an intercept (compile time, so that chains without one
+// run code with no trace of it).
+template <typename Real, typename Cfg, bool B0>
 __device__ __forceinline__ void lattice_sweep_block(const LatArgs<Real> &la, const SweepArgs &a,
                                                     const int tile)
 {
@@ -441,6 +505,8 @@ __device__ __forceinline__ void lattice_sweep_block(const LatArgs<Real> &la, con
     sc.lam = (Real)lam;
     sc.tau_rho = (Real)(tau * a.rho);
     site_scales<Real>(sc.tau, sc.lam, Cfg::ST, sc.inv_q_full, sc.isd_full);
+    sc.beta0 = B0 ? a.st->beta0 : 0.0;
+    sc.beta0_r = (Real)sc.beta0;
     sc.one_minus_rho = 1.0 - a.rho;
     sc.rho = a.rho;
     sc.t = t;
@@ -476,12 +542,12 @@ __device__ __forceinline__ void lattice_sweep_block(const LatArgs<Real> &la, con
     }
     lds_barrier();
 
-    double q = 0.0, sse = 0.0;
+    Red rd;
     const bool interior = r0 >= H && c0 >= H && r0 + TH + H <= rows && c0 + TW + H <= cols;
     if (interior)
-        lattice_phases<Real, Cfg, true>(xs, la.y, r0, c0, rows, cols, sc, q, sse);
+        lattice_phases<Real, Cfg, true, B0>(xs, la.y, r0, c0, rows, cols, sc, rd);
     else
-        lattice_phases<Real, Cfg, false>(xs, la.y, r0, c0, rows, cols, sc, q, sse);
+        lattice_phases<Real, Cfg, false, B0>(xs, la.y, r0, c0, rows, cols, sc, rd);
 
     // Write the interior back and update the accumulators, CH sites per
     // thread per batch so their loads are in flight together.
@@ -510,20 +576,21 @@ __device__ __forceinline__ void lattice_sweep_block(const LatArgs<Real> &la, con
                 const Real v = xs[(idx / TW + H) * LW + idx % TW + H];
                 dst[g[j]] = v;
                 if (acc) {
-                    const double dv = (double)v;
+                    // the accumulated image is beta0 + x (x alone without an intercept)
+                    const double dv = B0 ? (double)v + sc.beta0 : (double)v;
                     a.s1[g[j]] = o1[j] + dv;
                     a.s2[g[j]] = o2[j] + dv * dv;
                 }
             }
         }
     }
-    write_partials<NT>(a, q, sse, tile);
+    write_partials<NT>(a, rd, tile);
 }
 
-template <typename Real, typename Cfg>
+template <typename Real, typename Cfg, bool B0>
 __global__ __launch_bounds__(Cfg::NT) void lattice_sweep_kernel(LatArgs<Real> la, SweepArgs a)
 {
-    lattice_sweep_block<Real, Cfg>(la, a, xcd_tile((int)blockIdx.x, (int)gridDim.x));
+    lattice_sweep_block<Real, Cfg, B0>(la, a, xcd_tile((int)blockIdx.x, (int)gridDim.x));
 }
 
 // Batched lattice sweep: the tile table lists the tiles of every lattice
@@ -537,13 +604,13 @@ struct LatTile {
     int job, tile;
 };
 
-template <typename Real, typename Cfg>
+template <typename Real, typename Cfg, bool B0>
 __global__ __launch_bounds__(Cfg::NT) void lattice_batch_kernel(const LatJob<Real> *jobs,
                                                                 const LatTile *tiles)
 {
     const LatTile tl = tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
     const LatJob<Real> &j = jobs[tl.job];
-    lattice_sweep_block<Real, Cfg>(j.la, j.a, tl.tile);
+    lattice_sweep_block<Real, Cfg, B0>(j.la, j.a, tl.tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -564,7 +631,7 @@ template <typename Real> struct CsrArgs {
 constexpr int kCsrBatch = 8;
 
 // Sites p0 + threadIdx.x of the color slab [lo, lo + cnt); partial slot `slot`.
-template <typename Real>
+template <typename Real, bool B0>
 __device__ __forceinline__ void csr_pass_block(const CsrArgs<Real> &ca, const SweepArgs &a,
                                                const int lo, const int cnt, const int p0,
                                                const int slot)
@@ -572,8 +639,9 @@ __device__ __forceinline__ void csr_pass_block(const CsrArgs<Real> &ca, const Sw
     const unsigned t = (unsigned)a.st->sweep;
     const double tau_d = a.st->tau, lam_d = a.st->lam;
     const Real tau = (Real)tau_d, lam = (Real)lam_d, tau_rho = (Real)(tau_d * a.rho);
+    const double b0 = B0 ? a.st->beta0 : 0.0;
     const int p = p0 + (int)threadIdx.x;
-    double q = 0.0, sse = 0.0;
+    Red rd;
     if (p < lo + cnt) {
         const int e0 = ca.row_ptr[p], e1 = ca.row_ptr[p + 1];
         const int deg = e1 - e0;
@@ -604,7 +672,8 @@ __device__ __forceinline__ void csr_pass_block(const CsrArgs<Real> &ca, const Sw
         const Real z = site_normal<Real>(w);
         Real inv_q, isd;
         site_scales<Real>(tau, lam, deg, inv_q, isd);
-        const Real xn = site_draw<Real>(yv, s, z, lam, tau_rho, inv_q, isd);
+        const Real yeff = B0 ? yv - (Real)b0 : yv;
+        const Real xn = site_draw<Real>(yeff, s, z, lam, tau_rho, inv_q, isd);
         ca.x[p] = xn;
         const double xd = (double)xn;
         double edge = 0.0;
@@ -621,23 +690,26 @@ __device__ __forceinline__ void csr_pass_block(const CsrArgs<Real> &ca, const Sw
                 edge += d * d;
             }
         }
-        q = (1.0 - a.rho) * (double)deg * xd * xd + a.rho * edge;
-        const double rr = (double)yv - xd;
-        sse = rr * rr;
+        rd.q = (1.0 - a.rho) * (double)deg * xd * xd + a.rho * edge;
+        const double rr = B0 ? (double)yv - b0 - xd : (double)yv - xd;
+        rd.sse = rr * rr;
+        if (B0)
+            rd.rsum = rr;
         if (acc) {
-            a.s1[p] = o1 + xd;
-            a.s2[p] = o2 + xd * xd;
+            const double phi = B0 ? xd + b0 : xd;   // accumulated image beta0 + x
+            a.s1[p] = o1 + phi;
+            a.s2[p] = o2 + phi * phi;
         }
     }
-    write_partials<kThreads>(a, q, sse, slot);
+    write_partials<kThreads>(a, rd, slot);
 }
 
-template <typename Real>
+template <typename Real, bool B0>
 __global__ __launch_bounds__(kThreads) void csr_pass_kernel(CsrArgs<Real> ca, SweepArgs a, int lo,
                                                             int cnt, int slot_base)
 {
-    csr_pass_block<Real>(ca, a, lo, cnt, lo + (int)blockIdx.x * kThreads,
-                         slot_base + (int)blockIdx.x);
+    csr_pass_block<Real, B0>(ca, a, lo, cnt, lo + (int)blockIdx.x * kThreads,
+                             slot_base + (int)blockIdx.x);
 }
 
 // Batched color pass: one entry per block over the color-c slabs of every
@@ -650,28 +722,45 @@ struct CsrBlock {
     int job, lo, cnt, p0, slot;
 };
 
-template <typename Real>
+template <typename Real, bool B0>
 __global__ __launch_bounds__(kThreads) void csr_batch_kernel(const CsrJob<Real> *jobs,
                                                              const CsrBlock *blocks)
 {
     const CsrBlock bk = blocks[blockIdx.x];
     const CsrJob<Real> &j = jobs[bk.job];
-    csr_pass_block<Real>(j.ca, j.a, bk.lo, bk.cnt, bk.p0, bk.slot);
+    csr_pass_block<Real, B0>(j.ca, j.a, bk.lo, bk.cnt, bk.p0, bk.slot);
 }
 
 // ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
+// Redraw after the last completed sweep from its stored reductions (one
+// wavefront); bitwise what the finish kernel draws with hyperparameters on.
 __global__ void hyper_kernel(SweepArgs a)
 {
     const unsigned t = (unsigned)(a.st->sweep - 1ull);
-    draw_hyper(a, t, a.st->q, a.st->sse, (int)threadIdx.x);
+    const HyperIn in{a.st->tau, a.st->lam, a.st->beta0};
+    Red r;
+    r.q = a.st->q;
+    r.sse = a.st->sse;
+    r.rsum = a.st->rsum;
+    end_of_sweep_draws(a, t, r, in, (int)threadIdx.x);
 }
 
 __global__ void set_hyper_kernel(DevState *st, double tau, double lam)
 {
     st->tau = tau;
     st->lam = lam;
+}
+
+// Set the intercept; the stored residual sums move with it so that a redraw
+// from them stays consistent with x.
+__global__ void set_intercept_kernel(DevState *st, double beta0, double n)
+{
+    const double d = beta0 - st->beta0;
+    st->sse = st->sse - 2.0 * d * st->rsum + n * d * d;
+    st->rsum = st->rsum - n * d;
+    st->beta0 = beta0;
 }
 
 // Posterior mean S1/N and variance (S2 - S1^2/N)/(N - 1), un-permuted to the
@@ -719,18 +808,22 @@ struct gmrf_chain {
     hipStream_t capture_stream = nullptr;
     std::map<std::pair<int, unsigned>, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_defs;
+    double *d_trace = nullptr;        // caller's trace buffer (3 doubles per sweep) or NULL
+    int64_t trace_cap = 0;
 };
 
 struct gmrf_batch {
     std::vector<gmrf_chain *> chains;
     gmrf_precision prec = GMRF_FP64;
     // device job tables (inside the batch workspace)
-    void *lat_jobs[2] = {nullptr, nullptr};       // stencil 4, stencil 8
-    LatTile *lat_tiles[2] = {nullptr, nullptr};
-    int lat_tile_count[2] = {0, 0};
-    void *csr_jobs = nullptr;
-    CsrBlock *csr_blocks = nullptr;
-    std::vector<int> csr_color_off;               // per color index: first block
+    // lattice groups w = (stencil 8) + 2 (intercept); general-graph groups g =
+    // intercept.  Each group is its own launch (its kernel is specialised).
+    void *lat_jobs[4] = {};
+    LatTile *lat_tiles[4] = {};
+    int lat_tile_count[4] = {};
+    void *csr_jobs[2] = {};
+    CsrBlock *csr_blocks[2] = {};
+    std::vector<int> csr_color_off[2];            // per color index: first block
     SweepArgs *fin_args = nullptr;
     hipStream_t capture_stream = nullptr;
     std::map<std::pair<int, unsigned>, hipGraphExec_t> graphs;
@@ -802,7 +895,7 @@ size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chai
     char *y = take(rs * n);
     char *s1 = take(8 * n);
     char *s2 = take(8 * n);
-    char *part = take(16 * (size_t)std::max(slots, 1));
+    char *part = take(8 * kPartials * (size_t)std::max(slots, 1));
     char *stats = take(16 * n);
     if (c) {
         c->d_state = reinterpret_cast<DevState *>(st);
@@ -840,6 +933,10 @@ SweepArgs make_args(const gmrf_chain *c, unsigned flags)
     a.instance = c->instance;
     a.with_hyper = (flags & GMRF_WITH_HYPER) ? 1 : 0;
     a.total_slots = c->total_slots;
+    a.intercept = c->model.intercept ? 1 : 0;
+    a.n_sites = (double)c->g->h.n;
+    a.trace = c->d_trace;
+    a.trace_cap = c->trace_cap;
     return a;
 }
 
@@ -875,12 +972,13 @@ void launch_lattice(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipE
 {
     const LatArgs<Real> la = lattice_args<Real>(c);
     using Cfg = LatticeCfg<ST>;
+    auto kern = c->model.intercept ? lattice_sweep_kernel<Real, Cfg, true>
+                                   : lattice_sweep_kernel<Real, Cfg, false>;
     if (ev0 || ev1)
-        hipExtLaunchKernelGGL((lattice_sweep_kernel<Real, Cfg>), dim3(c->total_slots),
-                              dim3(Cfg::NT), 0, s, ev0, ev1, 0, la, a);
+        hipExtLaunchKernelGGL(kern, dim3(c->total_slots), dim3(Cfg::NT), 0, s, ev0, ev1, 0, la,
+                              a);
     else
-        hipLaunchKernelGGL((lattice_sweep_kernel<Real, Cfg>), dim3(c->total_slots),
-                           dim3(Cfg::NT), 0, s, la, a);
+        hipLaunchKernelGGL(kern, dim3(c->total_slots), dim3(Cfg::NT), 0, s, la, a);
 }
 
 // Launch configuration of the small element-wise kernels.
@@ -906,12 +1004,12 @@ void launch_csr(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent
             continue;
         const int lo = h.slab_offsets[col], cnt = h.slab_offsets[col + 1] - lo;
         hipEvent_t e0 = slot == 0 ? ev0 : nullptr, e1 = col == last ? ev1 : nullptr;
+        auto kern = c->model.intercept ? csr_pass_kernel<Real, true> : csr_pass_kernel<Real, false>;
         if (e0 || e1)
-            hipExtLaunchKernelGGL((csr_pass_kernel<Real>), dim3(nb), dim3(kThreads), 0, s, e0, e1,
-                                  0, ca, a, lo, cnt, slot);
+            hipExtLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, s, e0, e1, 0, ca, a, lo, cnt,
+                                  slot);
         else
-            hipLaunchKernelGGL((csr_pass_kernel<Real>), dim3(nb), dim3(kThreads), 0, s, ca, a,
-                               lo, cnt, slot);
+            hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, s, ca, a, lo, cnt, slot);
         slot += nb;
     }
 }
@@ -1030,10 +1128,10 @@ bool finite_array(const double *v, int64_t n)
 // Host image of a batch's job tables and the offsets of its sections.
 struct BatchImage {
     std::vector<char> bytes;
-    size_t off_lat_jobs[2] = {0, 0}, off_lat_tiles[2] = {0, 0};
-    size_t off_csr_jobs = 0, off_csr_blocks = 0, off_fin = 0;
-    int lat_tile_count[2] = {0, 0};
-    std::vector<int> csr_color_off;
+    size_t off_lat_jobs[4] = {}, off_lat_tiles[4] = {};
+    size_t off_csr_jobs[2] = {}, off_csr_blocks[2] = {}, off_fin = 0;
+    int lat_tile_count[4] = {};
+    std::vector<int> csr_color_off[2];
 };
 
 template <typename T> size_t append(std::vector<char> &img, const std::vector<T> &v)
@@ -1048,48 +1146,52 @@ template <typename T> size_t append(std::vector<char> &img, const std::vector<T>
 template <typename Real>
 void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im)
 {
-    std::vector<LatJob<Real>> ljobs[2];
-    std::vector<LatTile> ltiles[2];
-    std::vector<CsrJob<Real>> cjobs;
-    std::vector<std::vector<CsrBlock>> cblocks;   // per color index
+    std::vector<LatJob<Real>> ljobs[4];
+    std::vector<LatTile> ltiles[4];
+    std::vector<CsrJob<Real>> cjobs[2];
+    std::vector<std::vector<CsrBlock>> cblocks[2];   // per color index
     std::vector<SweepArgs> fin;
     for (const gmrf_chain *c : cs) {
         const SweepArgs a = make_args(c, 0u);
         fin.push_back(a);
         const HostGraph &h = c->g->h;
+        const int g = c->model.intercept ? 1 : 0;
         if (is_lattice(c->g)) {
-            const int w = h.stencil == 8 ? 1 : 0;
+            const int w = (h.stencil == 8 ? 1 : 0) + 2 * g;
             const int job = (int)ljobs[w].size();
             ljobs[w].push_back(LatJob<Real>{lattice_args<Real>(c), a});
             for (int t = 0; t < c->total_slots; ++t)
                 ltiles[w].push_back(LatTile{job, t});
         } else {
-            const int job = (int)cjobs.size();
-            cjobs.push_back(CsrJob<Real>{csr_args<Real>(c), a});
-            if ((int)cblocks.size() < h.k)
-                cblocks.resize(h.k);
+            const int job = (int)cjobs[g].size();
+            cjobs[g].push_back(CsrJob<Real>{csr_args<Real>(c), a});
+            if ((int)cblocks[g].size() < h.k)
+                cblocks[g].resize(h.k);
             int slot = 0;
             for (int32_t col = 0; col < h.k; ++col) {
                 const int lo = h.slab_offsets[col], cnt = h.slab_offsets[col + 1] - lo;
                 for (int b = 0; b < c->pass_blocks[col]; ++b)
-                    cblocks[col].push_back(CsrBlock{job, lo, cnt, lo + b * kThreads, slot + b});
+                    cblocks[g][col].push_back(
+                        CsrBlock{job, lo, cnt, lo + b * kThreads, slot + b});
                 slot += c->pass_blocks[col];
             }
         }
     }
-    std::vector<CsrBlock> flat;
-    im.csr_color_off.assign(1, 0);
-    for (const auto &v : cblocks) {
-        flat.insert(flat.end(), v.begin(), v.end());
-        im.csr_color_off.push_back((int)flat.size());
-    }
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < 4; ++w) {
         im.off_lat_jobs[w] = append(im.bytes, ljobs[w]);
         im.off_lat_tiles[w] = append(im.bytes, ltiles[w]);
         im.lat_tile_count[w] = (int)ltiles[w].size();
     }
-    im.off_csr_jobs = append(im.bytes, cjobs);
-    im.off_csr_blocks = append(im.bytes, flat);
+    for (int g = 0; g < 2; ++g) {
+        std::vector<CsrBlock> flat;
+        im.csr_color_off[g].assign(1, 0);
+        for (const auto &v : cblocks[g]) {
+            flat.insert(flat.end(), v.begin(), v.end());
+            im.csr_color_off[g].push_back((int)flat.size());
+        }
+        im.off_csr_jobs[g] = append(im.bytes, cjobs[g]);
+        im.off_csr_blocks[g] = append(im.bytes, flat);
+    }
     im.off_fin = append(im.bytes, fin);
 }
 
@@ -1126,22 +1228,39 @@ int build_image(gmrf_chain *const *chains, int32_t count, BatchImage &im, gmrf_p
     return GMRF_OK;
 }
 
+template <typename Real, int ST, bool B0>
+void launch_lattice_group(const gmrf_batch *b, hipStream_t s)
+{
+    const int w = (ST == 8 ? 1 : 0) + (B0 ? 2 : 0);
+    if (b->lat_tile_count[w] > 0)
+        hipLaunchKernelGGL((lattice_batch_kernel<Real, LatticeCfg<ST>, B0>),
+                           dim3(b->lat_tile_count[w]), dim3(LatticeCfg<ST>::NT), 0, s,
+                           static_cast<const LatJob<Real> *>(b->lat_jobs[w]), b->lat_tiles[w]);
+}
+
+template <typename Real, bool B0> void launch_csr_group(const gmrf_batch *b, size_t col, hipStream_t s)
+{
+    const int g = B0 ? 1 : 0;
+    if (col + 1 >= b->csr_color_off[g].size())
+        return;
+    const int nb = b->csr_color_off[g][col + 1] - b->csr_color_off[g][col];
+    if (nb > 0)
+        hipLaunchKernelGGL((csr_batch_kernel<Real, B0>), dim3(nb), dim3(kThreads), 0, s,
+                           static_cast<const CsrJob<Real> *>(b->csr_jobs[g]),
+                           b->csr_blocks[g] + b->csr_color_off[g][col]);
+}
+
 template <typename Real> void launch_batch_sweep_kernels(const gmrf_batch *b, hipStream_t s)
 {
-    if (b->lat_tile_count[0] > 0)
-        hipLaunchKernelGGL((lattice_batch_kernel<Real, LatticeCfg<4>>), dim3(b->lat_tile_count[0]),
-                           dim3(LatticeCfg<4>::NT), 0, s,
-                           static_cast<const LatJob<Real> *>(b->lat_jobs[0]), b->lat_tiles[0]);
-    if (b->lat_tile_count[1] > 0)
-        hipLaunchKernelGGL((lattice_batch_kernel<Real, LatticeCfg<8>>), dim3(b->lat_tile_count[1]),
-                           dim3(LatticeCfg<8>::NT), 0, s,
-                           static_cast<const LatJob<Real> *>(b->lat_jobs[1]), b->lat_tiles[1]);
-    for (size_t col = 0; col + 1 < b->csr_color_off.size(); ++col) {
-        const int nb = b->csr_color_off[col + 1] - b->csr_color_off[col];
-        if (nb > 0)
-            hipLaunchKernelGGL((csr_batch_kernel<Real>), dim3(nb), dim3(kThreads), 0, s,
-                               static_cast<const CsrJob<Real> *>(b->csr_jobs),
-                               b->csr_blocks + b->csr_color_off[col]);
+    launch_lattice_group<Real, 4, false>(b, s);
+    launch_lattice_group<Real, 8, false>(b, s);
+    launch_lattice_group<Real, 4, true>(b, s);
+    launch_lattice_group<Real, 8, true>(b, s);
+    // color c of every general-graph chain before color c + 1 of any
+    const size_t ncol = std::max(b->csr_color_off[0].size(), b->csr_color_off[1].size());
+    for (size_t col = 0; col + 1 < ncol; ++col) {
+        launch_csr_group<Real, false>(b, col, s);
+        launch_csr_group<Real, true>(b, col, s);
     }
 }
 
@@ -1154,6 +1273,17 @@ void launch_batch_sweep(const gmrf_batch *b, unsigned flags, hipStream_t s)
     hipLaunchKernelGGL(finish_batch_kernel, dim3((unsigned)b->chains.size()),
                        dim3(kFinishThreads), 0, s, b->fin_args,
                        (flags & GMRF_WITH_HYPER) ? 1 : 0);
+}
+
+// Destroy the cached captured sweeps of a chain.
+void drop_graphs(gmrf_chain *c)
+{
+    for (auto &kv : c->graphs)
+        (void)hipGraphExecDestroy(kv.second);
+    for (hipGraph_t gdef : c->graph_defs)
+        (void)hipGraphDestroy(gdef);
+    c->graphs.clear();
+    c->graph_defs.clear();
 }
 
 } // namespace
@@ -1285,6 +1415,10 @@ int gmrf_chain_create(const gmrf_graph *g, const gmrf_model *m, const double *y,
         return fail(GMRF_E_INVALID_ARG, "chain_create: tau0 and lam0 must be finite and > 0");
     if (m->burn_in < 0)
         return fail(GMRF_E_INVALID_ARG, "chain_create: burn_in must be >= 0");
+    if ((m->intercept != 0 && m->intercept != 1) || m->reserved != 0 || !std::isfinite(m->beta0) ||
+        (m->intercept == 0 && m->beta0 != 0.0))
+        return fail(GMRF_E_INVALID_ARG, "chain_create: intercept must be 0 or 1, reserved 0, and "
+                                        "beta0 finite (and 0 without an intercept)");
     if (!finite_array(y, n) || (x0 && !finite_array(x0, n)))
         return fail(GMRF_E_INVALID_ARG, "chain_create: y and x0 must be finite");
     const size_t need = chain_layout(g, p, nullptr, nullptr);
@@ -1308,13 +1442,15 @@ int gmrf_chain_create(const gmrf_graph *g, const gmrf_model *m, const double *y,
     DevState st{};
     st.tau = m->tau0;
     st.lam = m->lam0;
+    st.beta0 = m->beta0;
     hipError_t e = hipMemcpyAsync(c->d_state, &st, sizeof st, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
         e = hipMemsetAsync(c->d_s1, 0, 8 * n, stream);
     if (e == hipSuccess)
         e = hipMemsetAsync(c->d_s2, 0, 8 * n, stream);
     if (e == hipSuccess)
-        e = hipMemsetAsync(c->d_partials, 0, 16 * (size_t)std::max(c->total_slots, 1), stream);
+        e = hipMemsetAsync(c->d_partials, 0, 8 * kPartials * (size_t)std::max(c->total_slots, 1),
+                           stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(stream);
     if (e != hipSuccess)
@@ -1338,10 +1474,7 @@ int gmrf_chain_destroy(gmrf_chain *c)
 {
     if (!c)
         return GMRF_OK;
-    for (auto &kv : c->graphs)
-        (void)hipGraphExecDestroy(kv.second);
-    for (hipGraph_t gdef : c->graph_defs)
-        (void)hipGraphDestroy(gdef);
+    drop_graphs(c);
     if (c->capture_stream)
         (void)hipStreamDestroy(c->capture_stream);
     delete c;
@@ -1583,6 +1716,42 @@ int gmrf_set_accumulators(gmrf_chain *c, const double *s1, const double *s2, int
     return GMRF_OK;
 }
 
+int gmrf_get_intercept(gmrf_chain *c, double *beta0, hipStream_t stream)
+{
+    clear_error();
+    if (!c || !beta0)
+        return fail(GMRF_E_INVALID_ARG, "get_intercept: NULL chain or output");
+    DevState st;
+    int rc = read_state(c, &st, stream);
+    if (rc != GMRF_OK)
+        return rc;
+    *beta0 = st.beta0;
+    return check_status(st);
+}
+
+int gmrf_set_intercept(gmrf_chain *c, double beta0, hipStream_t stream)
+{
+    clear_error();
+    if (!c || !std::isfinite(beta0) || !c->model.intercept)
+        return fail(GMRF_E_INVALID_ARG, "set_intercept: NULL chain, non-finite beta0 or a chain "
+                                        "without an intercept");
+    hipLaunchKernelGGL(set_intercept_kernel, dim3(1), dim3(1), 0, stream, c->d_state, beta0,
+                       (double)c->g->h.n);
+    GMRF_HIP(hipGetLastError());
+    return GMRF_OK;
+}
+
+int gmrf_set_trace(gmrf_chain *c, double *d_trace, int64_t capacity)
+{
+    clear_error();
+    if (!c || capacity < 0 || (capacity > 0 && !d_trace))
+        return fail(GMRF_E_INVALID_ARG, "set_trace: NULL chain, negative capacity or NULL buffer");
+    c->d_trace = capacity > 0 ? d_trace : nullptr;
+    c->trace_cap = capacity > 0 ? capacity : 0;
+    drop_graphs(c);     // captured sweeps carry the old trace pointer
+    return GMRF_OK;
+}
+
 int gmrf_last_reductions(gmrf_chain *c, double *q, double *sse, hipStream_t stream)
 {
     clear_error();
@@ -1630,14 +1799,16 @@ int gmrf_batch_create(gmrf_chain *const *chains, int32_t count, void *d_ws, size
     gmrf_batch *b = new gmrf_batch();
     b->chains.assign(chains, chains + count);
     b->prec = prec;
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < 4; ++w) {
         b->lat_jobs[w] = base + im.off_lat_jobs[w];
         b->lat_tiles[w] = reinterpret_cast<LatTile *>(base + im.off_lat_tiles[w]);
         b->lat_tile_count[w] = im.lat_tile_count[w];
     }
-    b->csr_jobs = base + im.off_csr_jobs;
-    b->csr_blocks = reinterpret_cast<CsrBlock *>(base + im.off_csr_blocks);
-    b->csr_color_off = im.csr_color_off;
+    for (int g = 0; g < 2; ++g) {
+        b->csr_jobs[g] = base + im.off_csr_jobs[g];
+        b->csr_blocks[g] = reinterpret_cast<CsrBlock *>(base + im.off_csr_blocks[g]);
+        b->csr_color_off[g] = im.csr_color_off[g];
+    }
     b->fin_args = reinterpret_cast<SweepArgs *>(base + im.off_fin);
     *out = b;
     return GMRF_OK;

@@ -41,7 +41,8 @@ class GraphDesc(C.Structure):
 class Model(C.Structure):
     _fields_ = [("a_tau", C.c_double), ("b_tau", C.c_double), ("a_lam", C.c_double),
                 ("b_lam", C.c_double), ("tau0", C.c_double), ("lam0", C.c_double),
-                ("burn_in", C.c_int64)]
+                ("burn_in", C.c_int64), ("intercept", C.c_int32), ("reserved", C.c_int32),
+                ("beta0", C.c_double)]
 
 
 _lib = None
@@ -79,6 +80,9 @@ _SIGS = {
                                C.c_int64, C.c_void_p], C.c_int),
     "gmrf_last_reductions": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                               C.c_void_p], C.c_int),
+    "gmrf_get_intercept": ([C.c_void_p, C.POINTER(C.c_double), C.c_void_p], C.c_int),
+    "gmrf_set_intercept": ([C.c_void_p, C.c_double, C.c_void_p], C.c_int),
+    "gmrf_set_trace": ([C.c_void_p, C.c_void_p, C.c_int64], C.c_int),
     "gmrf_batch_footprint": ([C.POINTER(C.c_void_p), C.c_int32], C.c_size_t),
     "gmrf_batch_create": ([C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                            C.POINTER(C.c_void_p)], C.c_int),
@@ -217,16 +221,19 @@ class Graph:
 
 
 class Chain:
-    """One Markov chain (state, accumulators, tau, lam) of a Graph on the device."""
+    """One Markov chain (state, accumulators, tau, lam and, with
+    ``intercept=True``, beta0) of a Graph on the device."""
 
     def __init__(self, graph: Graph, y, *, precision=FP64, seed=1, instance=0, x0=None,
                  a_tau=1.0, b_tau=1.0, a_lam=1.0, b_lam=1.0, tau0=1.0, lam0=1.0, burn_in=0,
-                 stream=None):
+                 intercept=False, beta0=0.0, stream=None):
         L = lib()
         self.graph = graph
         self.n = graph.n
         self.precision = precision
-        self.model = Model(a_tau, b_tau, a_lam, b_lam, tau0, lam0, int(burn_in))
+        self.trace_buf = None
+        self.model = Model(a_tau, b_tau, a_lam, b_lam, tau0, lam0, int(burn_in),
+                           1 if intercept else 0, 0, float(beta0))
         need = L.gmrf_chain_footprint(graph.handle, precision)
         if need == 0:
             raise GmrfError(E_INVALID_ARG, last_error())
@@ -312,6 +319,39 @@ class Chain:
         _check(lib().gmrf_last_reductions(self.handle, C.byref(q), C.byref(s),
                                           _stream_handle(stream)))
         return q.value, s.value
+
+    @property
+    def beta0(self) -> float:
+        b = C.c_double()
+        _check(lib().gmrf_get_intercept(self.handle, C.byref(b), _stream_handle(None)))
+        return b.value
+
+    def set_intercept(self, beta0: float, stream=None):
+        _check(lib().gmrf_set_intercept(self.handle, float(beta0), _stream_handle(stream)))
+
+    def enable_trace(self, capacity: int):
+        """Record (tau, lam, beta0) after every sweep t < capacity into a device
+        buffer (float64 tensor of shape (capacity, 3), read it with trace())."""
+        torch = _torch()
+        self.trace_buf = torch.full((int(capacity), 3), float("nan"), dtype=torch.float64,
+                                    device=self.graph.device)
+        _check(lib().gmrf_set_trace(self.handle, C.c_void_p(self.trace_buf.data_ptr()),
+                                    int(capacity)))
+
+    def disable_trace(self):
+        _check(lib().gmrf_set_trace(self.handle, None, 0))
+        self.trace_buf = None
+
+    def trace(self, stream=None) -> np.ndarray:
+        """The recorded (tau, lam, beta0) rows as a host array (synchronises)."""
+        if self.trace_buf is None:
+            raise RuntimeError("trace: enable_trace() was not called")
+        torch = _torch()
+        if stream is not None:
+            stream.synchronize()
+        else:
+            torch.cuda.current_stream().synchronize()
+        return self.trace_buf.cpu().numpy()
 
 
 class Batch:

@@ -165,6 +165,21 @@ def lattice_workload(rows: int, cols: int, stencil: int, noise_sd: float = 0.1,
     return out
 
 
+def bump_image_workload(p: int, noise_sd: float = 1.0, data_seed: int = 1, stencil: int = 8):
+    """The paper's simulated image (Sec. 3.1): p x p Gaussian-bump truth plus
+    N(0, noise_sd^2) noise (noise_sd 1 for the low-noise case, 50 for the
+    high-noise one), on a lattice of `stencil` neighbours with its parity
+    coloring.  The model fitted to it has an intercept and an intrinsic
+    prior."""
+    color, k = lattice_coloring(p, p, stencil)
+    truth = gaussian_bump_image(p)
+    rng = np.random.Generator(np.random.PCG64(data_seed))
+    y = truth + noise_sd * rng.standard_normal(truth.size)
+    row_ptr, col = lattice_csr(p, p, stencil)
+    return dict(kind="lattice", rows=p, cols=p, stencil=stencil, n=p * p, color=color, k=k,
+                y=y, truth=truth, rho=1.0, row_ptr=row_ptr, col=col)
+
+
 def delaunay_workload(n: int, data_seed: int = 3, rho: float = 0.95, tau_true: float = 2.0,
                       noise_sd: float = 0.2):
     """Irregular-lattice workload: Delaunay adjacency of uniform points, truth
