@@ -81,6 +81,9 @@ typedef enum {
 #define GMRF_WITH_HYPER 1u  /* draw tau, lam after every sweep (normal MCMC mode) */
 #define GMRF_CAPTURE 2u     /* record the nsweeps sweeps once as a HIP graph and replay it */
 
+/* Number of compiled lattice tile shapes (gmrf_chain_set_tile). */
+#define GMRF_NUM_TILES 2
+
 /* gmrf_posterior_stats flags */
 #define GMRF_PTR_HOST 0u    /* mean / var are host pointers; the call synchronises */
 #define GMRF_PTR_DEVICE 1u  /* mean / var are device pointers; asynchronous */
@@ -249,6 +252,31 @@ int gmrf_set_intercept(gmrf_chain *c, double beta0, hipStream_t stream);
  * Drops the chain's captured sweeps; a batch reads the trace setting when it
  * is created.  Host-only call. */
 int gmrf_set_trace(gmrf_chain *c, double *d_trace, int64_t capacity);
+
+/* Lattice tile shape of a chain (Sec. 2.3: the color phases of a lattice
+ * sweep run tile by tile).  Shape 0 is a 64 x 64 tile with 512 threads,
+ * shape 1 a 32 x 32 tile with 256 threads; a new lattice chain starts with
+ * shape 0 if that gives at least 512 tiles, else shape 1.  The shape changes
+ * the grouping, hence the summation order, of the FP64 reductions (results
+ * agree to rounding, not bit for bit, across shapes); the draws of x are
+ * keyed by site and do not depend on it.  gmrf_chain_get_tile reports the
+ * shape (-1 for a general graph, whose passes use 256-thread blocks); any
+ * output pointer may be NULL.  gmrf_chain_set_tile (lattice chains only)
+ * drops the chain's captured sweeps; a batch keeps the shapes its chains had
+ * when it was created.  Host-only calls. */
+int gmrf_chain_get_tile(const gmrf_chain *c, int32_t *tile, int32_t *tile_rows, int32_t *tile_cols,
+                        int32_t *threads);
+int gmrf_chain_set_tile(gmrf_chain *c, int32_t tile);
+
+/* Autotune the tile shape of a lattice chain: time `reps` (1 .. 100000) sweep
+ * kernels of each shape on the chain itself and keep the fastest.  The timed
+ * launches read the current state and write only scratch (the other state
+ * buffer and the partial slots) with accumulation off, so the chain's state,
+ * accumulators and sweep count are unchanged.  us_per_sweep (NULL or
+ * GMRF_NUM_TILES doubles) receives the mean kernel time of each shape in
+ * microseconds, best the chosen shape.  Synchronises the stream. */
+int gmrf_chain_autotune(gmrf_chain *c, int32_t reps, hipStream_t stream, int32_t *best,
+                        double *us_per_sweep);
 
 /* Reductions of the last completed sweep: q = x'(D - rho W)x and
  * sse = ||y - beta0 1 - x||^2 (FP64; after a draw of beta0, at the new

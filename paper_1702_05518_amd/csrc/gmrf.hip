@@ -204,7 +204,7 @@ __device__ __forceinline__ void end_of_sweep_draws(const SweepArgs &a, unsigned 
 // End of a sweep (one block): sum the partials of every block of the sweep
 // in slot order, store q / sse, draw tau / lam, count the accumulated sweep
 // and advance the sweep index.
-constexpr int kFinishThreads = 1024;
+constexpr int kFinishThreads = 256;
 
 __device__ __forceinline__ void finish_sweep_block(const SweepArgs &a)
 {
@@ -802,7 +802,8 @@ struct gmrf_chain {
     double *d_s1 = nullptr, *d_s2 = nullptr;
     double *d_partials = nullptr;
     double *d_stats = nullptr;
-    int total_slots = 0;
+    int total_slots = 0;              // partial slots of one sweep (current tile shape)
+    int lat_tile = 0;                 // lattice tile shape (index into kTiles)
     std::vector<int> pass_blocks;     // CSR: blocks per color pass
     uint64_t host_sweeps = 0;         // sweeps enqueued (host view)
     hipStream_t capture_stream = nullptr;
@@ -816,11 +817,12 @@ struct gmrf_batch {
     std::vector<gmrf_chain *> chains;
     gmrf_precision prec = GMRF_FP64;
     // device job tables (inside the batch workspace)
-    // lattice groups w = (stencil 8) + 2 (intercept); general-graph groups g =
-    // intercept.  Each group is its own launch (its kernel is specialised).
-    void *lat_jobs[4] = {};
-    LatTile *lat_tiles[4] = {};
-    int lat_tile_count[4] = {};
+    // lattice groups w = (stencil 8) + 2 (intercept) + 4 (tile shape); general-
+    // graph groups g = intercept.  Each group is its own launch (its kernel is
+    // specialised).
+    void *lat_jobs[8] = {};
+    LatTile *lat_tiles[8] = {};
+    int lat_tile_count[8] = {};
     void *csr_jobs[2] = {};
     CsrBlock *csr_blocks[2] = {};
     std::vector<int> csr_color_off[2];            // per color index: first block
@@ -832,22 +834,19 @@ struct gmrf_batch {
 
 namespace {
 
-// Lattice tile configuration (tuned on MI355X; see the benchmark notes).
-#ifndef GMRF_LAT_TH
-#define GMRF_LAT_TH 64
-#endif
-#ifndef GMRF_LAT_TW
-#define GMRF_LAT_TW 64
-#endif
-#ifndef GMRF_LAT_NT
-#define GMRF_LAT_NT 512
-#endif
-#ifndef GMRF_LAT_CH
-#define GMRF_LAT_CH 4
-#endif
-
-constexpr int kLatTH = GMRF_LAT_TH, kLatTW = GMRF_LAT_TW;
-template <int ST> using LatticeCfg = LatCfg<ST, kLatTH, kLatTW, GMRF_LAT_NT, GMRF_LAT_CH>;
+// Lattice tile shapes (rows x cols of the tile, threads per block).  Shape 0
+// suits large lattices (fewest recomputed halo sites per interior site);
+// shape 1 suits small and mid-size ones, where more, smaller blocks shorten
+// the per-block chain of dependent phases.  Measured on MI355X, shape 1 is
+// 25-40% faster per sweep up to 1024 x 1024 and shape 0 is faster at
+// 2048 x 2048.
+struct TileShape {
+    int th, tw, nt;
+};
+constexpr TileShape kTiles[GMRF_NUM_TILES] = {{64, 64, 512}, {32, 32, 256}};
+template <int ST, int K>
+using LatticeCfg = LatCfg<ST, kTiles[K].th, kTiles[K].tw, kTiles[K].nt, 4>;
+static_assert(GMRF_NUM_TILES == 2, "tile dispatch below covers two shapes");
 
 #define GMRF_HIP(expr)                                                                    \
     do {                                                                                  \
@@ -860,10 +859,24 @@ bool is_lattice(const gmrf_graph *g) { return g->h.stencil != 0; }
 
 size_t real_size(gmrf_precision p) { return p == GMRF_FP64 ? 8 : 4; }
 
-int lattice_blocks(const HostGraph &h)
+int lattice_blocks(const HostGraph &h, int k)
 {
-    const int tr = (h.rows + kLatTH - 1) / kLatTH, tc = (h.cols + kLatTW - 1) / kLatTW;
+    const int tr = (h.rows + kTiles[k].th - 1) / kTiles[k].th;
+    const int tc = (h.cols + kTiles[k].tw - 1) / kTiles[k].tw;
     return tr * tc;
+}
+
+// Default tile shape: the large tile once it yields enough blocks to cover the
+// chip twice (256 CUs), the small one below that.
+int default_tile(const HostGraph &h) { return lattice_blocks(h, 0) >= 512 ? 0 : 1; }
+
+// Partial slots to reserve: the most any tile shape needs.
+int max_lattice_blocks(const HostGraph &h)
+{
+    int m = 0;
+    for (int k = 0; k < GMRF_NUM_TILES; ++k)
+        m = std::max(m, lattice_blocks(h, k));
+    return m;
 }
 
 // Chain workspace layout; ptrs may be NULL to only compute the size.
@@ -877,10 +890,11 @@ size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chai
         off += align_up(bytes);
         return base ? base + at : nullptr;
     };
-    int slots = 0;
+    int slots = 0, reserve = 0;
     std::vector<int> pass_blocks;
     if (is_lattice(g)) {
-        slots = lattice_blocks(g->h);
+        slots = lattice_blocks(g->h, c ? c->lat_tile : 0);
+        reserve = max_lattice_blocks(g->h);
     } else {
         for (int32_t col = 0; col < g->h.k; ++col) {
             const int cnt = g->h.slab_offsets[col + 1] - g->h.slab_offsets[col];
@@ -888,6 +902,7 @@ size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chai
             pass_blocks.push_back(nb);
             slots += nb;
         }
+        reserve = slots;
     }
     char *st = take(sizeof(DevState));
     char *x0 = take(rs * n);
@@ -895,7 +910,7 @@ size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chai
     char *y = take(rs * n);
     char *s1 = take(8 * n);
     char *s2 = take(8 * n);
-    char *part = take(8 * kPartials * (size_t)std::max(slots, 1));
+    char *part = take(8 * kPartials * (size_t)std::max(reserve, 1));
     char *stats = take(16 * n);
     if (c) {
         c->d_state = reinterpret_cast<DevState *>(st);
@@ -949,7 +964,7 @@ template <typename Real> LatArgs<Real> lattice_args(const gmrf_chain *c)
     la.y = static_cast<const Real *>(c->d_y);
     la.rows = h.rows;
     la.cols = h.cols;
-    la.tiles_c = (h.cols + kLatTW - 1) / kLatTW;
+    la.tiles_c = (h.cols + kTiles[c->lat_tile].tw - 1) / kTiles[c->lat_tile].tw;
     return la;
 }
 
@@ -966,12 +981,12 @@ template <typename Real> CsrArgs<Real> csr_args(const gmrf_chain *c)
 
 // ev0 / ev1 (optional): events the dispatch itself records at the start and
 // the end of the sweep kernel(s), for the profiling entry point.
-template <typename Real, int ST>
-void launch_lattice(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent_t ev0,
-                    hipEvent_t ev1)
+template <typename Real, int ST, int K>
+void launch_lattice_shape(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent_t ev0,
+                          hipEvent_t ev1)
 {
     const LatArgs<Real> la = lattice_args<Real>(c);
-    using Cfg = LatticeCfg<ST>;
+    using Cfg = LatticeCfg<ST, K>;
     auto kern = c->model.intercept ? lattice_sweep_kernel<Real, Cfg, true>
                                    : lattice_sweep_kernel<Real, Cfg, false>;
     if (ev0 || ev1)
@@ -979,6 +994,16 @@ void launch_lattice(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipE
                               a);
     else
         hipLaunchKernelGGL(kern, dim3(c->total_slots), dim3(Cfg::NT), 0, s, la, a);
+}
+
+template <typename Real, int ST>
+void launch_lattice(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent_t ev0,
+                    hipEvent_t ev1)
+{
+    if (c->lat_tile == 0)
+        launch_lattice_shape<Real, ST, 0>(c, a, s, ev0, ev1);
+    else
+        launch_lattice_shape<Real, ST, 1>(c, a, s, ev0, ev1);
 }
 
 // Launch configuration of the small element-wise kernels.
@@ -1128,9 +1153,9 @@ bool finite_array(const double *v, int64_t n)
 // Host image of a batch's job tables and the offsets of its sections.
 struct BatchImage {
     std::vector<char> bytes;
-    size_t off_lat_jobs[4] = {}, off_lat_tiles[4] = {};
+    size_t off_lat_jobs[8] = {}, off_lat_tiles[8] = {};
     size_t off_csr_jobs[2] = {}, off_csr_blocks[2] = {}, off_fin = 0;
-    int lat_tile_count[4] = {};
+    int lat_tile_count[8] = {};
     std::vector<int> csr_color_off[2];
 };
 
@@ -1146,8 +1171,8 @@ template <typename T> size_t append(std::vector<char> &img, const std::vector<T>
 template <typename Real>
 void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im)
 {
-    std::vector<LatJob<Real>> ljobs[4];
-    std::vector<LatTile> ltiles[4];
+    std::vector<LatJob<Real>> ljobs[8];
+    std::vector<LatTile> ltiles[8];
     std::vector<CsrJob<Real>> cjobs[2];
     std::vector<std::vector<CsrBlock>> cblocks[2];   // per color index
     std::vector<SweepArgs> fin;
@@ -1157,7 +1182,7 @@ void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im)
         const HostGraph &h = c->g->h;
         const int g = c->model.intercept ? 1 : 0;
         if (is_lattice(c->g)) {
-            const int w = (h.stencil == 8 ? 1 : 0) + 2 * g;
+            const int w = (h.stencil == 8 ? 1 : 0) + 2 * g + 4 * c->lat_tile;
             const int job = (int)ljobs[w].size();
             ljobs[w].push_back(LatJob<Real>{lattice_args<Real>(c), a});
             for (int t = 0; t < c->total_slots; ++t)
@@ -1177,7 +1202,7 @@ void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im)
             }
         }
     }
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < 8; ++w) {
         im.off_lat_jobs[w] = append(im.bytes, ljobs[w]);
         im.off_lat_tiles[w] = append(im.bytes, ltiles[w]);
         im.lat_tile_count[w] = (int)ltiles[w].size();
@@ -1228,13 +1253,14 @@ int build_image(gmrf_chain *const *chains, int32_t count, BatchImage &im, gmrf_p
     return GMRF_OK;
 }
 
-template <typename Real, int ST, bool B0>
+template <typename Real, int ST, bool B0, int K>
 void launch_lattice_group(const gmrf_batch *b, hipStream_t s)
 {
-    const int w = (ST == 8 ? 1 : 0) + (B0 ? 2 : 0);
+    const int w = (ST == 8 ? 1 : 0) + (B0 ? 2 : 0) + 4 * K;
+    using Cfg = LatticeCfg<ST, K>;
     if (b->lat_tile_count[w] > 0)
-        hipLaunchKernelGGL((lattice_batch_kernel<Real, LatticeCfg<ST>, B0>),
-                           dim3(b->lat_tile_count[w]), dim3(LatticeCfg<ST>::NT), 0, s,
+        hipLaunchKernelGGL((lattice_batch_kernel<Real, Cfg, B0>), dim3(b->lat_tile_count[w]),
+                           dim3(Cfg::NT), 0, s,
                            static_cast<const LatJob<Real> *>(b->lat_jobs[w]), b->lat_tiles[w]);
 }
 
@@ -1252,10 +1278,14 @@ template <typename Real, bool B0> void launch_csr_group(const gmrf_batch *b, siz
 
 template <typename Real> void launch_batch_sweep_kernels(const gmrf_batch *b, hipStream_t s)
 {
-    launch_lattice_group<Real, 4, false>(b, s);
-    launch_lattice_group<Real, 8, false>(b, s);
-    launch_lattice_group<Real, 4, true>(b, s);
-    launch_lattice_group<Real, 8, true>(b, s);
+    launch_lattice_group<Real, 4, false, 0>(b, s);
+    launch_lattice_group<Real, 8, false, 0>(b, s);
+    launch_lattice_group<Real, 4, true, 0>(b, s);
+    launch_lattice_group<Real, 8, true, 0>(b, s);
+    launch_lattice_group<Real, 4, false, 1>(b, s);
+    launch_lattice_group<Real, 8, false, 1>(b, s);
+    launch_lattice_group<Real, 4, true, 1>(b, s);
+    launch_lattice_group<Real, 8, true, 1>(b, s);
     // color c of every general-graph chain before color c + 1 of any
     const size_t ncol = std::max(b->csr_color_off[0].size(), b->csr_color_off[1].size());
     for (size_t col = 0; col + 1 < ncol; ++col) {
@@ -1433,6 +1463,7 @@ int gmrf_chain_create(const gmrf_graph *g, const gmrf_model *m, const double *y,
     c->seed = seed;
     c->instance = instance;
     c->rank = rank;
+    c->lat_tile = is_lattice(g) ? default_tile(g->h) : 0;
     chain_layout(g, p, static_cast<char *>(d_ws), c);
 
     auto cleanup = [&](int rc) {
@@ -1449,7 +1480,11 @@ int gmrf_chain_create(const gmrf_graph *g, const gmrf_model *m, const double *y,
     if (e == hipSuccess)
         e = hipMemsetAsync(c->d_s2, 0, 8 * n, stream);
     if (e == hipSuccess)
-        e = hipMemsetAsync(c->d_partials, 0, 8 * kPartials * (size_t)std::max(c->total_slots, 1),
+        e = hipMemsetAsync(c->d_partials, 0,
+                           8 * kPartials *
+                               (size_t)std::max(is_lattice(g) ? max_lattice_blocks(g->h)
+                                                              : c->total_slots,
+                                                1),
                            stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(stream);
@@ -1752,6 +1787,95 @@ int gmrf_set_trace(gmrf_chain *c, double *d_trace, int64_t capacity)
     return GMRF_OK;
 }
 
+int gmrf_chain_get_tile(const gmrf_chain *c, int32_t *tile, int32_t *tile_rows, int32_t *tile_cols,
+                        int32_t *threads)
+{
+    clear_error();
+    if (!c)
+        return fail(GMRF_E_INVALID_ARG, "chain_get_tile: NULL chain");
+    if (!is_lattice(c->g)) {
+        if (tile) *tile = -1;
+        if (tile_rows) *tile_rows = 0;
+        if (tile_cols) *tile_cols = 0;
+        if (threads) *threads = kThreads;
+        return GMRF_OK;
+    }
+    const TileShape &t = kTiles[c->lat_tile];
+    if (tile) *tile = c->lat_tile;
+    if (tile_rows) *tile_rows = t.th;
+    if (tile_cols) *tile_cols = t.tw;
+    if (threads) *threads = t.nt;
+    return GMRF_OK;
+}
+
+int gmrf_chain_set_tile(gmrf_chain *c, int32_t tile)
+{
+    clear_error();
+    if (!c || !is_lattice(c->g) || tile < 0 || tile >= GMRF_NUM_TILES)
+        return fail(GMRF_E_INVALID_ARG, "chain_set_tile: NULL or general-graph chain, or tile "
+                                        "not in 0 .. GMRF_NUM_TILES - 1");
+    if (tile != c->lat_tile) {
+        c->lat_tile = tile;
+        c->total_slots = lattice_blocks(c->g->h, tile);
+        drop_graphs(c);     // captured sweeps carry the old launch shape
+    }
+    return GMRF_OK;
+}
+
+int gmrf_chain_autotune(gmrf_chain *c, int32_t reps, hipStream_t stream, int32_t *best,
+                        double *us_per_sweep)
+{
+    clear_error();
+    if (!c || !is_lattice(c->g) || reps < 1 || reps > 100000)
+        return fail(GMRF_E_INVALID_ARG, "chain_autotune: NULL or general-graph chain, or reps "
+                                        "not in 1 .. 100000");
+    const int keep = c->lat_tile;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    GMRF_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    double t[GMRF_NUM_TILES];
+    int win = keep;
+    for (int k = 0; k < GMRF_NUM_TILES && he == hipSuccess; ++k) {
+        c->lat_tile = k;
+        c->total_slots = lattice_blocks(c->g->h, k);
+        // The sweep kernel alone reads the current state and writes only the
+        // other state buffer and the partial slots (both scratch until the
+        // next sweep); with accumulation off it leaves the chain unchanged.
+        SweepArgs a = make_args(c, 0u);
+        a.burn_in = (long long)(~0ull >> 1);
+        for (int i = 0; i < 2; ++i)
+            launch_sweep_kernels(c, a, stream);
+        he = hipEventRecord(e0, stream);
+        for (int i = 0; i < reps && he == hipSuccess; ++i)
+            launch_sweep_kernels(c, a, stream);
+        if (he == hipSuccess)
+            he = hipEventRecord(e1, stream);
+        if (he == hipSuccess)
+            he = hipGetLastError();
+        if (he == hipSuccess)
+            he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (he == hipSuccess)
+            he = hipEventElapsedTime(&ms, e0, e1);
+        t[k] = 1e3 * (double)ms / reps;
+        if (he == hipSuccess && (k == 0 || t[k] < t[win]))
+            win = k;
+    }
+    (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    c->lat_tile = keep;
+    c->total_slots = lattice_blocks(c->g->h, keep);
+    if (he != hipSuccess)
+        return fail(GMRF_E_DEVICE, std::string("chain_autotune: ") + hipGetErrorString(he));
+    if (us_per_sweep)
+        for (int k = 0; k < GMRF_NUM_TILES; ++k)
+            us_per_sweep[k] = t[k];
+    if (best)
+        *best = win;
+    return gmrf_chain_set_tile(c, win);
+}
+
 int gmrf_last_reductions(gmrf_chain *c, double *q, double *sse, hipStream_t stream)
 {
     clear_error();
@@ -1799,7 +1923,7 @@ int gmrf_batch_create(gmrf_chain *const *chains, int32_t count, void *d_ws, size
     gmrf_batch *b = new gmrf_batch();
     b->chains.assign(chains, chains + count);
     b->prec = prec;
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < 8; ++w) {
         b->lat_jobs[w] = base + im.off_lat_jobs[w];
         b->lat_tiles[w] = reinterpret_cast<LatTile *>(base + im.off_lat_tiles[w]);
         b->lat_tile_count[w] = im.lat_tile_count[w];

@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "GMRF_OK", 1: "GMRF_E_INVALID_ARG", 2: "GMRF_E_GRAPH",
                 6: "GMRF_E_NUMERIC"}
 FP64, FP32_ACC64 = 0, 1
 WITH_HYPER, CAPTURE = 1, 2
+NUM_TILES = 2
 PTR_HOST, PTR_DEVICE = 0, 1
 
 
@@ -83,6 +84,11 @@ _SIGS = {
     "gmrf_get_intercept": ([C.c_void_p, C.POINTER(C.c_double), C.c_void_p], C.c_int),
     "gmrf_set_intercept": ([C.c_void_p, C.c_double, C.c_void_p], C.c_int),
     "gmrf_set_trace": ([C.c_void_p, C.c_void_p, C.c_int64], C.c_int),
+    "gmrf_chain_get_tile": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                             C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+    "gmrf_chain_set_tile": ([C.c_void_p, C.c_int32], C.c_int),
+    "gmrf_chain_autotune": ([C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int32),
+                             C.POINTER(C.c_double)], C.c_int),
     "gmrf_batch_footprint": ([C.POINTER(C.c_void_p), C.c_int32], C.c_size_t),
     "gmrf_batch_create": ([C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                            C.POINTER(C.c_void_p)], C.c_int),
@@ -319,6 +325,26 @@ class Chain:
         _check(lib().gmrf_last_reductions(self.handle, C.byref(q), C.byref(s),
                                           _stream_handle(stream)))
         return q.value, s.value
+
+    @property
+    def tile(self):
+        """(shape index, tile rows, tile cols, threads); index -1 for a general graph."""
+        k, r, c, t = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().gmrf_chain_get_tile(self.handle, C.byref(k), C.byref(r), C.byref(c),
+                                         C.byref(t)))
+        return k.value, r.value, c.value, t.value
+
+    def set_tile(self, shape: int):
+        _check(lib().gmrf_chain_set_tile(self.handle, int(shape)))
+
+    def autotune(self, reps: int = 50, stream=None):
+        """Time each tile shape on this chain (state unchanged), keep the
+        fastest; returns (best shape, [us per sweep of each shape])."""
+        best = C.c_int32()
+        us = (C.c_double * NUM_TILES)()
+        _check(lib().gmrf_chain_autotune(self.handle, int(reps), _stream_handle(stream),
+                                         C.byref(best), us))
+        return best.value, list(us)
 
     @property
     def beta0(self) -> float:

@@ -66,12 +66,14 @@ LATTICES = [(64, 64, 4), (64, 64, 8), (150, 133, 4), (150, 133, 8), (1, 1, 8), (
             (77, 1, 8), (2, 3, 8), (129, 65, 8)]
 
 
+@pytest.mark.parametrize("shape", [0, 1])
 @pytest.mark.parametrize("rows,cols,st", LATTICES)
-def test_lattice_one_sweep_from_injected_state(G, orc, rows, cols, st):
+def test_lattice_one_sweep_from_injected_state(G, orc, rows, cols, st, shape):
     wl = lattice_case(rows, cols, st)
     n = rows * cols
     x0 = np.random.default_rng(n).normal(size=n) * 0.3 + 0.5
     g, ch, oc = pair(G, orc, wl, seed=7, instance=2)
+    ch.set_tile(shape)
     ch.set_state(x0, 1.7, 60.0, 5)
     oc.set_state(x0, 1.7, 60.0, 5)
     ch.sweep(1, hyper=True)

@@ -1,0 +1,113 @@
+"""Lattice tile shapes and their autotuner (through the C ABI).
+
+Both shapes must reproduce the CPU oracle (FP64 within 1e-12 relative over
+many sweeps: the shapes differ only in how the FP64 reductions are grouped),
+the autotuner must leave the chain's state untouched, and a batch that mixes
+shapes must equal standalone sweeps bit for bit.
+"""
+import numpy as np
+import pytest
+
+from paper_1702_05518_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+RTOL64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1702_05518_amd import gmrf
+
+    gmrf.lib()
+    return gmrf
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def test_default_shapes(G):
+    big = G.Chain(G.Graph(lattice=(2048, 2048, 8)), np.zeros(2048 * 2048),
+                  precision=G.FP32_ACC64)
+    small = G.Chain(G.Graph(lattice=(200, 300, 4)), np.zeros(60000))
+    assert big.tile == (0, 64, 64, 512)
+    assert small.tile == (1, 32, 32, 256)
+    wl = inputs.delaunay_workload(500, data_seed=2)
+    color, k = G.greedy_coloring(wl["row_ptr"], wl["col"])
+    csr = G.Chain(G.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color, num_colors=k,
+                          rho=0.95), wl["y"])
+    assert csr.tile[0] == -1
+    with pytest.raises(G.GmrfError):
+        csr.set_tile(0)
+    with pytest.raises(G.GmrfError):
+        small.set_tile(2)
+    with pytest.raises(G.GmrfError):
+        csr.autotune()
+
+
+@pytest.mark.parametrize("shape", [0, 1])
+@pytest.mark.parametrize("rows,cols,st", [(200, 131, 8), (97, 160, 4)])
+def test_shape_trajectory_matches_oracle(G, orc, rows, cols, st, shape):
+    wl = inputs.lattice_workload(rows, cols, st)
+    ch = G.Chain(G.Graph(lattice=(rows, cols, st)), wl["y"], seed=4, burn_in=20)
+    ch.set_tile(shape)
+    oc = orc.Chain(wl["row_ptr"], wl["col"], wl["color"], wl["y"], seed=4, burn_in=20)
+    ch.sweep(100, capture=True)
+    oc.sweeps(100)
+    x, tau, lam, sw = ch.get_state()
+    assert sw == 100
+    assert rel(x, oc.x) <= RTOL64 and rel(tau, oc.tau) <= RTOL64 and rel(lam, oc.lam) <= RTOL64
+    m, v, nacc = ch.posterior_stats()
+    om, ov = oc.stats()
+    assert nacc == 80 and rel(m, om) <= RTOL64 and rel(v, ov) <= 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_autotune_leaves_state_unchanged(G, prec):
+    p = G.FP64 if prec == "fp64" else G.FP32_ACC64
+    wl = inputs.lattice_workload(300, 257, 8)
+    g = G.Graph(lattice=(300, 257, 8))
+    a = G.Chain(g, wl["y"], precision=p, seed=6)
+    b = G.Chain(g, wl["y"], precision=p, seed=6)
+    for ch in (a, b):
+        ch.sweep(7)
+    before = a.get_state(), a.get_accumulators(), a.last_reductions()
+    best, us = a.autotune(reps=5)
+    after = a.get_state(), a.get_accumulators(), a.last_reductions()
+    assert best in (0, 1) and len(us) == 2 and all(u > 0 for u in us)
+    assert a.tile[0] == best
+    assert np.array_equal(before[0][0], after[0][0]) and before[0][1:] == after[0][1:]
+    assert np.array_equal(before[1][0], after[1][0]) and np.array_equal(before[1][1], after[1][1])
+    assert before[1][2] == after[1][2] and before[2] == after[2]
+    # the chain continues exactly as an untuned one on the same shape
+    b.set_tile(best)
+    a.sweep(5)
+    b.sweep(5)
+    assert np.array_equal(a.get_state()[0], b.get_state()[0])
+
+
+def test_batch_with_mixed_shapes_is_bitwise_standalone(G):
+    wls = [inputs.lattice_workload(s, s + 9, st, data_seed=s)
+           for s, st in ((70, 4), (130, 8), (45, 8), (260, 4))]
+    def make():
+        out = []
+        for i, wl in enumerate(wls):
+            ch = G.Chain(G.Graph(lattice=(wl["rows"], wl["cols"], wl["stencil"])), wl["y"],
+                         precision=G.FP32_ACC64, seed=20 + i)
+            ch.set_tile(i % 2)
+            out.append(ch)
+        return out
+    alone, batched = make(), make()
+    for ch in alone:
+        ch.sweep(25)
+    G.Batch(batched).sweep(25, capture=True)
+    for a, b in zip(alone, batched):
+        xa, ta, la, _ = a.get_state()
+        xb, tb, lb, _ = b.get_state()
+        assert np.array_equal(xa, xb) and ta == tb and la == lb
