@@ -24,6 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 WITH_HYPER = 1
 ZERO_NOISE = 2
 GAMMA_MAX_ATTEMPTS = 64
+GAUSSIAN, BINOMIAL = 0, 1
 
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
           "-std=c99", "-Wall"]
@@ -56,6 +57,9 @@ class _Problem(C.Structure):
         ("seed", C.c_uint64),
         ("instance", C.c_uint32),
         ("intercept", C.c_int32),
+        ("likelihood", C.c_int32),
+        ("trials", C.POINTER(C.c_int32)),
+        ("beta0_var", C.c_double),
     ]
 
 
@@ -72,6 +76,8 @@ class _Chain(C.Structure):
         ("sse", C.c_double),
         ("status", C.c_int32),
         ("beta0", C.c_double),
+        ("psi", C.POINTER(C.c_double)),
+        ("rsum", C.c_double),
     ]
 
 
@@ -93,6 +99,10 @@ def lib():
         L.orc_normal.restype = dbl
         L.orc_gamma.argtypes = [dbl, dbl, u64, u32, u32, u32, C.c_int, C.POINTER(dbl)]
         L.orc_gamma.restype = C.c_int
+        L.orc_pg1.argtypes = [dbl, u64, u32, u32, u32, u32, C.POINTER(dbl)]
+        L.orc_pg1.restype = C.c_int
+        L.orc_pg.argtypes = [i32, dbl, u64, u32, u32, u32, C.POINTER(dbl)]
+        L.orc_pg.restype = C.c_int
         L.orc_greedy_coloring.argtypes = [i64, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32)]
         L.orc_greedy_coloring.restype = i32
         L.orc_components.argtypes = [i64, C.POINTER(i64), C.POINTER(i32)]
@@ -152,6 +162,22 @@ def gamma(shape: float, rate: float, seed: int, sweep: int, instance: int, tag: 
     return (out.value if a > 0 else float("nan")), a
 
 
+def pg1(c: float, seed: int, site: int, sweep: int, instance: int, j: int) -> float:
+    """PG(1, c) draw from the uniform stream of term j of (site, sweep)."""
+    out = C.c_double(0.0)
+    if lib().orc_pg1(float(c), seed, site, sweep, instance, j, C.byref(out)):
+        raise FloatingPointError("pg1: uniform stream exhausted")
+    return out.value
+
+
+def pg(b: int, c: float, seed: int, site: int, sweep: int, instance: int) -> float:
+    """PG(b, c) for integer b: the sum of the PG(1, c) terms j = 0 .. b-1."""
+    out = C.c_double(0.0)
+    if lib().orc_pg(int(b), float(c), seed, site, sweep, instance, C.byref(out)):
+        raise FloatingPointError("pg: uniform stream exhausted")
+    return out.value
+
+
 # --------------------------------------------------------------------------
 # Graph utilities
 # --------------------------------------------------------------------------
@@ -191,7 +217,11 @@ class Chain:
 
     def __init__(self, row_ptr, col, color, y, rho=1.0, a_tau=1.0, b_tau=1.0, a_lam=1.0,
                  b_lam=1.0, tau0=1.0, lam0=1.0, burn_in=0, seed=1, instance=0, x0=None,
-                 rank=None, intercept=False, beta0=0.0):
+                 rank=None, intercept=False, beta0=0.0, trials=None, beta0_var=0.0):
+        """With ``trials`` (m_i, integers >= 0) the chain samples the binomial
+        logit model: y holds the successes Y_i, the Polya-Gamma psi_i of the
+        last sweep are in ``psi``, and beta0_var is the prior variance of b0
+        (0 = flat)."""
         self.row_ptr, self.col = _csr(row_ptr, col)
         self.n = n = self.row_ptr.size - 1
         self.color = np.ascontiguousarray(color, dtype=np.int32)
@@ -205,13 +235,21 @@ class Chain:
         self.x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
         self.s1 = np.zeros(n)
         self.s2 = np.zeros(n)
+        self.psi = np.zeros(max(n, 1))
+        binom = trials is not None
+        self.trials = (np.ascontiguousarray(trials, dtype=np.int32) if binom
+                       else np.zeros(1, dtype=np.int32))
+        if binom and self.trials.size != n:
+            raise ValueError("trials must have n entries")
         self._p = _Problem(n, _ptr(self.row_ptr, C.c_int64), _ptr(self.col, C.c_int32),
                            _ptr(self.color, C.c_int32), self.k, float(rho),
                            _ptr(self.y, C.c_double), a_tau, b_tau, a_lam, b_lam, self.rank,
-                           int(burn_in), int(seed), int(instance), 1 if intercept else 0)
+                           int(burn_in), int(seed), int(instance), 1 if intercept else 0,
+                           BINOMIAL if binom else GAUSSIAN, _ptr(self.trials, C.c_int32),
+                           float(beta0_var))
         self._s = _Chain(_ptr(self.x, C.c_double), _ptr(self.s1, C.c_double),
                          _ptr(self.s2, C.c_double), float(tau0), float(lam0), 0, 0, 0.0, 0.0, 0,
-                         float(beta0))
+                         float(beta0), _ptr(self.psi, C.c_double), 0.0)
 
     # state ----------------------------------------------------------------
     @property
@@ -245,6 +283,10 @@ class Chain:
     @property
     def beta0(self):
         return self._s.beta0
+
+    @property
+    def rsum(self):
+        return self._s.rsum
 
     def set_state(self, x, tau, lam, sweep, beta0=None):
         self.x[:] = x

@@ -38,6 +38,18 @@
  *     (the paper's order b0, sigma^2, tau^2, field), lam's sum of squares is
  *     ||y - 1 b0 - x||^2 with the new b0, and the accumulators collect the
  *     image b0 + x (the quantity the paper reports).
+ *   - Optionally the binomial model of Sec. 3.2: Y_i ~ Bin(m_i, pi_i) with
+ *     logit(pi_i) = b0 + x_i, made conditionally Gaussian by the Polya-Gamma
+ *     augmentation the paper cites (Polson, Scott & Windle 2013): with
+ *     kappa_i = Y_i - m_i / 2 and psi_i ~ PG(m_i, b0 + x_i),
+ *         Qii = tau * D_ii + psi_i,
+ *         m_i = (kappa_i - psi_i * b0 + tau * rho * sum_{j~i} x_j) / Qii,
+ *     b0 | x, psi ~ N(sum(kappa - psi x) / P, 1 / P), P = sum psi + 1/v0
+ *     (prior b0 ~ N(0, v0), v0 = 0 meaning flat), and tau as above.  The
+ *     supplement that details the paper's sampler is not available; the
+ *     reading here draws psi_i right before x_i in the site's color pass,
+ *     which equals drawing all of psi first because psi_i depends on its
+ *     own site only.
  *   - The greedy coloring of the paper's supplementary greedy algorithm
  *     (peel maximal independent sets, always taking the smallest remaining
  *     site).
@@ -217,6 +229,168 @@ int64_t orc_components(int64_t n, const int64_t *row_ptr, const int32_t *col)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Polya-Gamma variates (Polson, Scott & Windle 2013, JASA 108, Sec. 4,      */
+/* after Devroye 2009): PG(1, c) = J*(1, |c|/2) / 4, J* drawn by rejection    */
+/* from a two-piece envelope (truncated exponential right of t, truncated     */
+/* inverse Gaussian left of t) with the alternating-series acceptance test.   */
+/* PG(b, c) for integer b is the sum of b independent PG(1, c).               */
+/* ------------------------------------------------------------------------ */
+#define ORC_PI 3.141592653589793
+#define ORC_PG_T 0.64                 /* Devroye's switch point t */
+#define ORC_PG_MAX_UNIFORMS 2048      /* uniforms available to one PG(1, c) draw */
+#define ORC_PG_MAX_TERMS 200          /* series terms per acceptance test */
+
+/* The uniform stream of one PG(1, c) draw: uniform number u (0-based) is
+ * half (u & 1) of the Philox block at counter
+ * (site, sweep, instance, 0x80000000 | j << 10 | u >> 1), j the index of the
+ * PG(1, c) term inside PG(m_i, c) (j < 2^21). */
+typedef struct {
+    uint64_t seed;
+    uint32_t site, sweep, instance, j;
+    uint32_t used;
+    int exhausted;
+} orc_ustream;
+
+static double orc_ustream_next(orc_ustream *s)
+{
+    uint32_t w[4];
+    uint32_t u = s->used;
+    if (u >= ORC_PG_MAX_UNIFORMS) {
+        s->exhausted = 1;
+        return 0.5;
+    }
+    s->used = u + 1;
+    orc_words(s->seed, s->site, s->sweep, s->instance, 0x80000000u | (s->j << 10) | (u >> 1), w);
+    return (u & 1u) ? orc_uniform52(w[2], w[3]) : orc_uniform52(w[0], w[1]);
+}
+
+/* Standard normal from the next two uniforms of the stream (Box-Muller). */
+static double orc_ustream_normal(orc_ustream *s)
+{
+    double u1 = orc_ustream_next(s);
+    double u2 = orc_ustream_next(s);
+    return sqrt(-2.0 * log(u1)) * cos(ORC_TWO_PI * u2);
+}
+
+static double orc_std_normal_cdf(double x) { return 0.5 * erfc(-x / sqrt(2.0)); }
+
+/* n-th term of the alternating series of the J*(1) density, in the form used
+ * left (x <= t) and right (x > t) of the switch point. */
+static double orc_pg_term(int n, double x)
+{
+    double h = (double)n + 0.5;
+    if (x > ORC_PG_T)
+        return ORC_PI * h * exp(-0.5 * h * h * ORC_PI * ORC_PI * x);
+    {
+        double r = 2.0 / (ORC_PI * x);
+        return ORC_PI * h * r * sqrt(r) * exp(-2.0 * h * h / x);
+    }
+}
+
+/* Inverse Gaussian IG(mu = 1/z, 1) truncated to (0, t).  For mu > t (z < 1/t,
+ * z = 0 included): the z = 0 law truncated to (0, t) through 1/X =
+ * (1 + t E1)^2 / t with E1^2 <= 2 E2 / t (normal-tail rejection), then
+ * accepted with probability exp(-z^2 X / 2).  For mu <= t: the
+ * Michael-Schucany-Haas transformation, repeated until X < t. */
+static double orc_pg_left(double z, orc_ustream *s)
+{
+    const double t = ORC_PG_T;
+    if (z < 1.0 / t) {
+        for (;;) {
+            double e1, e2, x;
+            do {
+                e1 = -log(orc_ustream_next(s));
+                e2 = -log(orc_ustream_next(s));
+            } while (e1 * e1 > 2.0 * e2 / t && !s->exhausted);
+            x = t / ((1.0 + t * e1) * (1.0 + t * e1));
+            if (orc_ustream_next(s) <= exp(-0.5 * z * z * x) || s->exhausted)
+                return x;
+        }
+    } else {
+        const double mu = 1.0 / z;
+        for (;;) {
+            double nrm = orc_ustream_normal(s);
+            double y = nrm * nrm;
+            double my = mu * y;
+            double x = mu + 0.5 * mu * my - 0.5 * mu * sqrt(4.0 * my + my * my);
+            if (orc_ustream_next(s) > mu / (mu + x))
+                x = mu * mu / x;
+            if (x < t || s->exhausted)
+                return x;
+        }
+    }
+}
+
+/* PG(1, c) from the stream of term j.  Returns 0 and *out, or -1 when the
+ * stream ran out (probability far below 1e-100). */
+int orc_pg1(double c, uint64_t seed, uint32_t site, uint32_t sweep, uint32_t instance, uint32_t j,
+            double *out)
+{
+    const double t = ORC_PG_T;
+    const double z = 0.5 * fabs(c);
+    const double K = ORC_PI * ORC_PI / 8.0 + 0.5 * z * z;
+    double p, q;
+    orc_ustream s;
+    s.seed = seed;
+    s.site = site;
+    s.sweep = sweep;
+    s.instance = instance;
+    s.j = j;
+    s.used = 0;
+    s.exhausted = 0;
+    /* masses of the two envelope pieces */
+    p = ORC_PI / (2.0 * K) * exp(-K * t);
+    if (z == 0.0) {
+        q = 2.0 * erfc(1.0 / sqrt(2.0 * t));
+    } else {
+        double a = orc_std_normal_cdf((t * z - 1.0) / sqrt(t));
+        double b = z < 700.0 ? exp(z) * orc_std_normal_cdf(-(t * z + 1.0) / sqrt(t)) : 0.0;
+        q = 2.0 * (exp(-z) * a + b);
+    }
+    for (;;) {
+        double x, S, Y;
+        int n;
+        if (orc_ustream_next(&s) < p / (p + q))
+            x = t - log(orc_ustream_next(&s)) / K;
+        else
+            x = orc_pg_left(z, &s);
+        S = orc_pg_term(0, x);
+        Y = orc_ustream_next(&s) * S;
+        if (s.exhausted)
+            return -1;
+        for (n = 1; n <= ORC_PG_MAX_TERMS; ++n) {
+            if (n & 1) {
+                S -= orc_pg_term(n, x);
+                if (Y <= S) {
+                    *out = 0.25 * x;
+                    return 0;
+                }
+            } else {
+                S += orc_pg_term(n, x);
+                if (Y > S)
+                    break;
+            }
+        }
+    }
+}
+
+/* PG(b, c) for an integer b >= 0: the sum of PG(1, c) terms j = 0 .. b-1 in
+ * order (PG(0, c) = 0). */
+int orc_pg(int32_t b, double c, uint64_t seed, uint32_t site, uint32_t sweep, uint32_t instance,
+           double *out)
+{
+    double sum = 0.0, v;
+    int32_t j;
+    for (j = 0; j < b; ++j) {
+        if (orc_pg1(c, seed, site, sweep, instance, (uint32_t)j, &v))
+            return -1;
+        sum += v;
+    }
+    *out = sum;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Sampler                                                                    */
 /* ------------------------------------------------------------------------ */
 
@@ -233,8 +407,13 @@ typedef struct {
     int64_t burn_in;          /* sweeps with index < burn_in are not accumulated */
     uint64_t seed;
     uint32_t instance;
-    int32_t intercept;        /* 1: the image model with intercept b0 */
+    int32_t intercept;        /* 1: the model has an intercept b0 */
+    int32_t likelihood;       /* 0 Gaussian (y = b0 + x + e), 1 binomial logit */
+    const int32_t *trials;    /* binomial: m_i (y holds the successes Y_i) */
+    double beta0_var;         /* binomial: prior variance v0 of b0 (0 = flat) */
 } orc_problem;
+
+#define ORC_BINOMIAL 1
 
 typedef struct {
     double *x;                /* current field, original order */
@@ -245,6 +424,8 @@ typedef struct {
     double q, sse;            /* x'(D - rho W)x and ||y - b0 - x||^2 after the last sweep */
     int32_t status;           /* 0 ok, 1 Gamma attempt cap hit or non-finite draw */
     double beta0;             /* intercept (stays 0 without the intercept) */
+    double *psi;              /* binomial: the psi_i of the last sweep (n) */
+    double rsum;              /* binomial: sum_i (kappa_i - psi_i x_i) after the last sweep */
 } orc_chain;
 
 #define ORC_WITH_HYPER 1u
@@ -309,6 +490,23 @@ int orc_hyper(const orc_problem *p, orc_chain *s)
     uint32_t t = (uint32_t)(s->sweep - 1);
     double tau, lam;
     int a1, a2;
+    if (p->likelihood == ORC_BINOMIAL) {
+        /* b0 | x, psi ~ N(sum(kappa - psi x) / P, 1/P) (the sse slot holds
+         * sum psi after a binomial sweep), then tau */
+        if (p->intercept) {
+            double P = s->sse + (p->beta0_var > 0.0 ? 1.0 / p->beta0_var : 0.0);
+            double z = orc_normal(p->seed, 0u, t, p->instance, 3u);
+            s->beta0 = s->rsum / P + z / sqrt(P);
+        }
+        a1 = orc_gamma(p->a_tau + 0.5 * (double)p->rank, p->b_tau + 0.5 * s->q, p->seed, t,
+                       p->instance, 1u, ORC_GAMMA_MAX_ATTEMPTS, &tau);
+        if (a1 < 0 || !isfinite(tau) || !isfinite(s->beta0)) {
+            s->status = 1;
+            return 1;
+        }
+        s->tau = tau;
+        return 0;
+    }
     if (p->intercept) {
         /* b0 | x, lam ~ N(mean(y - x), 1 / (n lam)), then lam's sum of squares
          * with the new b0 (the x of the last sweep is unchanged) */
@@ -345,8 +543,18 @@ static void orc_update_site(const orc_problem *p, orc_chain *s, int64_t i, uint3
     for (e = p->row_ptr[i]; e < p->row_ptr[i + 1]; ++e)
         sum += s->x[p->col[e]];
     deg = (double)(p->row_ptr[i + 1] - p->row_ptr[i]);
-    Qii = s->tau * deg + s->lam;
-    m = (s->lam * (p->y[i] - s->beta0) + s->tau * p->rho * sum) / Qii;
+    if (p->likelihood == ORC_BINOMIAL) {
+        /* psi_i | x_i, b0 ~ PG(m_i, b0 + x_i), with this site's old x_i */
+        double psi = 0.0, kappa = p->y[i] - 0.5 * (double)p->trials[i];
+        if (orc_pg(p->trials[i], s->beta0 + s->x[i], p->seed, (uint32_t)i, t, p->instance, &psi))
+            s->status = 1;
+        s->psi[i] = psi;
+        Qii = s->tau * deg + psi;
+        m = (kappa - psi * s->beta0 + s->tau * p->rho * sum) / Qii;
+    } else {
+        Qii = s->tau * deg + s->lam;
+        m = (s->lam * (p->y[i] - s->beta0) + s->tau * p->rho * sum) / Qii;
+    }
     z = (flags & ORC_ZERO_NOISE) ? 0.0 : orc_normal(p->seed, (uint32_t)i, t, p->instance, 0u);
     s->x[i] = m + z / sqrt(Qii);
 }
@@ -379,7 +587,19 @@ int orc_sweeps(const orc_problem *p, orc_chain *s, int64_t nsweeps, uint32_t fla
                     orc_update_site(p, s, site, t, flags);
             }
         }
+        if (s->status)
+            return 1;
         orc_quadratic_terms_b0(p, s->x, s->beta0, &s->q, &s->sse);
+        if (p->likelihood == ORC_BINOMIAL) {
+            /* the b0 conditional's sums: sum psi (in the sse slot) and
+             * sum (kappa - psi x) */
+            double *d = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+            s->sse = orc_pairwise(s->psi, n);
+            for (i = 0; i < n; ++i)
+                d[i] = (p->y[i] - 0.5 * (double)p->trials[i]) - s->psi[i] * s->x[i];
+            s->rsum = orc_pairwise(d, n);
+            free(d);
+        }
         if ((int64_t)t >= p->burn_in) {
             for (i = 0; i < n; ++i) {
                 double phi = s->x[i] + s->beta0;   /* the image b0 + x (x without b0) */
