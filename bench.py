@@ -315,6 +315,85 @@ def bench_image(torch, gmrf, inputs, args):
     print(json.dumps(line), flush=True)
 
 
+def bench_binomial(torch, gmrf, inputs, args):
+    """The paper's binomial example on the GPU (Sec. 3.2, Table 2 setting):
+    n = 14,926 areas with a Delaunay adjacency (greedy coloring), counts of
+    lognormal trial numbers (median 250, 2.2% areas without data), proper CAR
+    rho = 0.995, beta0 ~ N(0, 1000), tau ~ Gamma(1, 1) (InvGam(1, 1) on
+    tau^2), 10,000 iterations of which the last 5,000 are retained.  T is the
+    wall time of the whole run; IAT / ESS / CES of the beta0 and tau^2
+    chains come from the device trace.  The oracle is timed on a bounded
+    number of iterations of the same workload.  Prints one JSON line."""
+    from paper_1702_05518_amd import diagnostics
+
+    total, burn, n = 10_000, 5_000, 14_926
+    wl = inputs.binomial_workload(n, data_seed=5)
+    color, k = gmrf.greedy_coloring(wl["row_ptr"], wl["col"])
+    graph = gmrf.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color, num_colors=k,
+                       rho=0.995)
+    rows = []
+    for name, prec in (("fp64", gmrf.FP64), ("fp32_acc", gmrf.FP32_ACC64)):
+        ch = gmrf.Chain(graph, wl["y"], precision=prec, seed=1, trials=wl["trials"],
+                        intercept=True, beta0_var=1000.0, burn_in=burn)
+        ch.enable_trace(total)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(total // 1000):
+            ch.sweep(1000, hyper=True, capture=True)
+        mean, var, nacc = ch.posterior_stats()
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        tr = ch.trace()
+        if nacc != total - burn or not np.isfinite(tr).all():
+            print("bench.py: binomial run failed", file=sys.stderr)
+            sys.exit(1)
+        b0 = diagnostics.summary(tr[burn:, 2], T)
+        t2 = diagnostics.summary(1.0 / tr[burn:, 0], T)
+        rows.append({"precision": name, "seconds": T, "site_updates_per_s": n * total / T,
+                     "ms_per_sweep": T / total * 1e3,
+                     "beta0": {"iat": b0["iat"], "ess": b0["ess"], "ces_s": b0["ces_s"]},
+                     "tau2": {"iat": t2["iat"], "ess": t2["ess"], "ces_s": t2["ces_s"]},
+                     "eta_corr_vs_truth": float(np.corrcoef(mean, wl["truth"])[0, 1])})
+        log(f"[bench] binomial {name}: T {T:.2f} s, CES beta0 {b0['ces_s']:.2e} s, "
+            f"tau2 {t2['ces_s']:.2e} s")
+        ch.disable_trace()
+        del ch
+    line = {
+        "metric": "CES of the beta0 and tau^2 chains, binomial model n=14,926",
+        "value": rows[0]["beta0"]["ces_s"], "unit": "s", "n_gpus": 1, "steps": total,
+        "warmup": 0, "ms_per_step": rows[0]["ms_per_sweep"], "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "binomial logit, Polya-Gamma augmentation, Delaunay n=14,926, "
+                               "greedy coloring, trials lognormal median 250 (2.2% empty), "
+                               "proper CAR rho 0.995, beta0 ~ N(0, 1000), 10,000 iterations, "
+                               "5,000 burn-in",
+                   "colors": int(k), "trials_total": int(wl["trials"].sum())},
+        "rows": rows,
+        "context_paper_table2_chromatic_cpu": {"seconds": 222.06, "beta0_ces_s": 0.0935,
+                                               "tau2_ces_s": 0.1155,
+                                               "hardware": "Core i5-3570, R, FP64"},
+    }
+    if not args.no_cpu:
+        import oracle
+
+        oracle.build(force=False)
+        threads = min(16, os.cpu_count() or 1)
+        oc = oracle.Chain(wl["row_ptr"], wl["col"], color, wl["y"], rho=0.995,
+                          trials=wl["trials"], intercept=True, beta0_var=1000.0, seed=1)
+        t0 = time.perf_counter()
+        oc.sweeps(1, nthreads=threads)
+        one = time.perf_counter() - t0
+        reps = max(1, min(200, int(10.0 / max(one, 1e-3))))
+        t0 = time.perf_counter()
+        oc.sweeps(reps, nthreads=threads)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": n * reps / dt, "unit": "site-updates/s",
+                                "cores": threads, "kind": "oracle",
+                                "sample": f"{reps} FP64 iterations of the same binomial "
+                                          f"workload, C oracle with {threads} OpenMP threads"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,10 +403,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--reps", type=int, default=10, help="solves for p50/p99 latency")
     ap.add_argument("--workload", default="lattice2048",
-                    choices=["lattice2048", "batch512", "serve", "image"],
+                    choices=["lattice2048", "batch512", "serve", "image", "binomial"],
                     help="lattice2048: the 2048x2048 lattice line (default); batch512: the "
                          "batched many-instance workload; serve: the serving workload; "
-                         "image: the paper's image example with IAT / ESS / CES "
+                         "image: the paper's image example with IAT / ESS / CES; "
+                         "binomial: the paper's binomial example with IAT / ESS / CES "
                          "(each a separate JSON line)")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe for rocprofv3 --pmc: a 512 MiB device copy (the "
@@ -358,6 +438,9 @@ def main():
         return
     if args.workload == "image":
         bench_image(torch, gmrf, inputs, args)
+        return
+    if args.workload == "binomial":
+        bench_binomial(torch, gmrf, inputs, args)
         return
     log(f"[bench] building workload {ROWS}x{COLS} stencil {STENCIL}")
     wl = inputs.lattice_workload(ROWS, COLS, STENCIL, noise_sd=0.1, data_seed=1,

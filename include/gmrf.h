@@ -28,10 +28,23 @@
  * mean/variance of the image; with a flat beta0 and an intrinsic prior only
  * phi is identified).
  *
+ * Binomial logit model (Sec. 3.2, general graphs, gmrf_chain_create_binomial):
+ *     Y_i ~ Bin(m_i, pi_i),  logit(pi_i) = beta0 + x_i,  beta0 ~ N(0, v0)
+ * made conditionally Gaussian by Polya-Gamma augmentation (Polson, Scott &
+ * Windle 2013): with kappa_i = Y_i - m_i / 2, each site of the current color
+ * first draws psi_i ~ PG(m_i, beta0 + x_i) from its old x_i (a sum of m_i
+ * PG(1, .) terms, Devroye's alternating-series sampler), then
+ *     Qii = tau * D_ii + psi_i,
+ *     m_i = (kappa_i - psi_i beta0 + tau * rho * sum_{j~i} x_j) / Qii,
+ * and after the sweep beta0 ~ N(sum(kappa - psi x) / P, 1/P),
+ * P = sum psi + 1/v0 (v0 = 0: flat), then tau as above.  The accumulators
+ * collect the linear predictor beta0 + x.
+ *
  * Random numbers: Philox4x32-10 keyed by the 64-bit seed with counter
  * (site id, sweep t, instance, tag); tag 0 = site normal (Box-Muller, cosine
  * branch), tags 1/2 = the tau/lam Gamma draws (Marsaglia-Tsang), tag 3 (site
- * id 0) = the beta0 normal.  Site ids are
+ * id 0) = the beta0 normal; the PG(1, .) term j of site i draws uniform u
+ * from half (u & 1) of the block at (i, t, instance, 2^31 | j << 10 | u >> 1).  Site ids are
  * the caller's ORIGINAL ids, so results do not depend on the internal layout,
  * the thread mapping or the color permutation.
  *
@@ -114,11 +127,16 @@ typedef struct {
     double a_lam, b_lam;    /* Gamma(shape, rate) prior of the noise precision lam */
     double tau0, lam0;      /* initial tau, lam (> 0) */
     int64_t burn_in;        /* sweeps t < burn_in are not accumulated */
-    int32_t intercept;      /* 1: y = beta0 1 + x + e with a flat prior on beta0
-                               (Sec. 3.1); 0: no intercept */
-    int32_t reserved;       /* must be 0 */
+    int32_t intercept;      /* 1: the model has an intercept beta0 (Sec. 3.1: flat prior;
+                               binomial: N(0, beta0_var)); 0: beta0 = 0 */
+    int32_t likelihood;     /* GMRF_GAUSSIAN (gmrf_chain_create) or GMRF_BINOMIAL
+                               (gmrf_chain_create_binomial) */
     double beta0;           /* initial beta0 (finite; must be 0 when intercept = 0) */
+    double beta0_var;       /* binomial: prior variance of beta0, 0 = flat; Gaussian: 0 */
 } gmrf_model;
+
+#define GMRF_GAUSSIAN 0
+#define GMRF_BINOMIAL 1
 
 typedef struct gmrf_graph gmrf_graph;
 typedef struct gmrf_chain gmrf_chain;
@@ -178,6 +196,23 @@ int gmrf_chain_create(const gmrf_graph *g, const gmrf_model *m, const double *y,
                       gmrf_precision p, uint64_t seed, uint32_t instance, void *d_ws,
                       size_t ws_bytes, hipStream_t stream, gmrf_chain **out);
 int gmrf_chain_destroy(gmrf_chain *c);
+
+/* Device workspace bytes of one binomial chain on a general graph g (adds the
+ * trials array; color passes run one wavefront per site). */
+size_t gmrf_binomial_footprint(const gmrf_graph *g, gmrf_precision p);
+
+/* Create a binomial logit chain (Sec. 3.2) on a general graph: successes
+ * (host, n values Y_i, integers) and trials (host, n values m_i, 0 <= Y_i <=
+ * m_i < 2^21; m_i = 0 marks a site without data, which then needs at least
+ * one neighbour), x0 as for gmrf_chain_create, m->likelihood = GMRF_BINOMIAL,
+ * m->beta0_var >= 0.  a_lam / b_lam / lam0 are not used by the sampler (lam
+ * stays lam0).  Batches do not take binomial chains.  The workspace needs
+ * gmrf_binomial_footprint bytes.  Synchronises.  Errors as gmrf_chain_create,
+ * plus GMRF_E_INVALID_ARG for a lattice graph or invalid counts. */
+int gmrf_chain_create_binomial(const gmrf_graph *g, const gmrf_model *m, const double *successes,
+                               const int32_t *trials, const double *x0, gmrf_precision p,
+                               uint64_t seed, uint32_t instance, void *d_ws, size_t ws_bytes,
+                               hipStream_t stream, gmrf_chain **out);
 
 /* Enqueue nsweeps sweeps (Algorithm 1 over all colors, with the fused
  * x'(D - rho W)x and ||y - beta0 1 - x||^2 reductions and the posterior
@@ -280,7 +315,7 @@ int gmrf_chain_autotune(gmrf_chain *c, int32_t reps, hipStream_t stream, int32_t
 
 /* Reductions of the last completed sweep: q = x'(D - rho W)x and
  * sse = ||y - beta0 1 - x||^2 (FP64; after a draw of beta0, at the new
- * beta0).  Synchronises. */
+ * beta0); for a binomial chain sse is sum_i psi_i.  Synchronises. */
 int gmrf_last_reductions(gmrf_chain *c, double *q, double *sse, hipStream_t stream);
 
 /* ---- batches: many chains advanced by shared launches -------------------- */

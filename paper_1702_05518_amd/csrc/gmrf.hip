@@ -74,6 +74,8 @@ struct SweepArgs {
     int with_hyper;
     int total_slots;            // blocks per sweep (all color passes)
     int intercept;              // 1: draw beta0 before tau / lam
+    int likelihood;             // 0 Gaussian, 1 binomial logit (Polya-Gamma)
+    double b0_prec;             // binomial: prior precision of beta0 (0 = flat)
     double n_sites;
     double *trace;              // NULL, or (tau, lam, beta0) per completed sweep
     long long trace_cap;        // rows of trace
@@ -129,6 +131,8 @@ __device__ __forceinline__ void block_sum3(double &a, double &b, double &c, doub
 
 // The FP64 sums a sweep block contributes: q = x'(D - rho W)x terms, and the
 // residuals r_i = y_i - beta0 - x_i as sse = sum r_i^2 and rsum = sum r_i.
+// For the binomial model the last two slots hold sum psi_i and
+// sum (kappa_i - psi_i x_i), the sums of the beta0 conditional.
 struct Red {
     double q = 0.0, sse = 0.0, rsum = 0.0;
 };
@@ -165,14 +169,21 @@ __device__ __forceinline__ void end_of_sweep_draws(const SweepArgs &a, unsigned 
     double b0 = in.beta0;
     if (a.with_hyper && a.intercept) {
         const double z = normal_f64(draw_words(a.seed, 0u, t, a.instance, 3u));
-        const double mean = in.beta0 + r.rsum / a.n_sites;
-        b0 = mean + z / sqrt(a.n_sites * in.lam);
-        const double d = b0 - in.beta0;
-        r.sse = r.sse - 2.0 * d * r.rsum + a.n_sites * d * d;
-        r.rsum = r.rsum - a.n_sites * d;
+        if (a.likelihood) {
+            // binomial (Sec. 3.2 augmented model): beta0 | x, psi ~
+            // N(sum(kappa - psi x) / P, 1 / P), P = sum psi + prior precision
+            const double P = r.sse + a.b0_prec;
+            b0 = r.rsum / P + z / sqrt(P);
+        } else {
+            const double mean = in.beta0 + r.rsum / a.n_sites;
+            b0 = mean + z / sqrt(a.n_sites * in.lam);
+            const double d = b0 - in.beta0;
+            r.sse = r.sse - 2.0 * d * r.rsum + a.n_sites * d * d;
+            r.rsum = r.rsum - a.n_sites * d;
+        }
     }
     double v = lane == 0 ? in.tau : in.lam;
-    if (a.with_hyper && lane < 2) {
+    if (a.with_hyper && lane < (a.likelihood ? 1 : 2)) {   // no noise precision if binomial
         const GammaShape g = lane == 0 ? a.g_tau : a.g_lam;
         const double rate = lane == 0 ? a.b_tau + 0.5 * r.q : a.b_lam + 0.5 * r.sse;
         double draw = 0.0;
@@ -621,7 +632,8 @@ template <typename Real> struct CsrArgs {
     const int *col;
     const int *orig;            // slab position -> original id (random-number key)
     Real *x;
-    const Real *y;
+    const Real *y;              // y (Gaussian) or kappa = Y - m/2 (binomial)
+    const int *trials;          // binomial: m_i (slab order); NULL otherwise
 };
 
 // One site per thread.  The first kCsrBatch neighbours are gathered in one
@@ -732,6 +744,85 @@ __global__ __launch_bounds__(kThreads) void csr_batch_kernel(const CsrJob<Real> 
 }
 
 // ---------------------------------------------------------------------------
+// general graphs, binomial logit model (Sec. 3.2 with Polya-Gamma
+// augmentation): one wavefront per site
+// ---------------------------------------------------------------------------
+// Site p of the color slab: psi_p ~ PG(m_p, beta0 + x_p) with the site's old
+// x_p, its m_p PG(1, .) terms split over the 64 lanes (lane l takes terms l,
+// l + 64, ...; the lane sums are added in a fixed tree); then lane 0 draws
+// x_p from N(m, 1/Q) with Q = tau D_pp + psi_p and
+// m = (kappa_p - psi_p beta0 + tau rho sum_{j~p} x_j) / Q.
+constexpr int kBinomSites = kThreads / 64;      // sites per block
+
+template <typename Real, bool B0>
+__global__ __launch_bounds__(kThreads) void csr_binomial_pass_kernel(CsrArgs<Real> ca, SweepArgs a,
+                                                                     int lo, int cnt, int slot_base)
+{
+    const unsigned t = (unsigned)a.st->sweep;
+    const double tau_d = a.st->tau;
+    const double b0 = B0 ? a.st->beta0 : 0.0;
+    const Real tau = (Real)tau_d, tau_rho = (Real)(tau_d * a.rho);
+    const int lane = (int)threadIdx.x & 63;
+    const int p = lo + (int)blockIdx.x * kBinomSites + ((int)threadIdx.x >> 6);
+    Red rd;
+    if (p < lo + cnt) {     // uniform across the wavefront
+        const int m = ca.trials[p];
+        const unsigned id = (unsigned)ca.orig[p];
+        const Real xold = ca.x[p];
+        const PgEnvelope env = pg_envelope(b0 + (double)xold);
+        double part = 0.0;
+        bool ok = true;
+        for (int j = lane; j < m; j += 64) {
+            double v = 0.0;
+            ok = pg1_draw(env, a.seed, id, t, a.instance, (unsigned)j, &v) && ok;
+            part += v;
+        }
+        if (!ok)
+            atomicOr(&a.st->status, kStatusGamma);
+        const double psi = __shfl(wave_sum(part), 0, 64);
+        if (lane == 0) {
+            const int e0 = ca.row_ptr[p], e1 = ca.row_ptr[p + 1];
+            const int deg = e1 - e0;
+            Real s = (Real)0;
+            for (int e = e0; e < e1; ++e)
+                s += ca.x[ca.col[e]];
+            const double kappa = (double)ca.y[p];
+            const Real Q = fma(tau, (Real)deg, (Real)psi);
+            Real inv_q, isd;
+            if constexpr (sizeof(Real) == 8) {
+                inv_q = 1.0 / Q;
+                isd = 1.0 / sqrt(Q);
+            } else {
+                inv_q = 1.0f / Q;
+                isd = __builtin_amdgcn_rsqf(Q);
+            }
+            const Real beff = (Real)(kappa - psi * b0);
+            const Real z = site_normal<Real>(draw_words(a.seed, id, t, a.instance, 0u));
+            const Real xn = fma(z, isd, fma(tau_rho, s, beff) * inv_q);
+            ca.x[p] = xn;
+            const double xd = (double)xn;
+            double edge = 0.0;
+            for (int e = e0; e < e1; ++e) {
+                const int j = ca.col[e];
+                if (j < lo) {      // lower color: already final this sweep
+                    const double d = xd - (double)ca.x[j];
+                    edge += d * d;
+                }
+            }
+            rd.q = (1.0 - a.rho) * (double)deg * xd * xd + a.rho * edge;
+            rd.sse = psi;
+            rd.rsum = kappa - psi * xd;
+            if ((long long)t >= a.burn_in) {
+                const double eta = B0 ? xd + b0 : xd;   // accumulated linear predictor
+                a.s1[p] += eta;
+                a.s2[p] += eta * eta;
+            }
+        }
+    }
+    write_partials<kThreads>(a, rd, slot_base + (int)blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
 // Redraw after the last completed sweep from its stored reductions (one
@@ -753,13 +844,16 @@ __global__ void set_hyper_kernel(DevState *st, double tau, double lam)
     st->lam = lam;
 }
 
-// Set the intercept; the stored residual sums move with it so that a redraw
-// from them stays consistent with x.
-__global__ void set_intercept_kernel(DevState *st, double beta0, double n)
+// Set the intercept; for the Gaussian model the stored residual sums move
+// with it so that a redraw from them stays consistent with x (the binomial
+// sums do not involve beta0).
+__global__ void set_intercept_kernel(DevState *st, double beta0, double n, int binomial)
 {
-    const double d = beta0 - st->beta0;
-    st->sse = st->sse - 2.0 * d * st->rsum + n * d * d;
-    st->rsum = st->rsum - n * d;
+    if (!binomial) {
+        const double d = beta0 - st->beta0;
+        st->sse = st->sse - 2.0 * d * st->rsum + n * d * d;
+        st->rsum = st->rsum - n * d;
+    }
     st->beta0 = beta0;
 }
 
@@ -804,6 +898,8 @@ struct gmrf_chain {
     double *d_stats = nullptr;
     int total_slots = 0;              // partial slots of one sweep (current tile shape)
     int lat_tile = 0;                 // lattice tile shape (index into kTiles)
+    bool binomial = false;            // binomial logit likelihood (general graphs only)
+    int *d_trials = nullptr;          // binomial: m_i in slab order
     std::vector<int> pass_blocks;     // CSR: blocks per color pass
     uint64_t host_sweeps = 0;         // sweeps enqueued (host view)
     hipStream_t capture_stream = nullptr;
@@ -879,8 +975,11 @@ int max_lattice_blocks(const HostGraph &h)
     return m;
 }
 
-// Chain workspace layout; ptrs may be NULL to only compute the size.
-size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chain *c)
+// Chain workspace layout; ptrs may be NULL to only compute the size.  A
+// binomial chain adds the trials array, and its color passes take
+// kBinomSites sites per block.
+size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chain *c,
+                    bool binomial)
 {
     const int64_t n = g->h.n;
     const size_t rs = real_size(p);
@@ -898,7 +997,8 @@ size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chai
     } else {
         for (int32_t col = 0; col < g->h.k; ++col) {
             const int cnt = g->h.slab_offsets[col + 1] - g->h.slab_offsets[col];
-            const int nb = (cnt + kThreads - 1) / kThreads;
+            const int per = binomial ? kBinomSites : kThreads;
+            const int nb = (cnt + per - 1) / per;
             pass_blocks.push_back(nb);
             slots += nb;
         }
@@ -912,7 +1012,9 @@ size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chai
     char *s2 = take(8 * n);
     char *part = take(8 * kPartials * (size_t)std::max(reserve, 1));
     char *stats = take(16 * n);
+    char *trials = binomial ? take(4 * n) : nullptr;
     if (c) {
+        c->d_trials = reinterpret_cast<int *>(trials);
         c->d_state = reinterpret_cast<DevState *>(st);
         c->d_x[0] = x0;
         c->d_x[1] = x1;
@@ -949,6 +1051,8 @@ SweepArgs make_args(const gmrf_chain *c, unsigned flags)
     a.with_hyper = (flags & GMRF_WITH_HYPER) ? 1 : 0;
     a.total_slots = c->total_slots;
     a.intercept = c->model.intercept ? 1 : 0;
+    a.likelihood = c->binomial ? 1 : 0;
+    a.b0_prec = c->binomial && c->model.beta0_var > 0.0 ? 1.0 / c->model.beta0_var : 0.0;
     a.n_sites = (double)c->g->h.n;
     a.trace = c->d_trace;
     a.trace_cap = c->trace_cap;
@@ -976,6 +1080,7 @@ template <typename Real> CsrArgs<Real> csr_args(const gmrf_chain *c)
     ca.orig = c->g->d_orig;
     ca.x = static_cast<Real *>(c->d_x[0]);
     ca.y = static_cast<const Real *>(c->d_y);
+    ca.trials = c->d_trials;
     return ca;
 }
 
@@ -1029,12 +1134,16 @@ void launch_csr(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent
             continue;
         const int lo = h.slab_offsets[col], cnt = h.slab_offsets[col + 1] - lo;
         hipEvent_t e0 = slot == 0 ? ev0 : nullptr, e1 = col == last ? ev1 : nullptr;
-        auto kern = c->model.intercept ? csr_pass_kernel<Real, true> : csr_pass_kernel<Real, false>;
+        auto kern = c->binomial ? (c->model.intercept ? csr_binomial_pass_kernel<Real, true>
+                                                      : csr_binomial_pass_kernel<Real, false>)
+                                : (c->model.intercept ? csr_pass_kernel<Real, true>
+                                                      : csr_pass_kernel<Real, false>);
+        const int threads = kThreads;
         if (e0 || e1)
-            hipExtLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, s, e0, e1, 0, ca, a, lo, cnt,
+            hipExtLaunchKernelGGL(kern, dim3(nb), dim3(threads), 0, s, e0, e1, 0, ca, a, lo, cnt,
                                   slot);
         else
-            hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, s, ca, a, lo, cnt, slot);
+            hipLaunchKernelGGL(kern, dim3(nb), dim3(threads), 0, s, ca, a, lo, cnt, slot);
         slot += nb;
     }
 }
@@ -1127,6 +1236,17 @@ int upload_doubles_layout(const gmrf_chain *c, double *dst, const double *x, hip
     for (int64_t p = 0; p < n; ++p)
         buf[p] = x[is_lattice(c->g) ? p : c->g->h.orig_of_slab[p]];
     GMRF_HIP(hipMemcpyAsync(dst, buf.data(), 8 * n, hipMemcpyHostToDevice, s));
+    GMRF_HIP(hipStreamSynchronize(s));
+    return GMRF_OK;
+}
+
+int upload_trials_layout(const gmrf_chain *c, const int32_t *trials, hipStream_t s)
+{
+    const int64_t n = c->g->h.n;
+    std::vector<int32_t> buf(n);
+    for (int64_t p = 0; p < n; ++p)
+        buf[p] = trials[c->g->h.orig_of_slab[p]];
+    GMRF_HIP(hipMemcpyAsync(c->d_trials, buf.data(), 4 * n, hipMemcpyHostToDevice, s));
     GMRF_HIP(hipStreamSynchronize(s));
     return GMRF_OK;
 }
@@ -1234,6 +1354,9 @@ int check_batch_chains(gmrf_chain *const *chains, int32_t count, gmrf_precision 
                                                 " appears twice");
         if (c->prec != chains[0]->prec)
             return fail(GMRF_E_INVALID_ARG, "batch: all chains must have one precision");
+        if (c->binomial)
+            return fail(GMRF_E_INVALID_ARG, "batch: binomial chains are swept on their own "
+                                            "(chain at index " + std::to_string(i) + ")");
         seen.push_back(c);
     }
     *prec = chains[0]->prec;
@@ -1417,45 +1540,88 @@ size_t gmrf_chain_footprint(const gmrf_graph *g, gmrf_precision p)
         set_error("chain_footprint: NULL graph or bad precision");
         return 0;
     }
-    return chain_layout(g, p, nullptr, nullptr);
+    return chain_layout(g, p, nullptr, nullptr, false);
 }
 
-int gmrf_chain_create(const gmrf_graph *g, const gmrf_model *m, const double *y, const double *x0,
-                      gmrf_precision p, uint64_t seed, uint32_t instance, void *d_ws,
-                      size_t ws_bytes, hipStream_t stream, gmrf_chain **out)
+size_t gmrf_binomial_footprint(const gmrf_graph *g, gmrf_precision p)
 {
-    clear_error();
+    if (!g || (p != GMRF_FP64 && p != GMRF_FP32_ACC64) || is_lattice(g)) {
+        set_error("binomial_footprint: NULL or lattice graph, or bad precision");
+        return 0;
+    }
+    return chain_layout(g, p, nullptr, nullptr, true);
+}
+
+// Common body of the two chain constructors.  binomial: y holds the
+// successes Y_i and trials the m_i.
+static int chain_create_impl(const char *who, const gmrf_graph *g, const gmrf_model *m,
+                             const double *y, const int32_t *trials, const double *x0,
+                             gmrf_precision p, uint64_t seed, uint32_t instance, void *d_ws,
+                             size_t ws_bytes, hipStream_t stream, gmrf_chain **out)
+{
+    const std::string w = who;
     if (!out)
-        return fail(GMRF_E_INVALID_ARG, "chain_create: out is NULL");
+        return fail(GMRF_E_INVALID_ARG, w + ": out is NULL");
     *out = nullptr;
+    const bool binomial = trials != nullptr;
     if (!g || !m || !y)
-        return fail(GMRF_E_INVALID_ARG, "chain_create: graph, model and y are required");
+        return fail(GMRF_E_INVALID_ARG, w + ": graph, model and y are required");
     if (p != GMRF_FP64 && p != GMRF_FP32_ACC64)
-        return fail(GMRF_E_INVALID_ARG, "chain_create: bad precision");
+        return fail(GMRF_E_INVALID_ARG, w + ": bad precision");
+    if (binomial && is_lattice(g))
+        return fail(GMRF_E_INVALID_ARG, w + ": the binomial model needs a general (CSR) graph");
     const int64_t n = g->h.n;
     const int64_t rank = g->h.rho == 1.0 ? n - g->h.components : n;
     const double shape_tau = m->a_tau + 0.5 * (double)rank, shape_lam = m->a_lam + 0.5 * (double)n;
-    if (!(m->b_tau > 0.0) || !(m->b_lam > 0.0) || !(shape_tau >= 1.0) || !(shape_lam >= 1.0) ||
-        !std::isfinite(m->a_tau) || !std::isfinite(m->a_lam) || !std::isfinite(m->b_tau) ||
-        !std::isfinite(m->b_lam))
-        return fail(GMRF_E_INVALID_ARG, "chain_create: priors need rates > 0 and conditional "
-                                        "shapes a_tau + r/2 >= 1, a_lam + n/2 >= 1");
+    if (!(m->b_tau > 0.0) || !(shape_tau >= 1.0) || !std::isfinite(m->a_tau) ||
+        !std::isfinite(m->b_tau) ||
+        (!binomial && (!(m->b_lam > 0.0) || !(shape_lam >= 1.0) || !std::isfinite(m->a_lam) ||
+                       !std::isfinite(m->b_lam))))
+        return fail(GMRF_E_INVALID_ARG, w + ": priors need rates > 0 and conditional shapes "
+                                            "a_tau + r/2 >= 1 (Gaussian: a_lam + n/2 >= 1)");
     if (!(m->tau0 > 0.0) || !(m->lam0 > 0.0) || !std::isfinite(m->tau0) ||
         !std::isfinite(m->lam0))
-        return fail(GMRF_E_INVALID_ARG, "chain_create: tau0 and lam0 must be finite and > 0");
+        return fail(GMRF_E_INVALID_ARG, w + ": tau0 and lam0 must be finite and > 0");
     if (m->burn_in < 0)
-        return fail(GMRF_E_INVALID_ARG, "chain_create: burn_in must be >= 0");
-    if ((m->intercept != 0 && m->intercept != 1) || m->reserved != 0 || !std::isfinite(m->beta0) ||
+        return fail(GMRF_E_INVALID_ARG, w + ": burn_in must be >= 0");
+    if ((m->intercept != 0 && m->intercept != 1) || !std::isfinite(m->beta0) ||
         (m->intercept == 0 && m->beta0 != 0.0))
-        return fail(GMRF_E_INVALID_ARG, "chain_create: intercept must be 0 or 1, reserved 0, and "
-                                        "beta0 finite (and 0 without an intercept)");
+        return fail(GMRF_E_INVALID_ARG, w + ": intercept must be 0 or 1 and beta0 finite (and 0 "
+                                            "without an intercept)");
+    if (m->likelihood != (binomial ? GMRF_BINOMIAL : GMRF_GAUSSIAN))
+        return fail(GMRF_E_INVALID_ARG, w + ": model likelihood does not match the constructor");
+    if (!binomial && m->beta0_var != 0.0)
+        return fail(GMRF_E_INVALID_ARG, w + ": beta0_var applies to the binomial model only");
+    if (binomial && (!(m->beta0_var >= 0.0) || !std::isfinite(m->beta0_var)))
+        return fail(GMRF_E_INVALID_ARG, w + ": beta0_var must be finite and >= 0");
     if (!finite_array(y, n) || (x0 && !finite_array(x0, n)))
-        return fail(GMRF_E_INVALID_ARG, "chain_create: y and x0 must be finite");
-    const size_t need = chain_layout(g, p, nullptr, nullptr);
+        return fail(GMRF_E_INVALID_ARG, w + ": y and x0 must be finite");
+    std::vector<double> kappa;
+    if (binomial) {
+        int64_t total = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t mi = trials[i];
+            const int32_t sp = g->h.slab_of_orig[i];
+            const int64_t deg = g->h.row_ptr[sp + 1] - g->h.row_ptr[sp];
+            if (mi < 0 || mi >= (1 << 21) || y[i] < 0.0 || y[i] > (double)mi ||
+                y[i] != std::floor(y[i]))
+                return fail(GMRF_E_INVALID_ARG, w + ": site " + std::to_string(i) +
+                                                    ": need 0 <= Y_i <= m_i < 2^21, Y_i integer");
+            if (mi == 0 && deg == 0)
+                return fail(GMRF_E_INVALID_ARG, w + ": site " + std::to_string(i) +
+                                                    " has no neighbours and no trials");
+            total += mi;
+        }
+        if (m->intercept && m->beta0_var == 0.0 && total == 0)
+            return fail(GMRF_E_INVALID_ARG, w + ": a flat beta0 prior needs some trials");
+        kappa.resize(n);
+        for (int64_t i = 0; i < n; ++i)
+            kappa[i] = y[i] - 0.5 * (double)trials[i];
+    }
+    const size_t need = chain_layout(g, p, nullptr, nullptr, binomial);
     if (!d_ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0)
-        return fail(GMRF_E_WORKSPACE, "chain_create: workspace NULL, misaligned or smaller than "
-                                      "gmrf_chain_footprint (" +
-                                          std::to_string(need) + " bytes)");
+        return fail(GMRF_E_WORKSPACE, w + ": workspace NULL, misaligned or smaller than the "
+                                          "footprint (" + std::to_string(need) + " bytes)");
     gmrf_chain *c = new gmrf_chain();
     c->g = g;
     c->prec = p;
@@ -1463,8 +1629,9 @@ int gmrf_chain_create(const gmrf_graph *g, const gmrf_model *m, const double *y,
     c->seed = seed;
     c->instance = instance;
     c->rank = rank;
+    c->binomial = binomial;
     c->lat_tile = is_lattice(g) ? default_tile(g->h) : 0;
-    chain_layout(g, p, static_cast<char *>(d_ws), c);
+    chain_layout(g, p, static_cast<char *>(d_ws), c, binomial);
 
     auto cleanup = [&](int rc) {
         delete c;
@@ -1489,8 +1656,10 @@ int gmrf_chain_create(const gmrf_graph *g, const gmrf_model *m, const double *y,
     if (e == hipSuccess)
         e = hipStreamSynchronize(stream);
     if (e != hipSuccess)
-        return cleanup(fail(GMRF_E_DEVICE, std::string("chain_create: ") + hipGetErrorString(e)));
-    int rc = upload_real(c, c->d_y, y, stream);
+        return cleanup(fail(GMRF_E_DEVICE, w + ": " + hipGetErrorString(e)));
+    int rc = upload_real(c, c->d_y, binomial ? kappa.data() : y, stream);
+    if (rc == GMRF_OK && binomial)
+        rc = upload_trials_layout(c, trials, stream);
     if (rc != GMRF_OK)
         return cleanup(rc);
     std::vector<double> zeros;
@@ -1503,6 +1672,30 @@ int gmrf_chain_create(const gmrf_graph *g, const gmrf_model *m, const double *y,
         return cleanup(rc);
     *out = c;
     return GMRF_OK;
+}
+
+int gmrf_chain_create(const gmrf_graph *g, const gmrf_model *m, const double *y, const double *x0,
+                      gmrf_precision p, uint64_t seed, uint32_t instance, void *d_ws,
+                      size_t ws_bytes, hipStream_t stream, gmrf_chain **out)
+{
+    clear_error();
+    return chain_create_impl("chain_create", g, m, y, nullptr, x0, p, seed, instance, d_ws,
+                             ws_bytes, stream, out);
+}
+
+int gmrf_chain_create_binomial(const gmrf_graph *g, const gmrf_model *m, const double *successes,
+                               const int32_t *trials, const double *x0, gmrf_precision p,
+                               uint64_t seed, uint32_t instance, void *d_ws, size_t ws_bytes,
+                               hipStream_t stream, gmrf_chain **out)
+{
+    clear_error();
+    if (!trials) {
+        if (out)
+            *out = nullptr;
+        return fail(GMRF_E_INVALID_ARG, "chain_create_binomial: trials are required");
+    }
+    return chain_create_impl("chain_create_binomial", g, m, successes, trials, x0, p, seed,
+                             instance, d_ws, ws_bytes, stream, out);
 }
 
 int gmrf_chain_destroy(gmrf_chain *c)
@@ -1771,7 +1964,7 @@ int gmrf_set_intercept(gmrf_chain *c, double beta0, hipStream_t stream)
         return fail(GMRF_E_INVALID_ARG, "set_intercept: NULL chain, non-finite beta0 or a chain "
                                         "without an intercept");
     hipLaunchKernelGGL(set_intercept_kernel, dim3(1), dim3(1), 0, stream, c->d_state, beta0,
-                       (double)c->g->h.n);
+                       (double)c->g->h.n, c->binomial ? 1 : 0);
     GMRF_HIP(hipGetLastError());
     return GMRF_OK;
 }

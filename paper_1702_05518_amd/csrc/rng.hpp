@@ -128,4 +128,145 @@ __device__ inline bool gamma_draw(GammaShape g, double rate, uint64_t seed, uint
     return false;
 }
 
+// ---------------------------------------------------------------------------
+// Polya-Gamma variates (Polson, Scott & Windle 2013, Sec. 4, after Devroye
+// 2009).  PG(1, c) = J*(1, |c|/2) / 4; J*(1, z) is drawn by rejection from
+// an envelope of two pieces split at t = 0.64 -- a truncated exponential on
+// (t, inf) and a truncated inverse Gaussian on (0, t) -- with the
+// alternating-series test of the J*(1) density.  PG(m, c) for an integer m is
+// the sum of m independent PG(1, c) terms.
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.141592653589793;
+constexpr double kPgT = 0.64;
+constexpr unsigned kPgMaxUniforms = 2048;   // uniforms available to one PG(1, c) draw
+constexpr int kPgMaxTerms = 200;            // series terms per acceptance test
+
+// Uniform stream of term j of one site's PG draw: uniform u is half (u & 1) of
+// the Philox block at counter (site, sweep, instance, 2^31 | j << 10 | u >> 1).
+struct PgStream {
+    uint64_t seed;
+    uint32_t site, sweep, instance, j;
+    uint32_t used;
+    bool exhausted;
+
+    __device__ double next()
+    {
+        const uint32_t u = used;
+        if (u >= kPgMaxUniforms) {
+            exhausted = true;
+            return 0.5;
+        }
+        used = u + 1;
+        const Words4 w = draw_words(seed, site, sweep, instance, 0x80000000u | (j << 10) | (u >> 1));
+        return (u & 1u) ? open_uniform_f64(w.w2, w.w3) : open_uniform_f64(w.w0, w.w1);
+    }
+    __device__ double normal()
+    {
+        const double u1 = next();
+        const double u2 = next();
+        return sqrt(-2.0 * log(u1)) * cos(kTwoPi * u2);
+    }
+};
+
+__device__ inline double std_normal_cdf(double x) { return 0.5 * erfc(-x / sqrt(2.0)); }
+
+// Term n of the alternating series of the J*(1) density (left form for
+// x <= t, right form for x > t).
+__device__ inline double pg_term(int n, double x)
+{
+    const double h = (double)n + 0.5;
+    if (x > kPgT)
+        return kPi * h * exp(-0.5 * h * h * kPi * kPi * x);
+    const double r = 2.0 / (kPi * x);
+    return kPi * h * r * sqrt(r) * exp(-2.0 * h * h / x);
+}
+
+// IG(1/z, 1) restricted to (0, t).  z < 1/t: the z = 0 law on (0, t) from a
+// normal tail beyond 1/sqrt(t) (1/X = (1 + t E1)^2 / t, E1^2 <= 2 E2 / t),
+// kept with probability exp(-z^2 X / 2).  Otherwise: Michael, Schucany &
+// Haas's transformation, repeated until X < t.
+__device__ inline double pg_left(double z, PgStream &s)
+{
+    const double t = kPgT;
+    if (z < 1.0 / t) {
+        for (;;) {
+            double e1, e2;
+            do {
+                e1 = -log(s.next());
+                e2 = -log(s.next());
+            } while (e1 * e1 > 2.0 * e2 / t && !s.exhausted);
+            const double x = t / ((1.0 + t * e1) * (1.0 + t * e1));
+            if (s.next() <= exp(-0.5 * z * z * x) || s.exhausted)
+                return x;
+        }
+    }
+    const double mu = 1.0 / z;
+    for (;;) {
+        const double nrm = s.normal();
+        const double y = nrm * nrm;
+        const double my = mu * y;
+        double x = mu + 0.5 * mu * my - 0.5 * mu * sqrt(4.0 * my + my * my);
+        if (s.next() > mu / (mu + x))
+            x = mu * mu / x;
+        if (x < t || s.exhausted)
+            return x;
+    }
+}
+
+// Envelope of PG(1, c) for one tilt: z = |c| / 2, rate K of the right piece
+// and the probability p / (p + q) of drawing from it.
+struct PgEnvelope {
+    double z, K, right;
+};
+
+__device__ inline PgEnvelope pg_envelope(double c)
+{
+    const double t = kPgT;
+    PgEnvelope e;
+    e.z = 0.5 * fabs(c);
+    e.K = kPi * kPi / 8.0 + 0.5 * e.z * e.z;
+    const double p = kPi / (2.0 * e.K) * exp(-e.K * t);
+    double q;
+    if (e.z == 0.0) {
+        q = 2.0 * erfc(1.0 / sqrt(2.0 * t));
+    } else {
+        const double a = std_normal_cdf((t * e.z - 1.0) / sqrt(t));
+        const double b = e.z < 700.0 ? exp(e.z) * std_normal_cdf(-(t * e.z + 1.0) / sqrt(t)) : 0.0;
+        q = 2.0 * (exp(-e.z) * a + b);
+    }
+    e.right = p / (p + q);
+    return e;
+}
+
+// PG(1, c) from the stream of term j; false when the stream ran out.
+__device__ inline bool pg1_draw(const PgEnvelope &e, uint64_t seed, uint32_t site, uint32_t sweep,
+                                uint32_t instance, uint32_t j, double *out)
+{
+    PgStream s{seed, site, sweep, instance, j, 0u, false};
+    for (;;) {
+        double x;
+        if (s.next() < e.right)
+            x = kPgT - log(s.next()) / e.K;
+        else
+            x = pg_left(e.z, s);
+        double S = pg_term(0, x);
+        const double Y = s.next() * S;
+        if (s.exhausted)
+            return false;
+        for (int n = 1; n <= kPgMaxTerms; ++n) {
+            if (n & 1) {
+                S -= pg_term(n, x);
+                if (Y <= S) {
+                    *out = 0.25 * x;
+                    return true;
+                }
+            } else {
+                S += pg_term(n, x);
+                if (Y > S)
+                    break;
+            }
+        }
+    }
+}
+
 } // namespace gmrf

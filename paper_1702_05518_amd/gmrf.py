@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "GMRF_OK", 1: "GMRF_E_INVALID_ARG", 2: "GMRF_E_GRAPH",
 FP64, FP32_ACC64 = 0, 1
 WITH_HYPER, CAPTURE = 1, 2
 NUM_TILES = 2
+GAUSSIAN, BINOMIAL = 0, 1
 PTR_HOST, PTR_DEVICE = 0, 1
 
 
@@ -42,8 +43,8 @@ class GraphDesc(C.Structure):
 class Model(C.Structure):
     _fields_ = [("a_tau", C.c_double), ("b_tau", C.c_double), ("a_lam", C.c_double),
                 ("b_lam", C.c_double), ("tau0", C.c_double), ("lam0", C.c_double),
-                ("burn_in", C.c_int64), ("intercept", C.c_int32), ("reserved", C.c_int32),
-                ("beta0", C.c_double)]
+                ("burn_in", C.c_int64), ("intercept", C.c_int32), ("likelihood", C.c_int32),
+                ("beta0", C.c_double), ("beta0_var", C.c_double)]
 
 
 _lib = None
@@ -64,6 +65,11 @@ _SIGS = {
                            C.POINTER(C.c_double), C.c_int, C.c_uint64, C.c_uint32, C.c_void_p,
                            C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "gmrf_chain_destroy": ([C.c_void_p], C.c_int),
+    "gmrf_binomial_footprint": ([C.c_void_p, C.c_int], C.c_size_t),
+    "gmrf_chain_create_binomial": ([C.c_void_p, C.POINTER(Model), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int,
+                                    C.c_uint64, C.c_uint32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                    C.POINTER(C.c_void_p)], C.c_int),
     "gmrf_sweep": ([C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p], C.c_int),
     "gmrf_sweep_timed": ([C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p,
                           C.POINTER(C.c_double)], C.c_int),
@@ -232,15 +238,21 @@ class Chain:
 
     def __init__(self, graph: Graph, y, *, precision=FP64, seed=1, instance=0, x0=None,
                  a_tau=1.0, b_tau=1.0, a_lam=1.0, b_lam=1.0, tau0=1.0, lam0=1.0, burn_in=0,
-                 intercept=False, beta0=0.0, stream=None):
+                 intercept=False, beta0=0.0, trials=None, beta0_var=0.0, stream=None):
+        """With ``trials`` (m_i) the chain is the binomial logit model and y
+        holds the successes Y_i; ``beta0_var`` is then the prior variance of
+        beta0 (0 = flat)."""
         L = lib()
         self.graph = graph
         self.n = graph.n
         self.precision = precision
         self.trace_buf = None
+        binom = trials is not None
         self.model = Model(a_tau, b_tau, a_lam, b_lam, tau0, lam0, int(burn_in),
-                           1 if intercept else 0, 0, float(beta0))
-        need = L.gmrf_chain_footprint(graph.handle, precision)
+                           1 if intercept else 0, BINOMIAL if binom else GAUSSIAN, float(beta0),
+                           float(beta0_var))
+        need = (L.gmrf_binomial_footprint(graph.handle, precision) if binom
+                else L.gmrf_chain_footprint(graph.handle, precision))
         if need == 0:
             raise GmrfError(E_INVALID_ARG, last_error())
         self.footprint = need
@@ -250,10 +262,19 @@ class Chain:
             raise ValueError("y must have n entries")
         xx = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
         h = C.c_void_p()
-        _check(L.gmrf_chain_create(graph.handle, C.byref(self.model), _p(yy, C.c_double),
-                                   _p(xx, C.c_double), precision, int(seed), int(instance),
-                                   C.c_void_p(self.ws.data_ptr()), need, _stream_handle(stream),
-                                   C.byref(h)))
+        if binom:
+            tt = np.ascontiguousarray(trials, dtype=np.int32)
+            if tt.size != self.n:
+                raise ValueError("trials must have n entries")
+            _check(L.gmrf_chain_create_binomial(
+                graph.handle, C.byref(self.model), _p(yy, C.c_double), _p(tt, C.c_int32),
+                _p(xx, C.c_double), precision, int(seed), int(instance),
+                C.c_void_p(self.ws.data_ptr()), need, _stream_handle(stream), C.byref(h)))
+        else:
+            _check(L.gmrf_chain_create(graph.handle, C.byref(self.model), _p(yy, C.c_double),
+                                       _p(xx, C.c_double), precision, int(seed), int(instance),
+                                       C.c_void_p(self.ws.data_ptr()), need,
+                                       _stream_handle(stream), C.byref(h)))
         self.handle = h
 
     def __del__(self):

@@ -193,6 +193,27 @@ def delaunay_workload(n: int, data_seed: int = 3, rho: float = 0.95, tau_true: f
                 rho=rho)
 
 
+def binomial_workload(n: int, data_seed: int = 5, rho: float = 0.995, tau_true: float = 4.0,
+                      beta0_true: float = 0.3, trials_median: float = 250.0,
+                      missing: float = 0.022):
+    """Binomial areal counts shaped like the paper's election example
+    (Sec. 3.2: n precincts, a Delaunay-like irregular adjacency, counts Y_i of
+    m_i trials, about 2.2% of areas without data).  Truth: gamma from the
+    proper CAR prior with precision tau_true (D - rho W), logit(pi_i) =
+    beta0_true + gamma_i; m_i = ceil(lognormal) with the given median (sd 0.8
+    on the log scale), m_i = 0 for the missing areas; Y_i ~ Bin(m_i, pi_i).
+    The coloring is left to the caller."""
+    pts, row_ptr, col = delaunay_graph(n, data_seed)
+    rng = np.random.Generator(np.random.PCG64(data_seed + 2000))
+    gamma = proper_car_prior_draw(row_ptr, col, tau_true, rho, rng)
+    eta = beta0_true + gamma
+    trials = np.ceil(np.exp(np.log(trials_median) + 0.8 * rng.standard_normal(n))).astype(np.int32)
+    trials[rng.random(n) < missing] = 0
+    y = rng.binomial(trials, 1.0 / (1.0 + np.exp(-eta))).astype(np.float64)
+    return dict(kind="csr", n=n, points=pts, row_ptr=row_ptr, col=col, y=y, trials=trials,
+                truth=eta, rho=rho)
+
+
 def smooth_field(points):
     """A smooth synthetic truth on the unit square (used where an exact prior
     draw would be too slow to generate for many graphs)."""
