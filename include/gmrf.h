@@ -33,7 +33,8 @@
  * made conditionally Gaussian by Polya-Gamma augmentation (Polson, Scott &
  * Windle 2013): with kappa_i = Y_i - m_i / 2, each site of the current color
  * first draws psi_i ~ PG(m_i, beta0 + x_i) from its old x_i (a sum of m_i
- * PG(1, .) terms, Devroye's alternating-series sampler), then
+ * PG(1, .) terms, Devroye's alternating-series sampler; the terms of a color
+ * are drawn by one launch in chunks of 2, then added per site), then
  *     Qii = tau * D_ii + psi_i,
  *     m_i = (kappa_i - psi_i beta0 + tau * rho * sum_{j~i} x_j) / Qii,
  * and after the sweep beta0 ~ N(sum(kappa - psi x) / P, 1/P),
@@ -197,9 +198,11 @@ int gmrf_chain_create(const gmrf_graph *g, const gmrf_model *m, const double *y,
                       size_t ws_bytes, hipStream_t stream, gmrf_chain **out);
 int gmrf_chain_destroy(gmrf_chain *c);
 
-/* Device workspace bytes of one binomial chain on a general graph g (adds the
- * trials array; color passes run one wavefront per site). */
-size_t gmrf_binomial_footprint(const gmrf_graph *g, gmrf_precision p);
+/* Device workspace bytes of one binomial chain on a general graph g with the
+ * given trials (host, n values m_i, original order): the Gaussian layout plus
+ * the trials, the Polya-Gamma term chunk tables and the chunk sums (about
+ * 6 bytes per trial).  Returns 0 and sets the error message on bad input. */
+size_t gmrf_binomial_footprint(const gmrf_graph *g, gmrf_precision p, const int32_t *trials);
 
 /* Create a binomial logit chain (Sec. 3.2) on a general graph: successes
  * (host, n values Y_i, integers) and trials (host, n values m_i, 0 <= Y_i <=
@@ -207,7 +210,7 @@ size_t gmrf_binomial_footprint(const gmrf_graph *g, gmrf_precision p);
  * one neighbour), x0 as for gmrf_chain_create, m->likelihood = GMRF_BINOMIAL,
  * m->beta0_var >= 0.  a_lam / b_lam / lam0 are not used by the sampler (lam
  * stays lam0).  Batches do not take binomial chains.  The workspace needs
- * gmrf_binomial_footprint bytes.  Synchronises.  Errors as gmrf_chain_create,
+ * gmrf_binomial_footprint(g, p, trials) bytes.  Synchronises.  Errors as gmrf_chain_create,
  * plus GMRF_E_INVALID_ARG for a lattice graph or invalid counts. */
 int gmrf_chain_create_binomial(const gmrf_graph *g, const gmrf_model *m, const double *successes,
                                const int32_t *trials, const double *x0, gmrf_precision p,

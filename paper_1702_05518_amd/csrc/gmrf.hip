@@ -85,7 +85,7 @@ constexpr int kPartials = 3;
 
 constexpr int kThreads = 256;   // CSR passes, finish and stats kernels
 
-__device__ __forceinline__ double wave_sum(double v)
+template <typename T> __device__ __forceinline__ T wave_sum(T v)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
@@ -634,6 +634,10 @@ template <typename Real> struct CsrArgs {
     Real *x;
     const Real *y;              // y (Gaussian) or kappa = Y - m/2 (binomial)
     const int *trials;          // binomial: m_i (slab order); NULL otherwise
+    const int *chunk_off;       // binomial: first term chunk of each slab position (n + 1)
+    const int *chunk_site;      // binomial: slab position of each chunk
+    double *chunk_sum;          // binomial: the sum of each chunk's PG(1, .) terms
+    PgEnvelope *env;            // binomial: each site's PG envelope for the current pass
 };
 
 // One site per thread.  The first kCsrBatch neighbours are gathered in one
@@ -745,14 +749,65 @@ __global__ __launch_bounds__(kThreads) void csr_batch_kernel(const CsrJob<Real> 
 
 // ---------------------------------------------------------------------------
 // general graphs, binomial logit model (Sec. 3.2 with Polya-Gamma
-// augmentation): one wavefront per site
+// augmentation): two launches per color
 // ---------------------------------------------------------------------------
-// Site p of the color slab: psi_p ~ PG(m_p, beta0 + x_p) with the site's old
-// x_p, its m_p PG(1, .) terms split over the 64 lanes (lane l takes terms l,
-// l + 64, ...; the lane sums are added in a fixed tree); then lane 0 draws
-// x_p from N(m, 1/Q) with Q = tau D_pp + psi_p and
-// m = (kappa_p - psi_p beta0 + tau rho sum_{j~p} x_j) / Q.
-constexpr int kBinomSites = kThreads / 64;      // sites per block
+// psi_p ~ PG(m_p, beta0 + x_p) is the sum of m_p PG(1, .) terms.  The terms
+// of a color's sites are cut into chunks of kPgChunk consecutive terms of one
+// site, and the term kernel runs one thread per chunk over the whole color
+// (so work is spread evenly whatever the m_p), writing each chunk's sum.  The
+// site kernel then runs one wavefront per site: the lanes add the site's
+// chunk sums (lane l takes chunks l, l + 64, ...; a fixed tree joins the
+// lanes) and lane 0 draws x_p from N(m, 1/Q), Q = tau D_pp + psi_p,
+// m = (kappa_p - psi_p beta0 + tau rho sum_{j~p} x_j) / Q.  Both read the
+// site's old x_p, which no launch of this color changes before the site
+// kernel.
+constexpr int kBinomSites = kThreads / 64;      // sites per block of the site kernel
+constexpr int kPgChunk = 2;                     // PG(1, .) terms per chunk
+#ifndef GMRF_PG_ENV_PREPASS
+#define GMRF_PG_ENV_PREPASS 1
+#endif
+constexpr bool kPgEnvPrepass = GMRF_PG_ENV_PREPASS;
+
+// The PG envelope of every site of a color slab (tilt beta0 + old x_p), so
+// that the term kernel's threads need not each evaluate its erfc and exp.
+template <typename Real, bool B0>
+__global__ __launch_bounds__(kThreads) void pg_env_kernel(CsrArgs<Real> ca, SweepArgs a, int lo,
+                                                          int cnt)
+{
+    const int p = lo + (int)blockIdx.x * kThreads + (int)threadIdx.x;
+    if (p >= lo + cnt)
+        return;
+    const double b0 = B0 ? a.st->beta0 : 0.0;
+    ca.env[p] = pg_envelope(b0 + (double)ca.x[p]);
+}
+
+template <typename Real, bool B0>
+__global__ __launch_bounds__(kThreads) void pg_chunk_kernel(CsrArgs<Real> ca, SweepArgs a, int q0,
+                                                            int nq)
+{
+    const int g = (int)blockIdx.x * kThreads + (int)threadIdx.x;
+    if (g >= nq)
+        return;
+    const int q = q0 + g;
+    const int p = ca.chunk_site[q];
+    const int m = ca.trials[p];
+    const int j0 = (q - ca.chunk_off[p]) * kPgChunk;
+    const int j1 = min(j0 + kPgChunk, m);
+    const unsigned t = (unsigned)a.st->sweep;
+    const double b0 = B0 ? a.st->beta0 : 0.0;
+    const unsigned id = (unsigned)ca.orig[p];
+    const PgEnvelope env = kPgEnvPrepass ? ca.env[p] : pg_envelope(b0 + (double)ca.x[p]);
+    double sum = 0.0;
+    bool ok = true;
+    for (int j = j0; j < j1; ++j) {
+        double v = 0.0;
+        ok = pg1_draw(env, a.seed, id, t, a.instance, (unsigned)j, &v) && ok;
+        sum += v;
+    }
+    if (!ok)
+        atomicOr(&a.st->status, kStatusGamma);
+    ca.chunk_sum[q] = sum;
+}
 
 template <typename Real, bool B0>
 __global__ __launch_bounds__(kThreads) void csr_binomial_pass_kernel(CsrArgs<Real> ca, SweepArgs a,
@@ -766,26 +821,20 @@ __global__ __launch_bounds__(kThreads) void csr_binomial_pass_kernel(CsrArgs<Rea
     const int p = lo + (int)blockIdx.x * kBinomSites + ((int)threadIdx.x >> 6);
     Red rd;
     if (p < lo + cnt) {     // uniform across the wavefront
-        const int m = ca.trials[p];
         const unsigned id = (unsigned)ca.orig[p];
-        const Real xold = ca.x[p];
-        const PgEnvelope env = pg_envelope(b0 + (double)xold);
         double part = 0.0;
-        bool ok = true;
-        for (int j = lane; j < m; j += 64) {
-            double v = 0.0;
-            ok = pg1_draw(env, a.seed, id, t, a.instance, (unsigned)j, &v) && ok;
-            part += v;
-        }
-        if (!ok)
-            atomicOr(&a.st->status, kStatusGamma);
+        for (int k = ca.chunk_off[p] + lane; k < ca.chunk_off[p + 1]; k += 64)
+            part += ca.chunk_sum[k];
         const double psi = __shfl(wave_sum(part), 0, 64);
+        // neighbour sum over the lanes (lane l takes neighbours l, l + 64, ...)
+        const int e0 = ca.row_ptr[p], e1 = ca.row_ptr[p + 1];
+        const int deg = e1 - e0;
+        Real nsum = (Real)0;
+        for (int e = e0 + lane; e < e1; e += 64)
+            nsum += ca.x[ca.col[e]];
+        const Real s = __shfl(wave_sum(nsum), 0, 64);
+        Real xn = (Real)0;
         if (lane == 0) {
-            const int e0 = ca.row_ptr[p], e1 = ca.row_ptr[p + 1];
-            const int deg = e1 - e0;
-            Real s = (Real)0;
-            for (int e = e0; e < e1; ++e)
-                s += ca.x[ca.col[e]];
             const double kappa = (double)ca.y[p];
             const Real Q = fma(tau, (Real)deg, (Real)psi);
             Real inv_q, isd;
@@ -798,17 +847,22 @@ __global__ __launch_bounds__(kThreads) void csr_binomial_pass_kernel(CsrArgs<Rea
             }
             const Real beff = (Real)(kappa - psi * b0);
             const Real z = site_normal<Real>(draw_words(a.seed, id, t, a.instance, 0u));
-            const Real xn = fma(z, isd, fma(tau_rho, s, beff) * inv_q);
+            xn = fma(z, isd, fma(tau_rho, s, beff) * inv_q);
             ca.x[p] = xn;
-            const double xd = (double)xn;
-            double edge = 0.0;
-            for (int e = e0; e < e1; ++e) {
-                const int j = ca.col[e];
-                if (j < lo) {      // lower color: already final this sweep
-                    const double d = xd - (double)ca.x[j];
-                    edge += d * d;
-                }
+        }
+        // edge terms of the lower-colored neighbours (already final this sweep)
+        const double xd = (double)__shfl(xn, 0, 64);
+        double edge = 0.0;
+        for (int e = e0 + lane; e < e1; e += 64) {
+            const int j = ca.col[e];
+            if (j < lo) {
+                const double d = xd - (double)ca.x[j];
+                edge += d * d;
             }
+        }
+        edge = wave_sum(edge);
+        if (lane == 0) {
+            const double kappa = (double)ca.y[p];
             rd.q = (1.0 - a.rho) * (double)deg * xd * xd + a.rho * edge;
             rd.sse = psi;
             rd.rsum = kappa - psi * xd;
@@ -900,6 +954,11 @@ struct gmrf_chain {
     int lat_tile = 0;                 // lattice tile shape (index into kTiles)
     bool binomial = false;            // binomial logit likelihood (general graphs only)
     int *d_trials = nullptr;          // binomial: m_i in slab order
+    int *d_chunk_off = nullptr;       // binomial: PG term chunk tables (see pg_chunk_kernel)
+    int *d_chunk_site = nullptr;
+    double *d_chunk_sum = nullptr;
+    PgEnvelope *d_env = nullptr;
+    std::vector<int> color_chunk;     // binomial: first chunk of each color (k + 1)
     std::vector<int> pass_blocks;     // CSR: blocks per color pass
     uint64_t host_sweeps = 0;         // sweeps enqueued (host view)
     hipStream_t capture_stream = nullptr;
@@ -979,7 +1038,7 @@ int max_lattice_blocks(const HostGraph &h)
 // binomial chain adds the trials array, and its color passes take
 // kBinomSites sites per block.
 size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chain *c,
-                    bool binomial)
+                    bool binomial, int64_t n_chunks = 0)
 {
     const int64_t n = g->h.n;
     const size_t rs = real_size(p);
@@ -1013,8 +1072,16 @@ size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chai
     char *part = take(8 * kPartials * (size_t)std::max(reserve, 1));
     char *stats = take(16 * n);
     char *trials = binomial ? take(4 * n) : nullptr;
+    char *chunk_off = binomial ? take(4 * (size_t)(n + 1)) : nullptr;
+    char *chunk_site = binomial ? take(4 * (size_t)std::max<int64_t>(n_chunks, 1)) : nullptr;
+    char *chunk_sum = binomial ? take(8 * (size_t)std::max<int64_t>(n_chunks, 1)) : nullptr;
+    char *env = binomial ? take(sizeof(PgEnvelope) * (size_t)n) : nullptr;
     if (c) {
         c->d_trials = reinterpret_cast<int *>(trials);
+        c->d_chunk_off = reinterpret_cast<int *>(chunk_off);
+        c->d_chunk_site = reinterpret_cast<int *>(chunk_site);
+        c->d_chunk_sum = reinterpret_cast<double *>(chunk_sum);
+        c->d_env = reinterpret_cast<PgEnvelope *>(env);
         c->d_state = reinterpret_cast<DevState *>(st);
         c->d_x[0] = x0;
         c->d_x[1] = x1;
@@ -1081,6 +1148,10 @@ template <typename Real> CsrArgs<Real> csr_args(const gmrf_chain *c)
     ca.x = static_cast<Real *>(c->d_x[0]);
     ca.y = static_cast<const Real *>(c->d_y);
     ca.trials = c->d_trials;
+    ca.chunk_off = c->d_chunk_off;
+    ca.chunk_site = c->d_chunk_site;
+    ca.chunk_sum = c->d_chunk_sum;
+    ca.env = c->d_env;
     return ca;
 }
 
@@ -1134,6 +1205,30 @@ void launch_csr(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent
             continue;
         const int lo = h.slab_offsets[col], cnt = h.slab_offsets[col + 1] - lo;
         hipEvent_t e0 = slot == 0 ? ev0 : nullptr, e1 = col == last ? ev1 : nullptr;
+        if (c->binomial) {
+            const int q0 = c->color_chunk[col], nq = c->color_chunk[col + 1] - q0;
+            if (nq > 0 && kPgEnvPrepass) {
+                auto ek = c->model.intercept ? pg_env_kernel<Real, true> : pg_env_kernel<Real, false>;
+                const int eb = (cnt + kThreads - 1) / kThreads;
+                if (e0)
+                    hipExtLaunchKernelGGL(ek, dim3(eb), dim3(kThreads), 0, s, e0, nullptr, 0, ca,
+                                          a, lo, cnt);
+                else
+                    hipLaunchKernelGGL(ek, dim3(eb), dim3(kThreads), 0, s, ca, a, lo, cnt);
+                e0 = nullptr;
+            }
+            if (nq > 0) {
+                auto tk = c->model.intercept ? pg_chunk_kernel<Real, true>
+                                             : pg_chunk_kernel<Real, false>;
+                const int tb = (nq + kThreads - 1) / kThreads;
+                if (e0)
+                    hipExtLaunchKernelGGL(tk, dim3(tb), dim3(kThreads), 0, s, e0, nullptr, 0, ca,
+                                          a, q0, nq);
+                else
+                    hipLaunchKernelGGL(tk, dim3(tb), dim3(kThreads), 0, s, ca, a, q0, nq);
+                e0 = nullptr;
+            }
+        }
         auto kern = c->binomial ? (c->model.intercept ? csr_binomial_pass_kernel<Real, true>
                                                       : csr_binomial_pass_kernel<Real, false>)
                                 : (c->model.intercept ? csr_pass_kernel<Real, true>
@@ -1240,13 +1335,29 @@ int upload_doubles_layout(const gmrf_chain *c, double *dst, const double *x, hip
     return GMRF_OK;
 }
 
-int upload_trials_layout(const gmrf_chain *c, const int32_t *trials, hipStream_t s)
+// Upload m_i in slab order and build the PG term chunk tables: chunk_off[p]
+// = first chunk of slab position p (chunks of a color are contiguous because
+// its slab is), chunk_site[q] = the slab position chunk q belongs to.
+int upload_trials_layout(gmrf_chain *c, const int32_t *trials, hipStream_t s)
 {
-    const int64_t n = c->g->h.n;
-    std::vector<int32_t> buf(n);
+    const HostGraph &h = c->g->h;
+    const int64_t n = h.n;
+    std::vector<int32_t> buf(n), off(n + 1, 0), site;
+    for (int64_t p = 0; p < n; ++p) {
+        buf[p] = trials[h.orig_of_slab[p]];
+        off[p + 1] = off[p] + (buf[p] + kPgChunk - 1) / kPgChunk;
+    }
+    site.resize(std::max<int64_t>(off[n], 1));
     for (int64_t p = 0; p < n; ++p)
-        buf[p] = trials[c->g->h.orig_of_slab[p]];
+        for (int q = off[p]; q < off[p + 1]; ++q)
+            site[q] = (int32_t)p;
+    c->color_chunk.assign(h.k + 1, 0);
+    for (int32_t col = 0; col <= h.k; ++col)
+        c->color_chunk[col] = off[h.slab_offsets[col]];
     GMRF_HIP(hipMemcpyAsync(c->d_trials, buf.data(), 4 * n, hipMemcpyHostToDevice, s));
+    GMRF_HIP(hipMemcpyAsync(c->d_chunk_off, off.data(), 4 * (n + 1), hipMemcpyHostToDevice, s));
+    GMRF_HIP(hipMemcpyAsync(c->d_chunk_site, site.data(), 4 * site.size(), hipMemcpyHostToDevice,
+                            s));
     GMRF_HIP(hipStreamSynchronize(s));
     return GMRF_OK;
 }
@@ -1543,13 +1654,28 @@ size_t gmrf_chain_footprint(const gmrf_graph *g, gmrf_precision p)
     return chain_layout(g, p, nullptr, nullptr, false);
 }
 
-size_t gmrf_binomial_footprint(const gmrf_graph *g, gmrf_precision p)
+// Number of PG term chunks of a binomial chain (trials in original order).
+static int64_t count_chunks(const gmrf_graph *g, const int32_t *trials)
 {
-    if (!g || (p != GMRF_FP64 && p != GMRF_FP32_ACC64) || is_lattice(g)) {
-        set_error("binomial_footprint: NULL or lattice graph, or bad precision");
+    int64_t nc = 0;
+    for (int64_t i = 0; i < g->h.n; ++i)
+        nc += (std::max(trials[i], 0) + kPgChunk - 1) / kPgChunk;
+    return nc;
+}
+
+size_t gmrf_binomial_footprint(const gmrf_graph *g, gmrf_precision p, const int32_t *trials)
+{
+    clear_error();
+    if (!g || (p != GMRF_FP64 && p != GMRF_FP32_ACC64) || is_lattice(g) || !trials) {
+        set_error("binomial_footprint: NULL or lattice graph, bad precision or NULL trials");
         return 0;
     }
-    return chain_layout(g, p, nullptr, nullptr, true);
+    const int64_t nc = count_chunks(g, trials);
+    if (nc > INT32_MAX) {
+        set_error("binomial_footprint: too many trials in total");
+        return 0;
+    }
+    return chain_layout(g, p, nullptr, nullptr, true, nc);
 }
 
 // Common body of the two chain constructors.  binomial: y holds the
@@ -1618,7 +1744,10 @@ static int chain_create_impl(const char *who, const gmrf_graph *g, const gmrf_mo
         for (int64_t i = 0; i < n; ++i)
             kappa[i] = y[i] - 0.5 * (double)trials[i];
     }
-    const size_t need = chain_layout(g, p, nullptr, nullptr, binomial);
+    const int64_t n_chunks = binomial ? count_chunks(g, trials) : 0;
+    if (n_chunks > INT32_MAX)
+        return fail(GMRF_E_INVALID_ARG, w + ": too many trials in total");
+    const size_t need = chain_layout(g, p, nullptr, nullptr, binomial, n_chunks);
     if (!d_ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0)
         return fail(GMRF_E_WORKSPACE, w + ": workspace NULL, misaligned or smaller than the "
                                           "footprint (" + std::to_string(need) + " bytes)");
@@ -1631,7 +1760,7 @@ static int chain_create_impl(const char *who, const gmrf_graph *g, const gmrf_mo
     c->rank = rank;
     c->binomial = binomial;
     c->lat_tile = is_lattice(g) ? default_tile(g->h) : 0;
-    chain_layout(g, p, static_cast<char *>(d_ws), c, binomial);
+    chain_layout(g, p, static_cast<char *>(d_ws), c, binomial, n_chunks);
 
     auto cleanup = [&](int rc) {
         delete c;

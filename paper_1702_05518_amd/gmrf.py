@@ -65,7 +65,7 @@ _SIGS = {
                            C.POINTER(C.c_double), C.c_int, C.c_uint64, C.c_uint32, C.c_void_p,
                            C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
     "gmrf_chain_destroy": ([C.c_void_p], C.c_int),
-    "gmrf_binomial_footprint": ([C.c_void_p, C.c_int], C.c_size_t),
+    "gmrf_binomial_footprint": ([C.c_void_p, C.c_int, C.POINTER(C.c_int32)], C.c_size_t),
     "gmrf_chain_create_binomial": ([C.c_void_p, C.POINTER(Model), C.POINTER(C.c_double),
                                     C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int,
                                     C.c_uint64, C.c_uint32, C.c_void_p, C.c_size_t, C.c_void_p,
@@ -251,8 +251,13 @@ class Chain:
         self.model = Model(a_tau, b_tau, a_lam, b_lam, tau0, lam0, int(burn_in),
                            1 if intercept else 0, BINOMIAL if binom else GAUSSIAN, float(beta0),
                            float(beta0_var))
-        need = (L.gmrf_binomial_footprint(graph.handle, precision) if binom
-                else L.gmrf_chain_footprint(graph.handle, precision))
+        if binom:
+            tt = np.ascontiguousarray(trials, dtype=np.int32)
+            if tt.size != self.n:
+                raise ValueError("trials must have n entries")
+            need = L.gmrf_binomial_footprint(graph.handle, precision, _p(tt, C.c_int32))
+        else:
+            need = L.gmrf_chain_footprint(graph.handle, precision)
         if need == 0:
             raise GmrfError(E_INVALID_ARG, last_error())
         self.footprint = need
@@ -263,9 +268,6 @@ class Chain:
         xx = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
         h = C.c_void_p()
         if binom:
-            tt = np.ascontiguousarray(trials, dtype=np.int32)
-            if tt.size != self.n:
-                raise ValueError("trials must have n entries")
             _check(L.gmrf_chain_create_binomial(
                 graph.handle, C.byref(self.model), _p(yy, C.c_double), _p(tt, C.c_int32),
                 _p(xx, C.c_double), precision, int(seed), int(instance),
