@@ -201,15 +201,15 @@ def bench_batch(torch, gmrf, inputs, args):
 
 
 def bench_serve(torch, gmrf, inputs, args):
-    """Serving: Poisson arrivals (mean 200 jobs/s for 2 s) of 1000-sweep jobs on
-    Delaunay graphs of the irregular workload's sizes (n = 15,000 with
-    probability 0.98, n = 1,000,000 with probability 0.02, so the offered load
-    stays below capacity), FP32 with FP64 accumulators, continuous batching;
-    against the FP64 plain form (one standalone chain at a time) on the first
-    40 arrivals.  Prints one JSON line."""
+    """Serving: Poisson arrivals of 1000-sweep jobs on Delaunay graphs of the
+    irregular workload's sizes (n = 15,000 with probability 0.98, n =
+    1,000,000 with probability 0.02), FP32 with FP64 accumulators, continuous
+    batching; arrival rates 50 .. 800 jobs/s, 2 s of arrivals each, for the
+    latency-against-load curve (the 200/s point is the headline); against the
+    FP64 plain form (one standalone chain at a time) on the first 40 arrivals
+    of the 200/s stream.  Prints one JSON line."""
     from paper_1702_05518_amd import serve
 
-    rng = np.random.Generator(np.random.PCG64(7))
     pool = []
     for n, ds in [(15000, 11), (15000, 12), (15000, 13), (1_000_000, 14)]:
         wl = inputs.delaunay_workload(n, data_seed=ds, rho=0.95)
@@ -217,35 +217,50 @@ def bench_serve(torch, gmrf, inputs, args):
         pool.append((gmrf.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color,
                                 num_colors=k, rho=0.95), wl["y"]))
     log("[bench] serve: graph pool ready")
-    t, jobs = 0.0, []
-    while True:
-        t += rng.exponential(1.0 / 200.0)
-        if t > 2.0:
-            break
-        g, y = pool[3] if rng.random() < 0.02 else pool[int(rng.integers(0, 3))]
-        jobs.append(serve.Job(len(jobs), g, y, seed=1000 + len(jobs), instance=len(jobs),
-                              nsweeps=1000, arrival=t, precision=gmrf.FP32_ACC64))
-    free, _ = torch.cuda.mem_get_info()
-    server = serve.Server(budget_bytes=int(0.5 * free), step_sweeps=10, max_active=1024)
-    wall = server.run(jobs, realtime=True)
-    sites = sum(j.sites * j.nsweeps for j in server.finished)
-    served = serve.latency_summary(server.finished)
-    log(f"[bench] serve: {len(jobs)} jobs in {wall:.2f} s, p50 {served['p50_ms']:.1f} ms")
+
+    def arrivals(rate, seed):
+        rng = np.random.Generator(np.random.PCG64(seed))
+        t, jobs = 0.0, []
+        while True:
+            t += rng.exponential(1.0 / rate)
+            if t > 2.0:
+                return jobs
+            g, y = pool[3] if rng.random() < 0.02 else pool[int(rng.integers(0, 3))]
+            jobs.append(serve.Job(len(jobs), g, y, seed=1000 + len(jobs), instance=len(jobs),
+                                  nsweeps=1000, arrival=t, precision=gmrf.FP32_ACC64))
+
+    curve, head, head_jobs = [], None, None
+    for rate in (50, 100, 200, 400, 800):
+        jobs = arrivals(rate, 7 if rate == 200 else 7 + rate)
+        offered = sum(j.sites * j.nsweeps for j in jobs) / 2.0
+        free, _ = torch.cuda.mem_get_info()
+        server = serve.Server(budget_bytes=int(0.5 * free), step_sweeps=10, max_active=1024)
+        wall = server.run(jobs, realtime=True)
+        sites = sum(j.sites * j.nsweeps for j in server.finished)
+        point = dict(serve.latency_summary(server.finished), rate_per_s=rate,
+                     offered_site_updates_per_s=offered, site_updates_per_s=sites / wall,
+                     wall_s=wall, batch_rebuilds=server.rebuilds)
+        curve.append(point)
+        log(f"[bench] serve {rate}/s: {len(jobs)} jobs in {wall:.2f} s, p50 "
+            f"{point['p50_ms']:.1f} ms, p99 {point['p99_ms']:.1f} ms")
+        if rate == 200:
+            head, head_jobs = point, jobs
     plain_jobs = [serve.Job(j.job_id, j.graph, j.y, j.seed, j.instance, j.nsweeps, j.arrival,
-                            gmrf.FP64) for j in jobs[:40]]
+                            gmrf.FP64) for j in head_jobs[:40]]
     wall_plain = serve.serve_plain(plain_jobs, precision=gmrf.FP64, realtime=True)
     plain = serve.latency_summary(plain_jobs)
     plain_sites = sum(j.sites * j.nsweeps for j in plain_jobs)
     line = {
         "metric": "p50/p99 solve latency (served, continuous batching)",
-        "value": sites / wall, "unit": "site-updates/s", "n_gpus": 1, "steps": 1000,
-        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "value": head["site_updates_per_s"], "unit": "site-updates/s", "n_gpus": 1,
+        "steps": 1000, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "Poisson arrivals 200/s for 2 s of 1000-sweep jobs, Delaunay "
                                "n=15k (p 0.98) or 1M (p 0.02), FP32 + FP64 accumulators, "
                                "continuous batching every 10 sweeps",
-                   "jobs": len(jobs), "batch_rebuilds": server.rebuilds},
-        "served_fp32": served,
+                   "jobs": head["jobs"], "batch_rebuilds": head["batch_rebuilds"]},
+        "served_fp32": {k: head[k] for k in ("p50_ms", "p99_ms", "mean_ms", "jobs")},
+        "load_curve": curve,
         "plain_fp64_first40": dict(plain, site_updates_per_s=plain_sites / wall_plain),
     }
     print(json.dumps(line), flush=True)
