@@ -60,12 +60,15 @@ def timed_sweeps(torch, chain, steps, capture):
     return e0.elapsed_time(e1) / 1e3
 
 
-def kernel_time(torch, chain, launches):
-    """Average duration in seconds of the lattice sweep kernel: the library
-    records HIP events on the launch stream around that kernel of each of
-    `launches` sweeps (the one-block finish kernel is outside the brackets)."""
+def plain_timed_region(torch, chain, steps):
+    """The timed region with plain launches: `steps` sweeps in which every
+    sweep kernel is bracketed by HIP events that its dispatch records on the
+    launch stream.  Returns (seconds for the `steps` sweeps, from the first
+    sweep kernel's start to the last sweep's end; average duration in
+    seconds of the sweep kernel over the same launches)."""
     torch.cuda.synchronize()
-    return chain.sweep_timed(launches, hyper=True) / launches / 1e3
+    k_ms, span_ms = chain.sweep_timed(steps, hyper=True, span=True)
+    return span_ms / 1e3, k_ms / steps / 1e3
 
 
 def solve_latencies(torch, chain, sweeps, reps):
@@ -470,11 +473,10 @@ def main():
         chain.sweep(args.warmup, hyper=True)
         torch.cuda.synchronize()
         log(f"[bench] {name}: timing {args.steps} sweeps")
-        t_plain = timed_sweeps(torch, chain, args.steps, capture=False)
+        t_plain, k_avg = plain_timed_region(torch, chain, args.steps)
         chain.sweep(args.steps, hyper=True, capture=True)      # record the graph once
         torch.cuda.synchronize()
         t_graph = timed_sweeps(torch, chain, args.steps, capture=True)
-        k_avg = kernel_time(torch, chain, 200)
         lat = solve_latencies(torch, chain, 1000, args.reps)
         mean, var, nacc = chain.posterior_stats()
         x, tau, lam, sw = chain.get_state()

@@ -229,12 +229,15 @@ int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t strea
 /* Profiling form of gmrf_sweep (plain launches, no capture): the same sweeps,
  * with a pair of HIP events that the dispatches themselves record at the
  * start and the end of the sweep kernels of every sweep (the lattice kernel,
- * or the first to the last color pass of a general graph), excluding the
- * one-block finish kernel that sums the reductions and draws tau / lam.
- * Synchronises and returns in *kernel_ms the summed event time of the sweep
- * kernels over the nsweeps sweeps. */
+ * or the first to the last kernel of the color passes of a general graph),
+ * excluding the one-block finish kernel that sums the reductions and draws
+ * the hyperparameters.  Synchronises and returns in *kernel_ms the summed
+ * event time of the sweep kernels over the nsweeps sweeps and, if span_ms is
+ * not NULL, the elapsed time from the start of the first sweep kernel to the
+ * end of the last sweep's finish kernel (all events are created before the
+ * first launch, so host work is not in the span). */
 int gmrf_sweep_timed(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream,
-                     double *kernel_ms);
+                     double *kernel_ms, double *span_ms);
 
 /* Draw beta0 (with an intercept), tau and lam (Sec. 3.1 conjugate
  * conditionals) from the reductions of the last completed sweep, with that

@@ -1878,15 +1878,19 @@ int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t strea
 }
 
 int gmrf_sweep_timed(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream,
-                     double *kernel_ms)
+                     double *kernel_ms, double *span_ms)
 {
     clear_error();
     if (!c || nsweeps < 0 || !kernel_ms || (flags & ~GMRF_WITH_HYPER))
         return fail(GMRF_E_INVALID_ARG, "sweep_timed: NULL chain / output, negative count or "
                                         "unsupported flag");
     *kernel_ms = 0.0;
+    if (span_ms)
+        *span_ms = 0.0;
     const SweepArgs a = make_args(c, flags);
-    std::vector<hipEvent_t> ev(2 * (size_t)nsweeps, nullptr);
+    // events are created before the first launch, so the span covers only
+    // device work: first sweep kernel's start to the end of the last finish
+    std::vector<hipEvent_t> ev(2 * (size_t)nsweeps + 1, nullptr);
     int rc = GMRF_OK;
     for (auto &e : ev) {
         const hipError_t he = hipEventCreate(&e);
@@ -1895,13 +1899,15 @@ int gmrf_sweep_timed(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t
             break;
         }
     }
-    if (rc == GMRF_OK) {
+    if (rc == GMRF_OK && nsweeps > 0) {
         hipError_t he = hipSuccess;
         for (int i = 0; i < nsweeps && he == hipSuccess; ++i) {
             launch_sweep_kernels(c, a, stream, ev[2 * i], ev[2 * i + 1]);
             launch_finish(a, stream);
             he = hipGetLastError();
         }
+        if (he == hipSuccess)
+            he = hipEventRecord(ev[2 * (size_t)nsweeps], stream);
         if (he == hipSuccess)
             he = hipStreamSynchronize(stream);
         double total = 0.0;
@@ -1910,10 +1916,16 @@ int gmrf_sweep_timed(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t
             he = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
             total += ms;
         }
-        if (he != hipSuccess)
+        float span = 0.0f;
+        if (he == hipSuccess)
+            he = hipEventElapsedTime(&span, ev[0], ev[2 * (size_t)nsweeps]);
+        if (he != hipSuccess) {
             rc = fail(GMRF_E_DEVICE, std::string("sweep_timed: ") + hipGetErrorString(he));
-        else
+        } else {
             *kernel_ms = total;
+            if (span_ms)
+                *span_ms = span;
+        }
         c->host_sweeps += (uint64_t)nsweeps;
     }
     for (auto &e : ev)

@@ -72,7 +72,7 @@ _SIGS = {
                                     C.POINTER(C.c_void_p)], C.c_int),
     "gmrf_sweep": ([C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p], C.c_int),
     "gmrf_sweep_timed": ([C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p,
-                          C.POINTER(C.c_double)], C.c_int),
+                          C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "gmrf_hyper_update": ([C.c_void_p, C.c_void_p], C.c_int),
     "gmrf_set_hyper": ([C.c_void_p, C.c_double, C.c_double, C.c_void_p], C.c_int),
     "gmrf_posterior_stats": ([C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64),
@@ -291,13 +291,16 @@ class Chain:
         _check(lib().gmrf_sweep(self.handle, int(nsweeps), flags, _stream_handle(stream)))
         return self
 
-    def sweep_timed(self, nsweeps: int, hyper: bool = True, stream=None) -> float:
+    def sweep_timed(self, nsweeps: int, hyper: bool = True, stream=None, span=False):
         """Run nsweeps sweeps (plain launches) and return the summed duration in
-        ms of their sweep kernels, from HIP events around those kernels."""
-        ms = C.c_double()
+        ms of their sweep kernels, from HIP events the dispatches record around
+        those kernels; with span=True return (kernel_ms, span_ms), span_ms
+        being the device time from the first sweep kernel's start to the end
+        of the last sweep."""
+        ms, sp = C.c_double(), C.c_double()
         _check(lib().gmrf_sweep_timed(self.handle, int(nsweeps), WITH_HYPER if hyper else 0,
-                                      _stream_handle(stream), C.byref(ms)))
-        return ms.value
+                                      _stream_handle(stream), C.byref(ms), C.byref(sp)))
+        return (ms.value, sp.value) if span else ms.value
 
     def hyper_update(self, stream=None):
         _check(lib().gmrf_hyper_update(self.handle, _stream_handle(stream)))

@@ -329,7 +329,8 @@ def test_sweep_timed_equals_sweep(G, orc, kind):
     a = G.Chain(g, wl["y"], seed=4)
     b = G.Chain(g, wl["y"], seed=4)
     a.sweep(6)
-    ms = b.sweep_timed(6)
-    assert ms > 0.0
+    ms, span = b.sweep_timed(6, span=True)
+    assert 0.0 < ms < span
     sa, sb = a.get_state(), b.get_state()
     assert np.array_equal(sa[0], sb[0]) and sa[1:] == sb[1:]
+    assert b.sweep_timed(0, span=True) == (0.0, 0.0)
