@@ -93,3 +93,45 @@ def test_batch_errors(G):
         G.Batch([a[0], b[1]])          # mixed precision
     with pytest.raises(G.GmrfError):
         G.Batch([])
+
+
+def test_full_512_instance_mix(G, orc):
+    """The benchmark's batch: all 512 instances (lattices with side 32..512,
+    Delaunay graphs with 1k..50k sites).  FP32: every chain of the batch is
+    bitwise its standalone self.  FP64: sampled chains of the batch match the
+    oracle after two sweeps."""
+    mix = inputs.batch_mix(512, data_seed=4)
+    graphs = []
+    for wl in mix:
+        if wl["kind"] == "lattice":
+            graphs.append(G.Graph(lattice=(wl["rows"], wl["cols"], wl["stencil"])))
+        else:
+            wl["color"], wl["k"] = G.greedy_coloring(wl["row_ptr"], wl["col"])
+            graphs.append(G.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=wl["color"],
+                                  num_colors=wl["k"], rho=wl["rho"]))
+    solo = [G.Chain(g, wl["y"], precision=G.FP32_ACC64, seed=1 + i, instance=i)
+            for i, (g, wl) in enumerate(zip(graphs, mix))]
+    for c in solo:
+        c.sweep(3)
+    mixed = [G.Chain(g, wl["y"], precision=G.FP32_ACC64, seed=1 + i, instance=i)
+             for i, (g, wl) in enumerate(zip(graphs, mix))]
+    G.Batch(mixed).sweep(3, capture=True)
+    for a, b in zip(solo, mixed):
+        xa, ta, la, _ = a.get_state()
+        xb, tb, lb, _ = b.get_state()
+        assert np.array_equal(xa, xb) and ta == tb and la == lb
+    del solo, mixed
+    picks = [0, 200, 256, 511]
+    chains = [G.Chain(graphs[i], mix[i]["y"], seed=1 + i, instance=i) for i in range(512)]
+    G.Batch(chains).sweep(2)
+    for i in picks:
+        wl = mix[i]
+        if wl["kind"] == "lattice":
+            rp, cl = inputs.lattice_csr(wl["rows"], wl["cols"], wl["stencil"])
+        else:
+            rp, cl = wl["row_ptr"], wl["col"]
+        oc = orc.Chain(rp, cl, wl["color"], wl["y"], rho=wl["rho"], seed=1 + i, instance=i)
+        oc.sweeps(2, nthreads=8)
+        x, tau, lam, _ = chains[i].get_state()
+        assert np.max(np.abs(x - oc.x)) <= 1e-12 * np.max(np.abs(oc.x))
+        assert abs(tau / oc.tau - 1) <= 1e-12 and abs(lam / oc.lam - 1) <= 1e-12

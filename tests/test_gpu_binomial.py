@@ -152,3 +152,17 @@ def test_binomial_argument_errors(G):
     ch = G.Chain(g, wl["y"], trials=wl["trials"], intercept=True, beta0_var=1000.0)
     with pytest.raises(G.GmrfError):
         G.Batch([ch])
+
+
+def test_binomial_full_size_one_sweep(G, orc):
+    """The benchmark's binomial workload (n = 14,926, ~5 million trials), one
+    FP64 sweep with the hyperparameter draws, against the oracle."""
+    wl = inputs.binomial_workload(14926, data_seed=5)
+    wl["color"], wl["k"] = G.greedy_coloring(wl["row_ptr"], wl["col"])
+    g, ch, oc = pair(G, orc, wl, seed=1)
+    ch.sweep(1)
+    oc.sweeps(1, nthreads=8)
+    x, tau, _, _ = ch.get_state()
+    q, spsi = ch.last_reductions()
+    assert rel(x, oc.x) <= RTOL64 and rel(spsi, oc.sse) <= RTOL64 and rel(q, oc.q) <= RTOL64
+    assert rel(tau, oc.tau) <= RTOL64 and rel(ch.beta0, oc.beta0) <= RTOL64

@@ -201,3 +201,17 @@ def test_intercept_argument_errors(G):
     ci = G.Chain(g, wl["y"], intercept=True)
     with pytest.raises(G.GmrfError):
         ci.set_intercept(float("nan"))
+
+
+@pytest.mark.parametrize("p", [2048])
+def test_image_full_size_one_sweep(G, orc, p):
+    """The largest image of the benchmark (2048 x 2048 Gaussian bump, 8
+    neighbours, intercept), FP64, two sweeps with every draw, against the
+    oracle over all sites."""
+    wl = inputs.bump_image_workload(p)
+    g, ch, oc = pair(G, orc, wl, seed=1)
+    ch.sweep(2)
+    oc.sweeps(2, nthreads=8)
+    x, tau, lam, _ = ch.get_state()
+    assert rel(x, oc.x) <= RTOL64 and rel(ch.beta0, oc.beta0) <= RTOL64
+    assert rel(tau, oc.tau) <= RTOL64 and rel(lam, oc.lam) <= RTOL64
