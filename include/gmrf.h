@@ -287,12 +287,13 @@ int gmrf_set_intercept(gmrf_chain *c, double beta0, hipStream_t stream);
 
 /* Hyperparameter trace (for autocorrelation diagnostics, Sec. 3.1 ESS / IAT):
  * d_trace is a device buffer of 3 * capacity doubles that the chain owner
- * keeps alive; after sweep t (0-based) with t < capacity, row t is set to
- * (tau, lam, beta0) after that sweep's draws (a later gmrf_hyper_update
- * rewrites it).  capacity 0 (d_trace may be NULL) turns the trace off.
- * Drops the chain's captured sweeps; a batch reads the trace setting when it
- * is created.  Host-only call. */
-int gmrf_set_trace(gmrf_chain *c, double *d_trace, int64_t capacity);
+ * keeps alive while the trace is on; after sweep t (0-based) with t <
+ * capacity, row t is set to (tau, lam, beta0) after that sweep's draws (a
+ * later gmrf_hyper_update rewrites it).  capacity 0 (d_trace may be NULL)
+ * turns the trace off.  The setting lives in the chain's device state, so
+ * captured sweeps and batches follow it; once this call has returned with
+ * the trace off, no later sweep writes the old buffer.  Synchronises. */
+int gmrf_set_trace(gmrf_chain *c, double *d_trace, int64_t capacity, hipStream_t stream);
 
 /* Lattice tile shape of a chain (Sec. 2.3: the color phases of a lattice
  * sweep run tile by tile).  Shape 0 is a 64 x 64 tile with 512 threads,

@@ -57,6 +57,8 @@ struct DevState {
     unsigned int pad;
     double beta0;               // intercept (0 without one)
     double rsum;                // sum_i (y_i - beta0 - x_i) of the last completed sweep
+    double *trace;              // NULL, or (tau, lam, beta0) per completed sweep
+    long long trace_cap;        // rows of trace
 };
 
 constexpr unsigned kStatusGamma = 1u;
@@ -77,8 +79,6 @@ struct SweepArgs {
     int likelihood;             // 0 Gaussian, 1 binomial logit (Polya-Gamma)
     double b0_prec;             // binomial: prior precision of beta0 (0 = flat)
     double n_sites;
-    double *trace;              // NULL, or (tau, lam, beta0) per completed sweep
-    long long trace_cap;        // rows of trace
 };
 
 constexpr int kPartials = 3;
@@ -204,10 +204,11 @@ __device__ __forceinline__ void end_of_sweep_draws(const SweepArgs &a, unsigned 
         a.st->sse = r.sse;
         a.st->rsum = r.rsum;
         a.st->beta0 = b0;
-        if (a.trace && (long long)t < a.trace_cap) {
-            a.trace[3 * (size_t)t] = v;
-            a.trace[3 * (size_t)t + 1] = other;
-            a.trace[3 * (size_t)t + 2] = b0;
+        double *const tr = a.st->trace;   // read at run time: batches and graphs see changes
+        if (tr && (long long)t < a.st->trace_cap) {
+            tr[3 * (size_t)t] = v;
+            tr[3 * (size_t)t + 1] = other;
+            tr[3 * (size_t)t + 2] = b0;
         }
     }
 }
@@ -964,8 +965,6 @@ struct gmrf_chain {
     hipStream_t capture_stream = nullptr;
     std::map<std::pair<int, unsigned>, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_defs;
-    double *d_trace = nullptr;        // caller's trace buffer (3 doubles per sweep) or NULL
-    int64_t trace_cap = 0;
 };
 
 struct gmrf_batch {
@@ -1121,8 +1120,6 @@ SweepArgs make_args(const gmrf_chain *c, unsigned flags)
     a.likelihood = c->binomial ? 1 : 0;
     a.b0_prec = c->binomial && c->model.beta0_var > 0.0 ? 1.0 / c->model.beta0_var : 0.0;
     a.n_sites = (double)c->g->h.n;
-    a.trace = c->d_trace;
-    a.trace_cap = c->trace_cap;
     return a;
 }
 
@@ -2110,14 +2107,19 @@ int gmrf_set_intercept(gmrf_chain *c, double beta0, hipStream_t stream)
     return GMRF_OK;
 }
 
-int gmrf_set_trace(gmrf_chain *c, double *d_trace, int64_t capacity)
+int gmrf_set_trace(gmrf_chain *c, double *d_trace, int64_t capacity, hipStream_t stream)
 {
     clear_error();
     if (!c || capacity < 0 || (capacity > 0 && !d_trace))
         return fail(GMRF_E_INVALID_ARG, "set_trace: NULL chain, negative capacity or NULL buffer");
-    c->d_trace = capacity > 0 ? d_trace : nullptr;
-    c->trace_cap = capacity > 0 ? capacity : 0;
-    drop_graphs(c);     // captured sweeps carry the old trace pointer
+    DevState st;
+    int rc = read_state(c, &st, stream);
+    if (rc != GMRF_OK)
+        return rc;
+    st.trace = capacity > 0 ? d_trace : nullptr;
+    st.trace_cap = capacity > 0 ? (long long)capacity : 0;
+    GMRF_HIP(hipMemcpyAsync(c->d_state, &st, sizeof st, hipMemcpyHostToDevice, stream));
+    GMRF_HIP(hipStreamSynchronize(stream));
     return GMRF_OK;
 }
 

@@ -89,7 +89,7 @@ _SIGS = {
                               C.c_void_p], C.c_int),
     "gmrf_get_intercept": ([C.c_void_p, C.POINTER(C.c_double), C.c_void_p], C.c_int),
     "gmrf_set_intercept": ([C.c_void_p, C.c_double, C.c_void_p], C.c_int),
-    "gmrf_set_trace": ([C.c_void_p, C.c_void_p, C.c_int64], C.c_int),
+    "gmrf_set_trace": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
     "gmrf_chain_get_tile": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                              C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "gmrf_chain_set_tile": ([C.c_void_p, C.c_int32], C.c_int),
@@ -381,17 +381,18 @@ class Chain:
     def set_intercept(self, beta0: float, stream=None):
         _check(lib().gmrf_set_intercept(self.handle, float(beta0), _stream_handle(stream)))
 
-    def enable_trace(self, capacity: int):
+    def enable_trace(self, capacity: int, stream=None):
         """Record (tau, lam, beta0) after every sweep t < capacity into a device
         buffer (float64 tensor of shape (capacity, 3), read it with trace())."""
         torch = _torch()
-        self.trace_buf = torch.full((int(capacity), 3), float("nan"), dtype=torch.float64,
-                                    device=self.graph.device)
-        _check(lib().gmrf_set_trace(self.handle, C.c_void_p(self.trace_buf.data_ptr()),
-                                    int(capacity)))
+        buf = torch.full((int(capacity), 3), float("nan"), dtype=torch.float64,
+                         device=self.graph.device)
+        _check(lib().gmrf_set_trace(self.handle, C.c_void_p(buf.data_ptr()), int(capacity),
+                                    _stream_handle(stream)))
+        self.trace_buf = buf
 
-    def disable_trace(self):
-        _check(lib().gmrf_set_trace(self.handle, None, 0))
+    def disable_trace(self, stream=None):
+        _check(lib().gmrf_set_trace(self.handle, None, 0, _stream_handle(stream)))
         self.trace_buf = None
 
     def trace(self, stream=None) -> np.ndarray:

@@ -215,3 +215,31 @@ def test_image_full_size_one_sweep(G, orc, p):
     x, tau, lam, _ = ch.get_state()
     assert rel(x, oc.x) <= RTOL64 and rel(ch.beta0, oc.beta0) <= RTOL64
     assert rel(tau, oc.tau) <= RTOL64 and rel(lam, oc.lam) <= RTOL64
+
+
+def test_trace_setting_is_read_at_run_time(G, orc):
+    """A batch and a captured graph created before the trace was turned on
+    record into it; once it is turned off nothing writes the buffer."""
+    wl = inputs.bump_image_workload(24)
+    g, ch, oc = pair(G, orc, wl, seed=13)
+    batch = G.Batch([ch])
+    ch.sweep(4, capture=True)                 # graph recorded with the trace off
+    oc.sweeps(4)
+    ch.enable_trace(32)
+    ch.sweep(4, capture=True)
+    batch.sweep(3)
+    ref = []
+    for _ in range(7):
+        oc.sweeps(1)
+        ref.append((oc.tau, oc.lam, oc.beta0))
+    tr = ch.trace()
+    assert np.all(np.isnan(tr[:4])) and rel(tr[4:11], np.array(ref)) <= RTOL64
+    buf = ch.trace_buf
+    ch.disable_trace()
+    before = buf.cpu().numpy().copy()
+    batch.sweep(3)
+    ch.sweep(4, capture=True)
+    import torch
+
+    torch.cuda.synchronize()
+    assert np.array_equal(buf.cpu().numpy(), before, equal_nan=True)
