@@ -96,7 +96,7 @@ typedef enum {
 #define GMRF_CAPTURE 2u     /* record the nsweeps sweeps once as a HIP graph and replay it */
 
 /* Number of compiled lattice tile shapes (gmrf_chain_set_tile). */
-#define GMRF_NUM_TILES 2
+#define GMRF_NUM_TILES 3
 
 /* gmrf_posterior_stats flags */
 #define GMRF_PTR_HOST 0u    /* mean / var are host pointers; the call synchronises */
@@ -297,26 +297,34 @@ int gmrf_set_trace(gmrf_chain *c, double *d_trace, int64_t capacity, hipStream_t
 
 /* Lattice tile shape of a chain (Sec. 2.3: the color phases of a lattice
  * sweep run tile by tile).  Shape 0 is a 64 x 64 tile with 512 threads,
- * shape 1 a 32 x 32 tile with 256 threads; a new lattice chain starts with
- * shape 0 if that gives at least 512 tiles, else shape 1.  The shape changes
- * the grouping, hence the summation order, of the FP64 reductions (results
- * agree to rounding, not bit for bit, across shapes); the draws of x are
- * keyed by site and do not depend on it.  gmrf_chain_get_tile reports the
- * shape (-1 for a general graph, whose passes use 256-thread blocks); any
- * output pointer may be NULL.  gmrf_chain_set_tile (lattice chains only)
- * drops the chain's captured sweeps; a batch keeps the shapes its chains had
- * when it was created.  Host-only calls. */
+ * shape 1 a 32 x 32 tile with 256 threads; shape 2 (lattices of at most
+ * 64 x 64 sites) is shape 0's single tile swept by a persistent one-block
+ * kernel that runs all the sweeps of a gmrf_sweep call, with their draws, in
+ * one launch (bitwise the results of shape 0).  A new lattice chain starts
+ * with shape 2 if the lattice fits one 64 x 64 tile, else with shape 0 if
+ * that gives at least 512 tiles, else shape 1.  The shape
+ * changes the grouping, hence the summation order, of the FP64 reductions
+ * (results agree to rounding, not bit for bit, between shapes 0 and 1); the
+ * draws of x are keyed by site and do not depend on it.  gmrf_chain_get_tile
+ * reports the shape (-1 for a general graph, whose passes use 256-thread
+ * blocks); any output pointer may be NULL.  gmrf_chain_set_tile (lattice
+ * chains only) drops the chain's captured sweeps; a batch keeps the shapes
+ * its chains had when it was created (shape 2 is batched as shape 0).  For a
+ * shape-2 chain gmrf_sweep_timed reports the duration of the single launch
+ * (draws included) as both kernel and span time.  Host-only calls. */
 int gmrf_chain_get_tile(const gmrf_chain *c, int32_t *tile, int32_t *tile_rows, int32_t *tile_cols,
                         int32_t *threads);
 int gmrf_chain_set_tile(gmrf_chain *c, int32_t tile);
 
-/* Autotune the tile shape of a lattice chain: time `reps` (1 .. 100000) sweep
- * kernels of each shape on the chain itself and keep the fastest.  The timed
- * launches read the current state and write only scratch (the other state
- * buffer and the partial slots) with accumulation off, so the chain's state,
- * accumulators and sweep count are unchanged.  us_per_sweep (NULL or
- * GMRF_NUM_TILES doubles) receives the mean kernel time of each shape in
- * microseconds, best the chosen shape.  Synchronises the stream. */
+/* Autotune the tile shape of a lattice chain: time `reps` (1 .. 100000)
+ * whole sweeps (draws included) of each shape that fits the lattice on the
+ * chain itself and keep the fastest.  The timed sweeps run in a dry mode:
+ * accumulation off, the draws computed but not stored, so only scratch (the
+ * other state buffer and the partial slots) is written and the chain's state,
+ * accumulators, trace and sweep count are unchanged.  us_per_sweep (NULL or
+ * GMRF_NUM_TILES doubles) receives the mean time per sweep of each shape in
+ * microseconds (0 for a shape that does not fit), best the chosen shape.
+ * Synchronises the stream. */
 int gmrf_chain_autotune(gmrf_chain *c, int32_t reps, hipStream_t stream, int32_t *best,
                         double *us_per_sweep);
 

@@ -77,6 +77,7 @@ struct SweepArgs {
     int total_slots;            // blocks per sweep (all color passes)
     int intercept;              // 1: draw beta0 before tau / lam
     int likelihood;             // 0 Gaussian, 1 binomial logit (Polya-Gamma)
+    int dry;                    // timing runs: write no chain state, trace or accumulators
     double b0_prec;             // binomial: prior precision of beta0 (0 = flat)
     double n_sites;
 };
@@ -163,8 +164,8 @@ struct HyperIn {
 //     sum (r_i - d)^2 = sse - 2 d rsum + n d^2,   sum (r_i - d) = rsum - n d.
 // Then tau (lane 0) and lam (lane 1).  Lane 0 stores the reductions and
 // beta0; the trace row t, if any, gets (tau, lam, beta0) after the draws.
-__device__ __forceinline__ void end_of_sweep_draws(const SweepArgs &a, unsigned t, Red r,
-                                                   const HyperIn &in, int lane)
+__device__ __forceinline__ HyperIn end_of_sweep_draws(const SweepArgs &a, unsigned t, Red r,
+                                                      const HyperIn &in, int lane)
 {
     double b0 = in.beta0;
     if (a.with_hyper && a.intercept) {
@@ -190,16 +191,18 @@ __device__ __forceinline__ void end_of_sweep_draws(const SweepArgs &a, unsigned 
         const bool ok = gamma_draw(g, rate, a.seed, t, a.instance, (unsigned)(lane + 1), &draw);
         if (ok && isfinite(draw) && draw > 0.0 && isfinite(b0)) {
             v = draw;
-            if (lane == 0)
-                a.st->tau = v;
-            else
-                a.st->lam = v;
-        } else {
+            if (!a.dry) {
+                if (lane == 0)
+                    a.st->tau = v;
+                else
+                    a.st->lam = v;
+            }
+        } else if (!a.dry) {
             atomicOr(&a.st->status, kStatusGamma);
         }
     }
     const double other = __shfl(v, 1, 64);   // lam after the draw, from lane 1
-    if (lane == 0) {
+    if (lane == 0 && !a.dry) {
         a.st->q = r.q;
         a.st->sse = r.sse;
         a.st->rsum = r.rsum;
@@ -211,6 +214,7 @@ __device__ __forceinline__ void end_of_sweep_draws(const SweepArgs &a, unsigned 
             tr[3 * (size_t)t + 2] = b0;
         }
     }
+    return HyperIn{v, other, b0};    // valid in lane 0
 }
 
 // End of a sweep (one block): sum the partials of every block of the sweep
@@ -236,7 +240,7 @@ __device__ __forceinline__ void finish_sweep_block(const SweepArgs &a)
         r.sse = __shfl(r.sse, 0, 64);
         r.rsum = __shfl(r.rsum, 0, 64);
         end_of_sweep_draws(a, t, r, in, lane);
-        if (lane == 0) {
+        if (lane == 0 && !a.dry) {
             if ((long long)t >= a.burn_in)
                 a.st->n_acc += 1;
             a.st->sweep = (unsigned long long)t + 1ull;
@@ -603,6 +607,130 @@ template <typename Real, typename Cfg, bool B0>
 __global__ __launch_bounds__(Cfg::NT) void lattice_sweep_kernel(LatArgs<Real> la, SweepArgs a)
 {
     lattice_sweep_block<Real, Cfg, B0>(la, a, xcd_tile((int)blockIdx.x, (int)gridDim.x));
+}
+
+// A lattice that fits one tile, many sweeps in one launch (one block): the
+// field stays in LDS (after a sweep every site of the tile is final, so the
+// next sweep needs no reload), this thread's accumulators stay in registers,
+// and the end-of-sweep reductions and draws run in the block itself.  Every
+// operation is the one the tile kernel and the finish kernel perform for a
+// single-tile lattice, in the same order, so the results are bitwise those of
+// tile shape 0.  With a.dry set (timing) it writes only the state buffer that
+// the sweep after the last one would overwrite.
+template <typename Real, typename Cfg, bool B0>
+__global__ __launch_bounds__(Cfg::NT) void lattice_persistent_kernel(LatArgs<Real> la, SweepArgs a,
+                                                                     int nsweeps)
+{
+    constexpr int H = Cfg::H, LH = Cfg::LH, LW = Cfg::LW, NT = Cfg::NT;
+    constexpr int TH = Cfg::TH, TW = Cfg::TW;
+    constexpr int NL = (LH * LW + NT - 1) / NT;
+    constexpr int NPT = (TH * TW + NT - 1) / NT;
+    __shared__ Real xs[LH * LW];
+    __shared__ double red[kPartials * (NT / 64)];
+    __shared__ double hyp[3];
+    const int rows = la.rows, cols = la.cols;
+    const int lane = (int)threadIdx.x & 63;
+    unsigned t = (unsigned)a.st->sweep;
+    long long nacc = a.st->n_acc;
+    double tau = a.st->tau, lam = a.st->lam, b0 = B0 ? a.st->beta0 : 0.0;
+    {
+        const Real *src = (t & 1u) ? la.x1 : la.x0;
+        Real v[NL];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int idx = (int)threadIdx.x + k * NT;
+            const int lr = idx / LW, lc = idx - (idx / LW) * LW;
+            const int r = min(max(lr - H, 0), rows - 1);
+            const int c = min(max(lc - H, 0), cols - 1);
+            v[k] = src[(size_t)r * cols + c];
+        }
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int idx = (int)threadIdx.x + k * NT;
+            if (k < NL - 1 || idx < LH * LW)
+                xs[idx] = v[k];
+        }
+    }
+    double s1r[NPT], s2r[NPT];
+    int gi[NPT];
+    bool own[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int idx = (int)threadIdx.x + k * NT;
+        const int r = idx / TW, c = idx % TW;
+        own[k] = idx < TH * TW && r < rows && c < cols;
+        gi[k] = min(r, rows - 1) * cols + min(c, cols - 1);
+        s1r[k] = a.s1[gi[k]];
+        s2r[k] = a.s2[gi[k]];
+    }
+    bool accumulated = false;
+    lds_barrier();
+    for (int s = 0; s < nsweeps; ++s) {
+        SiteCtx<Real> sc;
+        sc.tau = (Real)tau;
+        sc.lam = (Real)lam;
+        sc.tau_rho = (Real)(tau * a.rho);
+        site_scales<Real>(sc.tau, sc.lam, Cfg::ST, sc.inv_q_full, sc.isd_full);
+        sc.beta0 = b0;
+        sc.beta0_r = (Real)sc.beta0;
+        sc.one_minus_rho = 1.0 - a.rho;
+        sc.rho = a.rho;
+        sc.t = t;
+        sc.seed = a.seed;
+        sc.instance = a.instance;
+        Red rd;
+        lattice_phases<Real, Cfg, false, B0>(xs, la.y, 0, 0, rows, cols, sc, rd);
+        if ((long long)t >= a.burn_in) {
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                if (own[k]) {
+                    const int idx = (int)threadIdx.x + k * NT;
+                    const Real v = xs[(idx / TW + H) * LW + idx % TW + H];
+                    const double dv = B0 ? (double)v + sc.beta0 : (double)v;
+                    s1r[k] = s1r[k] + dv;
+                    s2r[k] = s2r[k] + dv * dv;
+                }
+            }
+            ++nacc;
+            accumulated = true;
+        }
+        block_sum3<NT>(rd.q, rd.sse, rd.rsum, red);
+        if (threadIdx.x < 64) {
+            // the finish kernel's sum over one partial slot: x + 0 + ... = x
+            rd.q = __shfl(rd.q, 0, 64);
+            rd.sse = __shfl(rd.sse, 0, 64);
+            rd.rsum = __shfl(rd.rsum, 0, 64);
+            const HyperIn out = end_of_sweep_draws(a, t, rd, HyperIn{tau, lam, b0}, lane);
+            if (lane == 0) {
+                hyp[0] = out.tau;
+                hyp[1] = out.lam;
+                hyp[2] = out.beta0;
+            }
+        }
+        lds_barrier();
+        tau = hyp[0];
+        lam = hyp[1];
+        b0 = hyp[2];
+        ++t;
+    }
+    // the state after the last sweep: x in buffer t mod 2, the accumulators,
+    // the counters (the draws already stored tau, lam, beta0 and reductions)
+    Real *dst = (t & 1u) ? la.x1 : la.x0;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        if (own[k]) {
+            const int idx = (int)threadIdx.x + k * NT;
+            dst[gi[k]] = xs[(idx / TW + H) * LW + idx % TW + H];
+            if (accumulated && !a.dry) {
+                a.s1[gi[k]] = s1r[k];
+                a.s2[gi[k]] = s2r[k];
+            }
+        }
+    }
+    if (threadIdx.x == 0 && !a.dry) {
+        a.st->n_acc = nacc;
+        a.st->sweep = (unsigned long long)t;
+    }
 }
 
 // Batched lattice sweep: the tile table lists the tiles of every lattice
@@ -993,14 +1121,25 @@ namespace {
 // shape 1 suits small and mid-size ones, where more, smaller blocks shorten
 // the per-block chain of dependent phases.  Measured on MI355X, shape 1 is
 // 25-40% faster per sweep up to 1024 x 1024 and shape 0 is faster at
-// 2048 x 2048.
+// 2048 x 2048.  Shape 2 is shape 0's tile for a lattice that fits in it,
+// swept by the persistent one-block kernel (many sweeps per launch).
 struct TileShape {
     int th, tw, nt;
 };
-constexpr TileShape kTiles[GMRF_NUM_TILES] = {{64, 64, 512}, {32, 32, 256}};
+constexpr TileShape kTiles[GMRF_NUM_TILES] = {{64, 64, 512}, {32, 32, 256}, {64, 64, 512}};
+constexpr int kPersistent = 2;
 template <int ST, int K>
 using LatticeCfg = LatCfg<ST, kTiles[K].th, kTiles[K].tw, kTiles[K].nt, 4>;
-static_assert(GMRF_NUM_TILES == 2, "tile dispatch below covers two shapes");
+static_assert(GMRF_NUM_TILES == 3, "tile dispatch below covers three shapes");
+
+// Tile configuration (0 or 1) whose kernels sweep a chain of shape k.
+int tile_cfg(int k) { return k == kPersistent ? 0 : k; }
+
+// Can shape k sweep this lattice?
+bool tile_fits(const HostGraph &h, int k)
+{
+    return k != kPersistent || (h.rows <= kTiles[0].th && h.cols <= kTiles[0].tw);
+}
 
 #define GMRF_HIP(expr)                                                                    \
     do {                                                                                  \
@@ -1020,16 +1159,23 @@ int lattice_blocks(const HostGraph &h, int k)
     return tr * tc;
 }
 
-// Default tile shape: the large tile once it yields enough blocks to cover the
-// chip twice (256 CUs), the small one below that.
-int default_tile(const HostGraph &h) { return lattice_blocks(h, 0) >= 512 ? 0 : 1; }
+// Default tile shape: the persistent kernel for a lattice that fits one tile;
+// else the large tile once it yields enough blocks to cover the chip twice
+// (256 CUs), the small one below that.
+int default_tile(const HostGraph &h)
+{
+    if (tile_fits(h, kPersistent))
+        return kPersistent;
+    return lattice_blocks(h, 0) >= 512 ? 0 : 1;
+}
 
 // Partial slots to reserve: the most any tile shape needs.
 int max_lattice_blocks(const HostGraph &h)
 {
     int m = 0;
     for (int k = 0; k < GMRF_NUM_TILES; ++k)
-        m = std::max(m, lattice_blocks(h, k));
+        if (tile_fits(h, k))
+            m = std::max(m, lattice_blocks(h, k));
     return m;
 }
 
@@ -1173,11 +1319,40 @@ template <typename Real, int ST>
 void launch_lattice(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent_t ev0,
                     hipEvent_t ev1)
 {
-    if (c->lat_tile == 0)
+    if (tile_cfg(c->lat_tile) == 0)
         launch_lattice_shape<Real, ST, 0>(c, a, s, ev0, ev1);
     else
         launch_lattice_shape<Real, ST, 1>(c, a, s, ev0, ev1);
 }
+
+// nsweeps sweeps of a shape-2 chain in one launch of the persistent kernel.
+template <typename Real, int ST>
+void launch_persistent_typed(const gmrf_chain *c, const SweepArgs &a, int nsweeps, hipStream_t s,
+                             hipEvent_t ev0, hipEvent_t ev1)
+{
+    const LatArgs<Real> la = lattice_args<Real>(c);
+    using Cfg = LatticeCfg<ST, 0>;
+    auto kern = c->model.intercept ? lattice_persistent_kernel<Real, Cfg, true>
+                                   : lattice_persistent_kernel<Real, Cfg, false>;
+    if (ev0 || ev1)
+        hipExtLaunchKernelGGL(kern, dim3(1), dim3(Cfg::NT), 0, s, ev0, ev1, 0, la, a, nsweeps);
+    else
+        hipLaunchKernelGGL(kern, dim3(1), dim3(Cfg::NT), 0, s, la, a, nsweeps);
+}
+
+void launch_persistent(const gmrf_chain *c, const SweepArgs &a, int nsweeps, hipStream_t s,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
+{
+    const bool f64 = c->prec == GMRF_FP64;
+    if (c->g->h.stencil == 4)
+        f64 ? launch_persistent_typed<double, 4>(c, a, nsweeps, s, ev0, ev1)
+            : launch_persistent_typed<float, 4>(c, a, nsweeps, s, ev0, ev1);
+    else
+        f64 ? launch_persistent_typed<double, 8>(c, a, nsweeps, s, ev0, ev1)
+            : launch_persistent_typed<float, 8>(c, a, nsweeps, s, ev0, ev1);
+}
+
+bool is_persistent(const gmrf_chain *c) { return c->g->h.stencil != 0 && c->lat_tile == kPersistent; }
 
 // Launch configuration of the small element-wise kernels.
 int elementwise_blocks(int64_t n)
@@ -1410,7 +1585,7 @@ void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im)
         const HostGraph &h = c->g->h;
         const int g = c->model.intercept ? 1 : 0;
         if (is_lattice(c->g)) {
-            const int w = (h.stencil == 8 ? 1 : 0) + 2 * g + 4 * c->lat_tile;
+            const int w = (h.stencil == 8 ? 1 : 0) + 2 * g + 4 * tile_cfg(c->lat_tile);
             const int job = (int)ljobs[w].size();
             ljobs[w].push_back(LatJob<Real>{lattice_args<Real>(c), a});
             for (int t = 0; t < c->total_slots; ++t)
@@ -1850,8 +2025,11 @@ int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t strea
             if (!c->capture_stream)
                 GMRF_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
             GMRF_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-            for (int i = 0; i < nsweeps; ++i)
-                launch_one_sweep(c, a, c->capture_stream);
+            if (is_persistent(c))
+                launch_persistent(c, a, nsweeps, c->capture_stream);
+            else
+                for (int i = 0; i < nsweeps; ++i)
+                    launch_one_sweep(c, a, c->capture_stream);
             hipGraph_t gdef = nullptr;
             const hipError_t le = hipGetLastError();
             GMRF_HIP(hipStreamEndCapture(c->capture_stream, &gdef));
@@ -1865,6 +2043,9 @@ int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t strea
             it = c->graphs.emplace(key, exec).first;
         }
         GMRF_HIP(hipGraphLaunch(it->second, stream));
+    } else if (is_persistent(c)) {
+        launch_persistent(c, a, nsweeps, stream);
+        GMRF_HIP(hipGetLastError());
     } else {
         for (int i = 0; i < nsweeps; ++i)
             launch_one_sweep(c, a, stream);
@@ -1896,7 +2077,25 @@ int gmrf_sweep_timed(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t
             break;
         }
     }
-    if (rc == GMRF_OK && nsweeps > 0) {
+    if (rc == GMRF_OK && nsweeps > 0 && is_persistent(c)) {
+        // one launch carries every sweep (and its draws): its duration is both
+        hipError_t he = hipSuccess;
+        launch_persistent(c, a, nsweeps, stream, ev[0], ev[1]);
+        he = hipGetLastError();
+        if (he == hipSuccess)
+            he = hipStreamSynchronize(stream);
+        float ms = 0.0f;
+        if (he == hipSuccess)
+            he = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (he != hipSuccess) {
+            rc = fail(GMRF_E_DEVICE, std::string("sweep_timed: ") + hipGetErrorString(he));
+        } else {
+            *kernel_ms = ms;
+            if (span_ms)
+                *span_ms = ms;
+        }
+        c->host_sweeps += (uint64_t)nsweeps;
+    } else if (rc == GMRF_OK && nsweeps > 0) {
         hipError_t he = hipSuccess;
         for (int i = 0; i < nsweeps && he == hipSuccess; ++i) {
             launch_sweep_kernels(c, a, stream, ev[2 * i], ev[2 * i + 1]);
@@ -2150,6 +2349,9 @@ int gmrf_chain_set_tile(gmrf_chain *c, int32_t tile)
     if (!c || !is_lattice(c->g) || tile < 0 || tile >= GMRF_NUM_TILES)
         return fail(GMRF_E_INVALID_ARG, "chain_set_tile: NULL or general-graph chain, or tile "
                                         "not in 0 .. GMRF_NUM_TILES - 1");
+    if (!tile_fits(c->g->h, tile))
+        return fail(GMRF_E_INVALID_ARG, "chain_set_tile: shape 2 needs a lattice of at most "
+                                        "64 x 64 sites");
     if (tile != c->lat_tile) {
         c->lat_tile = tile;
         c->total_slots = lattice_blocks(c->g->h, tile);
@@ -2172,18 +2374,33 @@ int gmrf_chain_autotune(gmrf_chain *c, int32_t reps, hipStream_t stream, int32_t
     double t[GMRF_NUM_TILES];
     int win = keep;
     for (int k = 0; k < GMRF_NUM_TILES && he == hipSuccess; ++k) {
+        t[k] = 0.0;
+        if (!tile_fits(c->g->h, k))
+            continue;
         c->lat_tile = k;
         c->total_slots = lattice_blocks(c->g->h, k);
-        // The sweep kernel alone reads the current state and writes only the
-        // other state buffer and the partial slots (both scratch until the
-        // next sweep); with accumulation off it leaves the chain unchanged.
-        SweepArgs a = make_args(c, 0u);
+        // Whole sweeps (sweep kernels and the finish, or the persistent
+        // kernel) in dry mode: accumulation off, draws computed but nothing
+        // stored, so the sweep kernels write only the other state buffer and
+        // the partial slots (scratch until the next sweep) and the chain is
+        // unchanged; the persistent kernel runs an odd number of sweeps so
+        // that it too ends in the other state buffer.
+        SweepArgs a = make_args(c, GMRF_WITH_HYPER);
         a.burn_in = (long long)(~0ull >> 1);
-        for (int i = 0; i < 2; ++i)
-            launch_sweep_kernels(c, a, stream);
-        he = hipEventRecord(e0, stream);
-        for (int i = 0; i < reps && he == hipSuccess; ++i)
-            launch_sweep_kernels(c, a, stream);
+        a.dry = 1;
+        const int odd = reps | 1;
+        if (k == kPersistent) {
+            launch_persistent(c, a, 1, stream);
+            he = hipEventRecord(e0, stream);
+            if (he == hipSuccess)
+                launch_persistent(c, a, odd, stream);
+        } else {
+            for (int i = 0; i < 2; ++i)
+                launch_one_sweep(c, a, stream);
+            he = hipEventRecord(e0, stream);
+            for (int i = 0; i < reps && he == hipSuccess; ++i)
+                launch_one_sweep(c, a, stream);
+        }
         if (he == hipSuccess)
             he = hipEventRecord(e1, stream);
         if (he == hipSuccess)
@@ -2193,7 +2410,7 @@ int gmrf_chain_autotune(gmrf_chain *c, int32_t reps, hipStream_t stream, int32_t
         float ms = 0.0f;
         if (he == hipSuccess)
             he = hipEventElapsedTime(&ms, e0, e1);
-        t[k] = 1e3 * (double)ms / reps;
+        t[k] = 1e3 * (double)ms / (k == kPersistent ? odd : reps);
         if (he == hipSuccess && (k == 0 || t[k] < t[win]))
             win = k;
     }

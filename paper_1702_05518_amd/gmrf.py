@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "GMRF_OK", 1: "GMRF_E_INVALID_ARG", 2: "GMRF_E_GRAPH",
                 6: "GMRF_E_NUMERIC"}
 FP64, FP32_ACC64 = 0, 1
 WITH_HYPER, CAPTURE = 1, 2
-NUM_TILES = 2
+NUM_TILES = 3
 GAUSSIAN, BINOMIAL = 0, 1
 PTR_HOST, PTR_DEVICE = 0, 1
 

@@ -80,7 +80,7 @@ def test_autotune_leaves_state_unchanged(G, prec):
     before = a.get_state(), a.get_accumulators(), a.last_reductions()
     best, us = a.autotune(reps=5)
     after = a.get_state(), a.get_accumulators(), a.last_reductions()
-    assert best in (0, 1) and len(us) == 2 and all(u > 0 for u in us)
+    assert best in (0, 1) and len(us) == 3 and all(u > 0 for u in us[:2]) and us[2] == 0.0
     assert a.tile[0] == best
     assert np.array_equal(before[0][0], after[0][0]) and before[0][1:] == after[0][1:]
     assert np.array_equal(before[1][0], after[1][0]) and np.array_equal(before[1][1], after[1][1])
@@ -111,3 +111,65 @@ def test_batch_with_mixed_shapes_is_bitwise_standalone(G):
         xa, ta, la, _ = a.get_state()
         xb, tb, lb, _ = b.get_state()
         assert np.array_equal(xa, xb) and ta == tb and la == lb
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("rows,cols,st,intercept", [(50, 50, 8, True), (64, 64, 4, False),
+                                                     (17, 40, 8, False), (1, 1, 8, False)])
+def test_persistent_shape_is_bitwise_shape0(G, orc, prec, rows, cols, st, intercept):
+    """Shape 2 (one launch per gmrf_sweep call) gives bit for bit the state,
+    accumulators, reductions and trace of shape 0, plain and captured, across
+    the burn-in boundary; FP64 also matches the oracle."""
+    p = G.FP64 if prec == "fp64" else G.FP32_ACC64
+    wl = inputs.lattice_workload(rows, cols, st, data_seed=rows + cols)
+    kw = dict(precision=p, seed=9, burn_in=5, intercept=intercept)
+    g = G.Graph(lattice=(rows, cols, st))
+    a = G.Chain(g, wl["y"], **kw)
+    b = G.Chain(g, wl["y"], **kw)
+    a.set_tile(0)
+    b.set_tile(2)
+    for ch in (a, b):
+        ch.enable_trace(64)
+        ch.sweep(3)
+        ch.sweep(7, capture=True)
+        ch.sweep(7, capture=True)
+        ch.sweep(1)
+    sa, sb = a.get_state(), b.get_state()
+    assert np.array_equal(sa[0], sb[0]) and sa[1:] == sb[1:] and sb[3] == 18
+    ma, va, na = a.posterior_stats()
+    mb, vb, nb = b.posterior_stats()
+    assert na == nb == 13 and np.array_equal(ma, mb) and np.array_equal(va, vb)
+    assert a.last_reductions() == b.last_reductions() and a.beta0 == b.beta0
+    assert np.array_equal(a.trace(), b.trace(), equal_nan=True)
+    if prec == "fp64":
+        oc = orc.Chain(wl["row_ptr"], wl["col"], wl["color"], wl["y"], seed=9, burn_in=5,
+                       intercept=intercept)
+        oc.sweeps(18)
+        assert rel(sb[0], oc.x) <= RTOL64 and rel(sb[1], oc.tau) <= RTOL64
+
+
+def test_persistent_shape_rules_and_autotune(G):
+    wl = inputs.lattice_workload(50, 50, 8)
+    g = G.Graph(lattice=(50, 50, 8))
+    ch = G.Chain(g, wl["y"], seed=3)
+    ch.sweep(4)
+    before = ch.get_state(), ch.get_accumulators(), ch.last_reductions()
+    best, us = ch.autotune(reps=20)
+    after = ch.get_state(), ch.get_accumulators(), ch.last_reductions()
+    assert len(us) == 3 and all(u > 0 for u in us) and best in (0, 1, 2)
+    assert np.array_equal(before[0][0], after[0][0]) and before[0][1:] == after[0][1:]
+    assert np.array_equal(before[1][0], after[1][0]) and before[1][2] == after[1][2]
+    assert before[2] == after[2]
+    big = G.Chain(G.Graph(lattice=(65, 64, 4)), np.zeros(65 * 64))
+    with pytest.raises(G.GmrfError):
+        big.set_tile(2)
+    b2, us2 = big.autotune(reps=3)
+    assert us2[2] == 0.0 and b2 in (0, 1)
+    # a shape-2 chain batches as shape 0: bitwise equal to standalone shape 2
+    a = G.Chain(g, wl["y"], seed=5)
+    b = G.Chain(g, wl["y"], seed=5)
+    a.set_tile(2)
+    b.set_tile(2)
+    a.sweep(6)
+    G.Batch([b]).sweep(6)
+    assert np.array_equal(a.get_state()[0], b.get_state()[0])
