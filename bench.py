@@ -269,6 +269,15 @@ def bench_serve(torch, gmrf, inputs, args):
     print(json.dumps(line), flush=True)
 
 
+def run_captured(chain, total):
+    """`total` sweeps with every draw, as captured graphs of 1000 sweeps (and
+    one graph for the remainder)."""
+    for _ in range(total // 1000):
+        chain.sweep(1000, hyper=True, capture=True)
+    if total % 1000:
+        chain.sweep(total % 1000, hyper=True, capture=True)
+
+
 def bench_image(torch, gmrf, inputs, args):
     """The paper's image example on the GPU (Sec. 3.1, Table 1 setting):
     p x p Gaussian-bump truth plus N(0, 1) (and N(0, 50^2)) noise, 8-neighbour
@@ -280,7 +289,8 @@ def bench_image(torch, gmrf, inputs, args):
     JSON line; the paper's CPU figures are context only."""
     from paper_1702_05518_amd import diagnostics
 
-    total, burn = 10_000, 8_000
+    total = args.iterations
+    burn = total * 4 // 5                 # 8,000 of 10,000 in Table 1
     prior = dict(a_tau=0.001, b_tau=0.001, a_lam=0.001, b_lam=0.001)
     rows = []
     for p, noise in [(50, 1.0), (50, 50.0), (128, 1.0), (512, 1.0), (2048, 1.0)]:
@@ -292,8 +302,7 @@ def bench_image(torch, gmrf, inputs, args):
             ch.enable_trace(total)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for _ in range(total // 1000):
-                ch.sweep(1000, hyper=True, capture=True)
+            run_captured(ch, total)
             mean, var, nacc = ch.posterior_stats()
             torch.cuda.synchronize()
             T = time.perf_counter() - t0
@@ -344,7 +353,8 @@ def bench_binomial(torch, gmrf, inputs, args):
     number of iterations of the same workload.  Prints one JSON line."""
     from paper_1702_05518_amd import diagnostics
 
-    total, burn, n = 10_000, 5_000, 14_926
+    total, n = args.iterations, 14_926
+    burn = total // 2                     # 5,000 of 10,000 in Table 2
     wl = inputs.binomial_workload(n, data_seed=5)
     color, k = gmrf.greedy_coloring(wl["row_ptr"], wl["col"])
     graph = gmrf.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color, num_colors=k,
@@ -356,8 +366,7 @@ def bench_binomial(torch, gmrf, inputs, args):
         ch.enable_trace(total)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(total // 1000):
-            ch.sweep(1000, hyper=True, capture=True)
+        run_captured(ch, total)
         mean, var, nacc = ch.posterior_stats()
         torch.cuda.synchronize()
         T = time.perf_counter() - t0
@@ -427,6 +436,9 @@ def main():
                          "image: the paper's image example with IAT / ESS / CES; "
                          "binomial: the paper's binomial example with IAT / ESS / CES "
                          "(each a separate JSON line)")
+    ap.add_argument("--iterations", type=int, default=10_000,
+                    help="image / binomial: iterations of the paper's example (default 10,000, "
+                         "with the paper's burn-in fractions 4/5 and 1/2)")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe for rocprofv3 --pmc: a 512 MiB device copy (the "
                          "scale reference for FETCH_SIZE / WRITE_SIZE), then --steps sweeps")
