@@ -84,3 +84,43 @@ def test_admission_respects_budget(S):
         serve.Server(budget_bytes=10).submit(jobs[0])
     with pytest.raises(ValueError):
         serve.Server(budget_bytes=budget, step_sweeps=7).submit(jobs[0])
+
+
+def test_full_config_stream_equals_standalone(S):
+    """The benchmark's serving configuration: Poisson arrivals at 200/s for
+    2 s of 1000-sweep jobs on Delaunay graphs of 15,000 sites (probability
+    0.98) or 1,000,000 sites (0.02), served in real time with continuous
+    batching; sampled jobs (every 1M-site job among them) equal a standalone
+    run bit for bit."""
+    gmrf, serve = S
+    graphs = []
+    for n, ds in [(15000, 11), (15000, 12), (15000, 13), (1_000_000, 14)]:
+        pts, rp, cl = inputs.delaunay_graph(n, data_seed=ds)
+        y = inputs.smooth_field(pts) + 0.2 * np.random.default_rng(ds).standard_normal(n)
+        color, k = gmrf.greedy_coloring(rp, cl)
+        graphs.append((gmrf.Graph(row_ptr=rp, col_idx=cl, color=color, num_colors=k, rho=0.95),
+                       y))
+    rng = np.random.default_rng(7)
+    t, jobs = 0.0, []
+    while True:
+        t += rng.exponential(1 / 200.0)
+        if t > 2.0:
+            break
+        g, y = graphs[3] if rng.random() < 0.02 else graphs[int(rng.integers(0, 3))]
+        jobs.append(serve.Job(len(jobs), g, y, seed=1000 + len(jobs), instance=len(jobs),
+                              nsweeps=1000, arrival=t, precision=gmrf.FP32_ACC64))
+    import torch
+
+    free, _ = torch.cuda.mem_get_info()
+    server = serve.Server(budget_bytes=int(0.5 * free), step_sweeps=10, max_active=1024)
+    server.run(jobs, realtime=True)
+    assert len(server.finished) == len(jobs) > 300
+    big = [j for j in jobs if j.sites == 1_000_000]
+    picks = big + [jobs[i] for i in rng.choice(len(jobs), 5, replace=False)]
+    for job in picks:
+        ch = gmrf.Chain(job.graph, job.y, precision=job.precision, seed=job.seed,
+                        instance=job.instance)
+        ch.sweep(job.nsweeps, capture=True)
+        mean, var, nacc = ch.posterior_stats()
+        assert nacc == 1000
+        assert np.array_equal(mean, job.mean) and np.array_equal(var, job.var)
