@@ -159,7 +159,10 @@ def bench_batch(torch, gmrf, inputs, args):
             color, k = gmrf.greedy_coloring(wl["row_ptr"], wl["col"])
             g = gmrf.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color, num_colors=k,
                            rho=wl["rho"])
-        chains.append(gmrf.Chain(g, wl["y"], precision=gmrf.FP32_ACC64, seed=1 + i, instance=i))
+        ch = gmrf.Chain(g, wl["y"], precision=gmrf.FP32_ACC64, seed=1 + i, instance=i)
+        if wl["kind"] == "lattice":
+            ch.set_tile(1)       # throughput: the 32x32 tile wastes least when the chip is full
+        chains.append(ch)
         sites += wl["n"]
     batch = gmrf.Batch(chains)
     batch.sweep(args.warmup, capture=False)
