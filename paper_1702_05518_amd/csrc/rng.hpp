@@ -58,14 +58,15 @@ __device__ __forceinline__ double open_uniform_f64(uint32_t hi, uint32_t lo)
     return ((double)m + 0.5) * 0x1p-52;
 }
 
-constexpr double kTwoPi = 6.283185307179586;
 
-// FP64 standard normal of one Philox block.
+// FP64 standard normal of one Philox block.  cos(2 pi u2) is evaluated as
+// cospi(2 u2): the same value up to a few ulps (no rounded 2 pi product, no
+// general range reduction), and a lighter instruction sequence.
 __device__ __forceinline__ double normal_f64(const Words4 &w)
 {
     const double u1 = open_uniform_f64(w.w0, w.w1);
     const double u2 = open_uniform_f64(w.w2, w.w3);
-    return sqrt(-2.0 * log(u1)) * cos(kTwoPi * u2);
+    return sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
 }
 
 // FP32 standard normal of the same block: the same two uniforms carried to
@@ -164,7 +165,7 @@ struct PgStream {
     {
         const double u1 = next();
         const double u2 = next();
-        return sqrt(-2.0 * log(u1)) * cos(kTwoPi * u2);
+        return sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
     }
 };
 
