@@ -251,7 +251,9 @@ int gmrf_hyper_update(gmrf_chain *c, hipStream_t stream);
 int gmrf_set_hyper(gmrf_chain *c, double tau, double lam, hipStream_t stream);
 
 /* Posterior mean S1/N and variance (S2 - S1^2/N)/(N - 1) of phi = beta0 + x
- * over the N accumulated sweeps, in original site order, FP64.  With GMRF_PTR_HOST the
+ * over the N accumulated sweeps, in original site order, FP64 (the variance
+ * needs N >= 2 and the mean N >= 1 to be finite; they are computed as
+ * written whatever N is).  With GMRF_PTR_HOST the
  * call synchronises and mean / var / n_acc are host pointers (n_acc may be
  * NULL); with GMRF_PTR_DEVICE mean / var are device buffers of n doubles and
  * n_acc must be NULL.  Returns GMRF_E_NUMERIC if a device draw failed. */
