@@ -149,7 +149,10 @@ struct PgStream {
     uint32_t site, sweep, instance, j;
     uint32_t used;
     bool exhausted;
+    Words4 blk{};               // the block of the last even-numbered uniform
 
+    // Uniform `used`: an even one computes its block and keeps it for the
+    // odd one that follows (one Philox evaluation per two uniforms).
     __device__ double next()
     {
         const uint32_t u = used;
@@ -158,8 +161,10 @@ struct PgStream {
             return 0.5;
         }
         used = u + 1;
-        const Words4 w = draw_words(seed, site, sweep, instance, 0x80000000u | (j << 10) | (u >> 1));
-        return (u & 1u) ? open_uniform_f64(w.w2, w.w3) : open_uniform_f64(w.w0, w.w1);
+        if (u & 1u)
+            return open_uniform_f64(blk.w2, blk.w3);
+        blk = draw_words(seed, site, sweep, instance, 0x80000000u | (j << 10) | (u >> 1));
+        return open_uniform_f64(blk.w0, blk.w1);
     }
     __device__ double normal()
     {
@@ -171,16 +176,43 @@ struct PgStream {
 
 __device__ inline double std_normal_cdf(double x) { return 0.5 * erfc(-x / sqrt(2.0)); }
 
-// Term n of the alternating series of the J*(1) density (left form for
-// x <= t, right form for x > t).
-__device__ inline double pg_term(int n, double x)
-{
-    const double h = (double)n + 0.5;
-    if (x > kPgT)
-        return kPi * h * exp(-0.5 * h * h * kPi * kPi * x);
-    const double r = 2.0 / (kPi * x);
-    return kPi * h * r * sqrt(r) * exp(-2.0 * h * h / x);
-}
+// Terms of the alternating series of the J*(1) density at x, in order.
+// Term n is pi (n + 1/2) c E^((2n+1)^2) with, right of t (x > t), c = 1 and
+// E = exp(-pi^2 x / 8), and left of t, c = (2 / (pi x))^(3/2) and
+// E = exp(-1 / (2 x)).  The powers come from one exp by the recurrence
+// E^((2n+1)^2) = E^((2n-1)^2) * E^(8n), so each term after the first costs
+// two multiplications; the values equal the per-term exponentials up to a
+// few ulps.
+struct PgSeries {
+    double c, e, e8, ratio, power;
+    int n;
+
+    __device__ explicit PgSeries(double x)
+    {
+        if (x > kPgT) {
+            c = 1.0;
+            e = exp(-0.125 * kPi * kPi * x);
+        } else {
+            const double r = 2.0 / (kPi * x);
+            c = r * sqrt(r);
+            e = exp(-0.5 / x);
+        }
+        const double e2 = e * e, e4 = e2 * e2;
+        e8 = e4 * e4;
+        ratio = 1.0;
+        power = e;
+        n = 0;
+    }
+    // the current term, then advance to the next one
+    __device__ double next()
+    {
+        const double v = kPi * ((double)n + 0.5) * c * power;
+        ratio *= e8;                 // E^(8 (n + 1))
+        power *= ratio;              // E^((2n + 3)^2)
+        ++n;
+        return v;
+    }
+};
 
 // IG(1/z, 1) restricted to (0, t).  z < 1/t: the z = 0 law on (0, t) from a
 // normal tail beyond 1/sqrt(t) (1/X = (1 + t E1)^2 / t, E1^2 <= 2 E2 / t),
@@ -243,26 +275,27 @@ __device__ inline PgEnvelope pg_envelope(double c)
 __device__ inline bool pg1_draw(const PgEnvelope &e, uint64_t seed, uint32_t site, uint32_t sweep,
                                 uint32_t instance, uint32_t j, double *out)
 {
-    PgStream s{seed, site, sweep, instance, j, 0u, false};
+    PgStream s{seed, site, sweep, instance, j, 0u, false, Words4{}};
     for (;;) {
         double x;
         if (s.next() < e.right)
             x = kPgT - log(s.next()) / e.K;
         else
             x = pg_left(e.z, s);
-        double S = pg_term(0, x);
+        PgSeries terms(x);
+        double S = terms.next();
         const double Y = s.next() * S;
         if (s.exhausted)
             return false;
         for (int n = 1; n <= kPgMaxTerms; ++n) {
             if (n & 1) {
-                S -= pg_term(n, x);
+                S -= terms.next();
                 if (Y <= S) {
                     *out = 0.25 * x;
                     return true;
                 }
             } else {
-                S += pg_term(n, x);
+                S += terms.next();
                 if (Y > S)
                     break;
             }
