@@ -881,15 +881,15 @@ __global__ __launch_bounds__(kThreads) void csr_batch_kernel(const CsrJob<Real> 
 // augmentation): two launches per color
 // ---------------------------------------------------------------------------
 // psi_p ~ PG(m_p, beta0 + x_p) is the sum of m_p PG(1, .) terms.  The terms
-// of a color's sites are cut into chunks of kPgChunk consecutive terms of one
-// site, and the term kernel runs one thread per chunk over the whole color
-// (so work is spread evenly whatever the m_p), writing each chunk's sum.  The
-// site kernel then runs one wavefront per site: the lanes add the site's
-// chunk sums (lane l takes chunks l, l + 64, ...; a fixed tree joins the
-// lanes) and lane 0 draws x_p from N(m, 1/Q), Q = tau D_pp + psi_p,
-// m = (kappa_p - psi_p beta0 + tau rho sum_{j~p} x_j) / Q.  Both read the
-// site's old x_p, which no launch of this color changes before the site
-// kernel.
+// of all sites are cut into chunks of kPgChunk consecutive terms of one site,
+// and the term kernel runs one thread per chunk over the whole graph at the
+// start of the sweep (so work is spread evenly whatever the m_p), writing
+// each chunk's sum; it reads each site's value at the start of the sweep,
+// which is the value the site's own color pass sees.  The site kernel of a
+// color then runs one wavefront per site: the lanes add the site's chunk
+// sums (lane l takes chunks l, l + 64, ...; a fixed tree joins the lanes)
+// and lane 0 draws x_p from N(m, 1/Q), Q = tau D_pp + psi_p,
+// m = (kappa_p - psi_p beta0 + tau rho sum_{j~p} x_j) / Q.
 constexpr int kBinomSites = kThreads / 64;      // sites per block of the site kernel
 constexpr int kPgChunk = 2;                     // PG(1, .) terms per chunk
 #ifndef GMRF_PG_ENV_PREPASS
@@ -897,8 +897,11 @@ constexpr int kPgChunk = 2;                     // PG(1, .) terms per chunk
 #endif
 constexpr bool kPgEnvPrepass = GMRF_PG_ENV_PREPASS;
 
-// The PG envelope of every site of a color slab (tilt beta0 + old x_p), so
-// that the term kernel's threads need not each evaluate its erfc and exp.
+// The PG envelope of sites lo .. lo + cnt - 1 (tilt beta0 + x_p), so that
+// the term kernel's threads need not each evaluate its erfc and exp.  Run
+// over all sites at the start of a sweep: beta0 is fixed during the sweep and
+// no color pass changes a site before that site's own pass, so every
+// envelope is the one of the site's pass.
 template <typename Real, bool B0>
 __global__ __launch_bounds__(kThreads) void pg_env_kernel(CsrArgs<Real> ca, SweepArgs a, int lo,
                                                           int cnt)
@@ -1371,36 +1374,37 @@ void launch_csr(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent
     for (int32_t col = 0; col < h.k; ++col)
         if (c->pass_blocks[col] > 0)
             last = col;
+    // Binomial: every psi_p depends only on beta0 and the site's value at the
+    // start of the sweep (no pass changes a site before its own), so the
+    // envelopes and all PG terms of the sweep are drawn up front, in one
+    // launch each, before the color passes.
+    const int nq_all = c->binomial ? c->color_chunk[h.k] : 0;
+    if (nq_all > 0 && kPgEnvPrepass) {
+        auto ek = c->model.intercept ? pg_env_kernel<Real, true> : pg_env_kernel<Real, false>;
+        const int eb = (int)((h.n + kThreads - 1) / kThreads);
+        if (ev0)
+            hipExtLaunchKernelGGL(ek, dim3(eb), dim3(kThreads), 0, s, ev0, nullptr, 0, ca, a, 0,
+                                  (int)h.n);
+        else
+            hipLaunchKernelGGL(ek, dim3(eb), dim3(kThreads), 0, s, ca, a, 0, (int)h.n);
+        ev0 = nullptr;
+    }
+    if (nq_all > 0) {
+        auto tk = c->model.intercept ? pg_chunk_kernel<Real, true> : pg_chunk_kernel<Real, false>;
+        const int tb = (nq_all + kThreads - 1) / kThreads;
+        if (ev0)
+            hipExtLaunchKernelGGL(tk, dim3(tb), dim3(kThreads), 0, s, ev0, nullptr, 0, ca, a, 0,
+                                  nq_all);
+        else
+            hipLaunchKernelGGL(tk, dim3(tb), dim3(kThreads), 0, s, ca, a, 0, nq_all);
+        ev0 = nullptr;
+    }
     for (int32_t col = 0; col < h.k; ++col) {
         const int nb = c->pass_blocks[col];
         if (nb == 0)
             continue;
         const int lo = h.slab_offsets[col], cnt = h.slab_offsets[col + 1] - lo;
         hipEvent_t e0 = slot == 0 ? ev0 : nullptr, e1 = col == last ? ev1 : nullptr;
-        if (c->binomial) {
-            const int q0 = c->color_chunk[col], nq = c->color_chunk[col + 1] - q0;
-            if (nq > 0 && kPgEnvPrepass) {
-                auto ek = c->model.intercept ? pg_env_kernel<Real, true> : pg_env_kernel<Real, false>;
-                const int eb = (cnt + kThreads - 1) / kThreads;
-                if (e0)
-                    hipExtLaunchKernelGGL(ek, dim3(eb), dim3(kThreads), 0, s, e0, nullptr, 0, ca,
-                                          a, lo, cnt);
-                else
-                    hipLaunchKernelGGL(ek, dim3(eb), dim3(kThreads), 0, s, ca, a, lo, cnt);
-                e0 = nullptr;
-            }
-            if (nq > 0) {
-                auto tk = c->model.intercept ? pg_chunk_kernel<Real, true>
-                                             : pg_chunk_kernel<Real, false>;
-                const int tb = (nq + kThreads - 1) / kThreads;
-                if (e0)
-                    hipExtLaunchKernelGGL(tk, dim3(tb), dim3(kThreads), 0, s, e0, nullptr, 0, ca,
-                                          a, q0, nq);
-                else
-                    hipLaunchKernelGGL(tk, dim3(tb), dim3(kThreads), 0, s, ca, a, q0, nq);
-                e0 = nullptr;
-            }
-        }
         auto kern = c->binomial ? (c->model.intercept ? csr_binomial_pass_kernel<Real, true>
                                                       : csr_binomial_pass_kernel<Real, false>)
                                 : (c->model.intercept ? csr_pass_kernel<Real, true>
