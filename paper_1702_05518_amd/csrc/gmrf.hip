@@ -765,8 +765,9 @@ template <typename Real> struct CsrArgs {
     const int *trials;          // binomial: m_i (slab order); NULL otherwise
     const int *chunk_off;       // binomial: first term chunk of each slab position (n + 1)
     const int *chunk_site;      // binomial: slab position of each chunk
-    double *chunk_sum;          // binomial: the sum of each chunk's PG(1, .) terms
-    PgEnvelope *env;            // binomial: each site's PG envelope for the current pass
+    double *chunk_sum;          // binomial: run sums of the PG(1, .) terms (see below)
+    PgEnvelope *env;            // binomial: each site's PG envelope for the current sweep
+    double *psi;                // binomial: each site's psi for the current sweep
 };
 
 // One site per thread.  The first kCsrBatch neighbours are gathered in one
@@ -880,18 +881,27 @@ __global__ __launch_bounds__(kThreads) void csr_batch_kernel(const CsrJob<Real> 
 // general graphs, binomial logit model (Sec. 3.2 with Polya-Gamma
 // augmentation): two launches per color
 // ---------------------------------------------------------------------------
-// psi_p ~ PG(m_p, beta0 + x_p) is the sum of m_p PG(1, .) terms.  The terms
-// of all sites are cut into chunks of kPgChunk consecutive terms of one site,
-// and the term kernel runs one thread per chunk over the whole graph at the
-// start of the sweep (so work is spread evenly whatever the m_p), writing
-// each chunk's sum; it reads each site's value at the start of the sweep,
-// which is the value the site's own color pass sees.  The site kernel of a
-// color then runs one wavefront per site: the lanes add the site's chunk
-// sums (lane l takes chunks l, l + 64, ...; a fixed tree joins the lanes)
-// and lane 0 draws x_p from N(m, 1/Q), Q = tau D_pp + psi_p,
-// m = (kappa_p - psi_p beta0 + tau rho sum_{j~p} x_j) / Q.
-constexpr int kBinomSites = kThreads / 64;      // sites per block of the site kernel
-constexpr int kPgChunk = 2;                     // PG(1, .) terms per chunk
+// psi_p ~ PG(m_p, beta0 + x_p) is the sum of m_p PG(1, .) terms.  Every
+// psi_p of a sweep depends only on beta0 and site p's value at the start of
+// the sweep (no color pass changes a site before its own), so all of them
+// are drawn before the color passes:
+//   * the envelope kernel, one thread per site;
+//   * the term kernel: the terms of all sites are cut into chunks of
+//     kPgChunk consecutive terms of one site, one thread per chunk over the
+//     whole graph (so work is spread evenly whatever the m_p).  Chunk q runs
+//     on lane q mod 64 and the chunks of a site are consecutive, so a site's
+//     chunks fall into one run of lanes per wavefront; a segmented scan over
+//     the lanes leaves each run's sum in its last chunk's slot;
+//   * the psi kernel, one wavefront per site: psi_p is the sum of the site's
+//     run sums (at most m_p / (64 kPgChunk) + 2 of them), lane l taking runs
+//     l, l + 64, ... and a fixed tree joining the lanes.
+// Each color pass then runs one thread per site: x_p ~ N(m, 1/Q) with
+// Q = tau D_pp + psi_p, m = (kappa_p - psi_p beta0 + tau rho sum_{j~p} x_j) / Q.
+constexpr int kPsiSites = kThreads / 64;        // sites per block of the psi kernel
+#ifndef GMRF_PG_CHUNK
+#define GMRF_PG_CHUNK 2
+#endif
+constexpr int kPgChunk = GMRF_PG_CHUNK;         // PG(1, .) terms per chunk
 #ifndef GMRF_PG_ENV_PREPASS
 #define GMRF_PG_ENV_PREPASS 1
 #endif
@@ -913,34 +923,75 @@ __global__ __launch_bounds__(kThreads) void pg_env_kernel(CsrArgs<Real> ca, Swee
     ca.env[p] = pg_envelope(b0 + (double)ca.x[p]);
 }
 
+// Chunks 0 .. nq - 1; the grid is whole blocks of whole wavefronts, so chunk
+// q runs on lane q mod 64.
 template <typename Real, bool B0>
-__global__ __launch_bounds__(kThreads) void pg_chunk_kernel(CsrArgs<Real> ca, SweepArgs a, int q0,
-                                                            int nq)
+__global__ __launch_bounds__(kThreads) void pg_chunk_kernel(CsrArgs<Real> ca, SweepArgs a, int nq)
 {
-    const int g = (int)blockIdx.x * kThreads + (int)threadIdx.x;
-    if (g >= nq)
-        return;
-    const int q = q0 + g;
-    const int p = ca.chunk_site[q];
-    const int m = ca.trials[p];
-    const int j0 = (q - ca.chunk_off[p]) * kPgChunk;
-    const int j1 = min(j0 + kPgChunk, m);
-    const unsigned t = (unsigned)a.st->sweep;
-    const double b0 = B0 ? a.st->beta0 : 0.0;
-    const unsigned id = (unsigned)ca.orig[p];
-    const PgEnvelope env = kPgEnvPrepass ? ca.env[p] : pg_envelope(b0 + (double)ca.x[p]);
+    const int q = (int)blockIdx.x * kThreads + (int)threadIdx.x;
+    const int lane = (int)threadIdx.x & 63;
+    const bool valid = q < nq;
+    const int p = valid ? ca.chunk_site[q] : -1;
     double sum = 0.0;
-    bool ok = true;
-    for (int j = j0; j < j1; ++j) {
-        double v = 0.0;
-        ok = pg1_draw(env, a.seed, id, t, a.instance, (unsigned)j, &v) && ok;
-        sum += v;
+    if (valid) {
+        const int m = ca.trials[p];
+        const int j0 = (q - ca.chunk_off[p]) * kPgChunk;
+        const int j1 = min(j0 + kPgChunk, m);
+        const unsigned t = (unsigned)a.st->sweep;
+        const double b0 = B0 ? a.st->beta0 : 0.0;
+        const unsigned id = (unsigned)ca.orig[p];
+        const PgEnvelope env = kPgEnvPrepass ? ca.env[p] : pg_envelope(b0 + (double)ca.x[p]);
+        bool ok = true;
+        for (int j = j0; j < j1; ++j) {
+            double v = 0.0;
+            ok = pg1_draw(env, a.seed, id, t, a.instance, (unsigned)j, &v) && ok;
+            sum += v;
+        }
+        if (!ok)
+            atomicOr(&a.st->status, kStatusGamma);
     }
-    if (!ok)
-        atomicOr(&a.st->status, kStatusGamma);
-    ca.chunk_sum[q] = sum;
+    // Segmented inclusive scan over the lanes, segments = runs of one site
+    // (lanes past nq form a run of their own and store nothing).
+    const int prev = __shfl_up(p, 1, 64), next = __shfl_down(p, 1, 64);
+    const unsigned long long heads = __ballot(lane == 0 || prev != p);
+    const unsigned long long upto = heads & ((2ull << lane) - 1ull);   // lanes 0 .. lane
+    const int start = 63 - __builtin_clzll(upto);                      // lane 0 is a head
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double o = __shfl_up(sum, off, 64);
+        if (lane - off >= start)
+            sum += o;
+    }
+    if (valid && (lane == 63 || next != p))
+        ca.chunk_sum[q] = sum;
 }
 
+// psi_p of sites lo .. lo + cnt - 1, one wavefront per site.  The run sums
+// of site p sit in the last chunk of each run: at the chunks q = 63 mod 64
+// inside [c0, c1 - 1) (run r at (c0 | 63) + 64 r) and at c1 - 1 (the last run).
+template <typename Real>
+__global__ __launch_bounds__(kThreads) void pg_psi_kernel(CsrArgs<Real> ca, int lo, int cnt)
+{
+    const int lane = (int)threadIdx.x & 63;
+    const int p = lo + (int)blockIdx.x * kPsiSites + ((int)threadIdx.x >> 6);
+    if (p >= lo + cnt)      // uniform across the wavefront
+        return;
+    const int c0 = ca.chunk_off[p], c1 = ca.chunk_off[p + 1];
+    double part = 0.0;
+    if (c1 > c0) {
+        const int qa = c0 | 63, ql = c1 - 1;
+        const int runs = (qa < ql ? (ql - qa + 63) / 64 : 0) + 1;
+        for (int r = lane; r < runs; r += 64)
+            part += ca.chunk_sum[r == runs - 1 ? ql : qa + 64 * r];
+    }
+    const double psi = wave_sum(part);
+    if (lane == 0)
+        ca.psi[p] = psi;
+}
+
+// One color pass of the binomial model, one site per thread (the PG terms
+// drawn beforehand).  Neighbours as in the Gaussian pass: the first kCsrBatch in
+// one batch, kept in registers for the edge terms, in row order.
 template <typename Real, bool B0>
 __global__ __launch_bounds__(kThreads) void csr_binomial_pass_kernel(CsrArgs<Real> ca, SweepArgs a,
                                                                      int lo, int cnt, int slot_base)
@@ -949,60 +1000,71 @@ __global__ __launch_bounds__(kThreads) void csr_binomial_pass_kernel(CsrArgs<Rea
     const double tau_d = a.st->tau;
     const double b0 = B0 ? a.st->beta0 : 0.0;
     const Real tau = (Real)tau_d, tau_rho = (Real)(tau_d * a.rho);
-    const int lane = (int)threadIdx.x & 63;
-    const int p = lo + (int)blockIdx.x * kBinomSites + ((int)threadIdx.x >> 6);
+    const int p = lo + (int)blockIdx.x * kThreads + (int)threadIdx.x;
     Red rd;
-    if (p < lo + cnt) {     // uniform across the wavefront
-        const unsigned id = (unsigned)ca.orig[p];
-        double part = 0.0;
-        for (int k = ca.chunk_off[p] + lane; k < ca.chunk_off[p + 1]; k += 64)
-            part += ca.chunk_sum[k];
-        const double psi = __shfl(wave_sum(part), 0, 64);
-        // neighbour sum over the lanes (lane l takes neighbours l, l + 64, ...)
+    if (p < lo + cnt) {
         const int e0 = ca.row_ptr[p], e1 = ca.row_ptr[p + 1];
         const int deg = e1 - e0;
-        Real nsum = (Real)0;
-        for (int e = e0 + lane; e < e1; e += 64)
-            nsum += ca.x[ca.col[e]];
-        const Real s = __shfl(wave_sum(nsum), 0, 64);
-        Real xn = (Real)0;
-        if (lane == 0) {
-            const double kappa = (double)ca.y[p];
-            const Real Q = fma(tau, (Real)deg, (Real)psi);
-            Real inv_q, isd;
-            if constexpr (sizeof(Real) == 8) {
-                inv_q = 1.0 / Q;
-                isd = 1.0 / sqrt(Q);
-            } else {
-                inv_q = 1.0f / Q;
-                isd = __builtin_amdgcn_rsqf(Q);
-            }
-            const Real beff = (Real)(kappa - psi * b0);
-            const Real z = site_normal<Real>(draw_words(a.seed, id, t, a.instance, 0u));
-            xn = fma(z, isd, fma(tau_rho, s, beff) * inv_q);
-            ca.x[p] = xn;
+        const double kappa = (double)ca.y[p];
+        const double psi = ca.psi[p];
+        const unsigned id = (unsigned)ca.orig[p];
+        const bool acc = (long long)t >= a.burn_in;
+        double o1 = 0.0, o2 = 0.0;
+        if (acc) {
+            o1 = a.s1[p];
+            o2 = a.s2[p];
         }
+        int cj[kCsrBatch];
+        Real nb[kCsrBatch];
+#pragma unroll
+        for (int k = 0; k < kCsrBatch; ++k)
+            cj[k] = ca.col[min(e0 + k, max(e1 - 1, 0))];   // clamped; used only if k < deg
+#pragma unroll
+        for (int k = 0; k < kCsrBatch; ++k)
+            nb[k] = ca.x[cj[k]];
+        Real s = (Real)0;
+#pragma unroll
+        for (int k = 0; k < kCsrBatch; ++k)
+            if (k < deg)
+                s += nb[k];
+        for (int e = e0 + kCsrBatch; e < e1; ++e)
+            s += ca.x[ca.col[e]];
+        const Real Q = fma(tau, (Real)deg, (Real)psi);
+        Real inv_q, isd;
+        if constexpr (sizeof(Real) == 8) {
+            inv_q = 1.0 / Q;
+            isd = 1.0 / sqrt(Q);
+        } else {
+            inv_q = 1.0f / Q;
+            isd = __builtin_amdgcn_rsqf(Q);
+        }
+        const Real beff = (Real)(kappa - psi * b0);
+        const Real z = site_normal<Real>(draw_words(a.seed, id, t, a.instance, 0u));
+        const Real xn = fma(z, isd, fma(tau_rho, s, beff) * inv_q);
+        ca.x[p] = xn;
         // edge terms of the lower-colored neighbours (already final this sweep)
-        const double xd = (double)__shfl(xn, 0, 64);
+        const double xd = (double)xn;
         double edge = 0.0;
-        for (int e = e0 + lane; e < e1; e += 64) {
+#pragma unroll
+        for (int k = 0; k < kCsrBatch; ++k)
+            if (k < deg && cj[k] < lo) {
+                const double d = xd - (double)nb[k];
+                edge += d * d;
+            }
+        for (int e = e0 + kCsrBatch; e < e1; ++e) {
             const int j = ca.col[e];
             if (j < lo) {
                 const double d = xd - (double)ca.x[j];
                 edge += d * d;
             }
         }
-        edge = wave_sum(edge);
-        if (lane == 0) {
-            const double kappa = (double)ca.y[p];
-            rd.q = (1.0 - a.rho) * (double)deg * xd * xd + a.rho * edge;
-            rd.sse = psi;
-            rd.rsum = kappa - psi * xd;
-            if ((long long)t >= a.burn_in) {
-                const double eta = B0 ? xd + b0 : xd;   // accumulated linear predictor
-                a.s1[p] += eta;
-                a.s2[p] += eta * eta;
-            }
+        rd.q = (1.0 - a.rho) * (double)deg * xd * xd + a.rho * edge;
+        rd.sse = psi;
+        rd.rsum = kappa - psi * xd;
+        if (acc) {
+            const double eta = B0 ? xd + b0 : xd;   // accumulated linear predictor
+            a.s1[p] = o1 + eta;
+            a.s2[p] = o2 + eta * eta;
         }
     }
     write_partials<kThreads>(a, rd, slot_base + (int)blockIdx.x);
@@ -1090,6 +1152,7 @@ struct gmrf_chain {
     int *d_chunk_site = nullptr;
     double *d_chunk_sum = nullptr;
     PgEnvelope *d_env = nullptr;
+    double *d_psi = nullptr;
     std::vector<int> color_chunk;     // binomial: first chunk of each color (k + 1)
     std::vector<int> pass_blocks;     // CSR: blocks per color pass
     uint64_t host_sweeps = 0;         // sweeps enqueued (host view)
@@ -1183,8 +1246,8 @@ int max_lattice_blocks(const HostGraph &h)
 }
 
 // Chain workspace layout; ptrs may be NULL to only compute the size.  A
-// binomial chain adds the trials array, and its color passes take
-// kBinomSites sites per block.
+// binomial chain adds the trials, the term chunk tables, and per-site
+// envelopes and psi.
 size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chain *c,
                     bool binomial, int64_t n_chunks = 0)
 {
@@ -1204,8 +1267,7 @@ size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chai
     } else {
         for (int32_t col = 0; col < g->h.k; ++col) {
             const int cnt = g->h.slab_offsets[col + 1] - g->h.slab_offsets[col];
-            const int per = binomial ? kBinomSites : kThreads;
-            const int nb = (cnt + per - 1) / per;
+            const int nb = (cnt + kThreads - 1) / kThreads;
             pass_blocks.push_back(nb);
             slots += nb;
         }
@@ -1224,7 +1286,9 @@ size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chai
     char *chunk_site = binomial ? take(4 * (size_t)std::max<int64_t>(n_chunks, 1)) : nullptr;
     char *chunk_sum = binomial ? take(8 * (size_t)std::max<int64_t>(n_chunks, 1)) : nullptr;
     char *env = binomial ? take(sizeof(PgEnvelope) * (size_t)n) : nullptr;
+    char *psi = binomial ? take(8 * (size_t)n) : nullptr;
     if (c) {
+        c->d_psi = reinterpret_cast<double *>(psi);
         c->d_trials = reinterpret_cast<int *>(trials);
         c->d_chunk_off = reinterpret_cast<int *>(chunk_off);
         c->d_chunk_site = reinterpret_cast<int *>(chunk_site);
@@ -1298,6 +1362,7 @@ template <typename Real> CsrArgs<Real> csr_args(const gmrf_chain *c)
     ca.chunk_site = c->d_chunk_site;
     ca.chunk_sum = c->d_chunk_sum;
     ca.env = c->d_env;
+    ca.psi = c->d_psi;
     return ca;
 }
 
@@ -1374,29 +1439,36 @@ void launch_csr(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent
     for (int32_t col = 0; col < h.k; ++col)
         if (c->pass_blocks[col] > 0)
             last = col;
-    // Binomial: every psi_p depends only on beta0 and the site's value at the
-    // start of the sweep (no pass changes a site before its own), so the
-    // envelopes and all PG terms of the sweep are drawn up front, in one
-    // launch each, before the color passes.
-    const int nq_all = c->binomial ? c->color_chunk[h.k] : 0;
-    if (nq_all > 0 && kPgEnvPrepass) {
+    // Binomial: the envelopes, the PG terms and psi of every site, one launch
+    // each, before the color passes (psi alone when no site has trials).
+    if (c->binomial) {
+        const int nq = c->color_chunk[h.k];
+        const int nsite = (int)h.n;
         auto ek = c->model.intercept ? pg_env_kernel<Real, true> : pg_env_kernel<Real, false>;
-        const int eb = (int)((h.n + kThreads - 1) / kThreads);
-        if (ev0)
-            hipExtLaunchKernelGGL(ek, dim3(eb), dim3(kThreads), 0, s, ev0, nullptr, 0, ca, a, 0,
-                                  (int)h.n);
-        else
-            hipLaunchKernelGGL(ek, dim3(eb), dim3(kThreads), 0, s, ca, a, 0, (int)h.n);
-        ev0 = nullptr;
-    }
-    if (nq_all > 0) {
         auto tk = c->model.intercept ? pg_chunk_kernel<Real, true> : pg_chunk_kernel<Real, false>;
-        const int tb = (nq_all + kThreads - 1) / kThreads;
+        const int eb = (nsite + kThreads - 1) / kThreads, tb = (nq + kThreads - 1) / kThreads;
+        const int pb = (nsite + kPsiSites - 1) / kPsiSites;
+        if (nq > 0 && kPgEnvPrepass) {
+            if (ev0)
+                hipExtLaunchKernelGGL(ek, dim3(eb), dim3(kThreads), 0, s, ev0, nullptr, 0, ca, a,
+                                      0, nsite);
+            else
+                hipLaunchKernelGGL(ek, dim3(eb), dim3(kThreads), 0, s, ca, a, 0, nsite);
+            ev0 = nullptr;
+        }
+        if (nq > 0) {
+            if (ev0)
+                hipExtLaunchKernelGGL(tk, dim3(tb), dim3(kThreads), 0, s, ev0, nullptr, 0, ca, a,
+                                      nq);
+            else
+                hipLaunchKernelGGL(tk, dim3(tb), dim3(kThreads), 0, s, ca, a, nq);
+            ev0 = nullptr;
+        }
         if (ev0)
-            hipExtLaunchKernelGGL(tk, dim3(tb), dim3(kThreads), 0, s, ev0, nullptr, 0, ca, a, 0,
-                                  nq_all);
+            hipExtLaunchKernelGGL(pg_psi_kernel<Real>, dim3(pb), dim3(kThreads), 0, s, ev0,
+                                  nullptr, 0, ca, 0, nsite);
         else
-            hipLaunchKernelGGL(tk, dim3(tb), dim3(kThreads), 0, s, ca, a, 0, nq_all);
+            hipLaunchKernelGGL(pg_psi_kernel<Real>, dim3(pb), dim3(kThreads), 0, s, ca, 0, nsite);
         ev0 = nullptr;
     }
     for (int32_t col = 0; col < h.k; ++col) {

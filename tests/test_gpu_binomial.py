@@ -130,6 +130,34 @@ def test_binomial_fp32_agrees_statistically(G, orc):
     assert np.corrcoef(m32, wl["truth"])[0, 1] > 0.5
 
 
+@pytest.mark.parametrize("layout", ["mixed", "no_trials"])
+def test_binomial_extreme_trial_counts(G, orc, layout):
+    """Sites without trials (psi = 0) next to one site with 5,000 trials,
+    whose 2,500 PG term chunks span many wavefronts; and a graph with no
+    trials at all (no PG terms to draw)."""
+    wl = case(G, n=500, median=10.0, seed=12)
+    trials, y = wl["trials"].copy(), wl["y"].copy()
+    if layout == "mixed":
+        trials[::3], y[::3] = 0, 0.0
+        trials[5], y[5] = 5000, 2400.0
+        trials[6], y[6] = 130, 70.0       # a run that starts mid-wavefront
+    else:
+        trials[:], y[:] = 0, 0.0
+    wl["trials"], wl["y"] = trials, y
+    g, ch, oc = pair(G, orc, wl, seed=13, instance=1)
+    for _ in range(3):
+        ch.sweep(1)
+        oc.sweeps(1)
+        x, tau, _, _ = ch.get_state()
+        q, spsi = ch.last_reductions()
+        assert rel(x, oc.x) <= RTOL64 and rel(tau, oc.tau) <= RTOL64
+        assert rel(ch.beta0, oc.beta0) <= RTOL64
+        if layout == "no_trials":
+            assert spsi == 0.0 and oc.sse == 0.0
+        else:
+            assert rel(spsi, oc.sse) <= RTOL64
+
+
 def test_binomial_argument_errors(G):
     wl = case(G, n=300, median=10.0, seed=1)
     g = G.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=wl["color"], num_colors=wl["k"],
