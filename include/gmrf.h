@@ -31,10 +31,12 @@
  * Binomial logit model (Sec. 3.2, general graphs, gmrf_chain_create_binomial):
  *     Y_i ~ Bin(m_i, pi_i),  logit(pi_i) = beta0 + x_i,  beta0 ~ N(0, v0)
  * made conditionally Gaussian by Polya-Gamma augmentation (Polson, Scott &
- * Windle 2013): with kappa_i = Y_i - m_i / 2, each site of the current color
- * first draws psi_i ~ PG(m_i, beta0 + x_i) from its old x_i (a sum of m_i
- * PG(1, .) terms, Devroye's alternating-series sampler; the terms of a color
- * are drawn by one launch in chunks of 2, then added per site), then
+ * Windle 2013): with kappa_i = Y_i - m_i / 2, each site draws
+ * psi_i ~ PG(m_i, beta0 + x_i) from its value before its color's pass (a sum
+ * of m_i PG(1, .) terms, Devroye's alternating-series sampler).  Since psi_i
+ * depends only on beta0 and site i's own value, which no earlier color pass
+ * changes, the library draws every psi_i of a sweep before the color passes
+ * (one launch for all terms, in chunks of 2, then one sum per site); then
  *     Qii = tau * D_ii + psi_i,
  *     m_i = (kappa_i - psi_i beta0 + tau * rho * sum_{j~i} x_j) / Qii,
  * and after the sweep beta0 ~ N(sum(kappa - psi x) / P, 1/P),
@@ -200,8 +202,8 @@ int gmrf_chain_destroy(gmrf_chain *c);
 
 /* Device workspace bytes of one binomial chain on a general graph g with the
  * given trials (host, n values m_i, original order): the Gaussian layout plus
- * the trials, the Polya-Gamma term chunk tables and the chunk sums (about
- * 6 bytes per trial).  Returns 0 and sets the error message on bad input. */
+ * the trials, the Polya-Gamma term chunk tables and sums (about 6 bytes per
+ * trial), and a per-site envelope and psi (about 40 bytes per site).  Returns 0 and sets the error message on bad input. */
 size_t gmrf_binomial_footprint(const gmrf_graph *g, gmrf_precision p, const int32_t *trials);
 
 /* Create a binomial logit chain (Sec. 3.2) on a general graph: successes
@@ -228,9 +230,10 @@ int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t strea
 
 /* Profiling form of gmrf_sweep (plain launches, no capture): the same sweeps,
  * with a pair of HIP events that the dispatches themselves record at the
- * start and the end of the sweep kernels of every sweep (the lattice kernel,
- * or the first to the last kernel of the color passes of a general graph),
- * excluding the one-block finish kernel that sums the reductions and draws
+ * start and the end of the sweep kernels of every sweep (the lattice kernel;
+ * on a general graph, from its first launch, which for the binomial model is
+ * the first Polya-Gamma kernel, to the last color pass), excluding the
+ * one-block finish kernel that sums the reductions and draws
  * the hyperparameters.  Synchronises and returns in *kernel_ms the summed
  * event time of the sweep kernels over the nsweeps sweeps and, if span_ms is
  * not NULL, the elapsed time from the start of the first sweep kernel to the

@@ -1153,7 +1153,7 @@ struct gmrf_chain {
     double *d_chunk_sum = nullptr;
     PgEnvelope *d_env = nullptr;
     double *d_psi = nullptr;
-    std::vector<int> color_chunk;     // binomial: first chunk of each color (k + 1)
+    int n_chunks = 0;                 // binomial: PG term chunks of all sites
     std::vector<int> pass_blocks;     // CSR: blocks per color pass
     uint64_t host_sweeps = 0;         // sweeps enqueued (host view)
     hipStream_t capture_stream = nullptr;
@@ -1442,7 +1442,7 @@ void launch_csr(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent
     // Binomial: the envelopes, the PG terms and psi of every site, one launch
     // each, before the color passes (psi alone when no site has trials).
     if (c->binomial) {
-        const int nq = c->color_chunk[h.k];
+        const int nq = c->n_chunks;
         const int nsite = (int)h.n;
         auto ek = c->model.intercept ? pg_env_kernel<Real, true> : pg_env_kernel<Real, false>;
         auto tk = c->model.intercept ? pg_chunk_kernel<Real, true> : pg_chunk_kernel<Real, false>;
@@ -1599,9 +1599,7 @@ int upload_trials_layout(gmrf_chain *c, const int32_t *trials, hipStream_t s)
     for (int64_t p = 0; p < n; ++p)
         for (int q = off[p]; q < off[p + 1]; ++q)
             site[q] = (int32_t)p;
-    c->color_chunk.assign(h.k + 1, 0);
-    for (int32_t col = 0; col <= h.k; ++col)
-        c->color_chunk[col] = off[h.slab_offsets[col]];
+    c->n_chunks = off[n];
     GMRF_HIP(hipMemcpyAsync(c->d_trials, buf.data(), 4 * n, hipMemcpyHostToDevice, s));
     GMRF_HIP(hipMemcpyAsync(c->d_chunk_off, off.data(), 4 * (n + 1), hipMemcpyHostToDevice, s));
     GMRF_HIP(hipMemcpyAsync(c->d_chunk_site, site.data(), 4 * site.size(), hipMemcpyHostToDevice,
@@ -1903,6 +1901,10 @@ size_t gmrf_chain_footprint(const gmrf_graph *g, gmrf_precision p)
 }
 
 // Number of PG term chunks of a binomial chain (trials in original order).
+// Most PG term chunks of one chain: chunk indices, and the grid of one thread
+// per chunk rounded up to whole blocks, stay within int.
+constexpr int64_t kMaxChunks = INT32_MAX - kThreads;
+
 static int64_t count_chunks(const gmrf_graph *g, const int32_t *trials)
 {
     int64_t nc = 0;
@@ -1919,7 +1921,7 @@ size_t gmrf_binomial_footprint(const gmrf_graph *g, gmrf_precision p, const int3
         return 0;
     }
     const int64_t nc = count_chunks(g, trials);
-    if (nc > INT32_MAX) {
+    if (nc > kMaxChunks) {
         set_error("binomial_footprint: too many trials in total");
         return 0;
     }
@@ -1993,7 +1995,7 @@ static int chain_create_impl(const char *who, const gmrf_graph *g, const gmrf_mo
             kappa[i] = y[i] - 0.5 * (double)trials[i];
     }
     const int64_t n_chunks = binomial ? count_chunks(g, trials) : 0;
-    if (n_chunks > INT32_MAX)
+    if (n_chunks > kMaxChunks)
         return fail(GMRF_E_INVALID_ARG, w + ": too many trials in total");
     const size_t need = chain_layout(g, p, nullptr, nullptr, binomial, n_chunks);
     if (!d_ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0)
