@@ -300,23 +300,31 @@ int gmrf_set_intercept(gmrf_chain *c, double beta0, hipStream_t stream);
  * the trace off, no later sweep writes the old buffer.  Synchronises. */
 int gmrf_set_trace(gmrf_chain *c, double *d_trace, int64_t capacity, hipStream_t stream);
 
-/* Lattice tile shape of a chain (Sec. 2.3: the color phases of a lattice
- * sweep run tile by tile).  Shape 0 is a 64 x 64 tile with 512 threads,
- * shape 1 a 32 x 32 tile with 256 threads; shape 2 (lattices of at most
- * 64 x 64 sites) is shape 0's single tile swept by a persistent one-block
- * kernel that runs all the sweeps of a gmrf_sweep call, with their draws, in
- * one launch (bitwise the results of shape 0).  A new lattice chain starts
- * with shape 2 if the lattice fits one 64 x 64 tile, else with shape 0 if
- * that gives at least 512 tiles, else shape 1.  The shape
- * changes the grouping, hence the summation order, of the FP64 reductions
- * (results agree to rounding, not bit for bit, between shapes 0 and 1); the
- * draws of x are keyed by site and do not depend on it.  gmrf_chain_get_tile
- * reports the shape (-1 for a general graph, whose passes use 256-thread
- * blocks); any output pointer may be NULL.  gmrf_chain_set_tile (lattice
- * chains only) drops the chain's captured sweeps; a batch keeps the shapes
- * its chains had when it was created (shape 2 is batched as shape 0).  For a
- * shape-2 chain gmrf_sweep_timed reports the duration of the single launch
- * (draws included) as both kernel and span time.  Host-only calls. */
+/* Launch shape of a chain.  Lattices (Sec. 2.3: the color phases of a
+ * lattice sweep run tile by tile): shape 0 is a 64 x 64 tile with 512
+ * threads, shape 1 a 32 x 32 tile with 256 threads; shape 2 (lattices of at
+ * most 64 x 64 sites) is shape 0's single tile swept by a persistent
+ * one-block kernel that runs all the sweeps of a gmrf_sweep call, with their
+ * draws, in one launch (bitwise the results of shape 0).  A new lattice chain
+ * starts with shape 2 if the lattice fits one 64 x 64 tile, else with shape 0
+ * if that gives at least 512 tiles, else shape 1.  Shapes 0 and 1 group the
+ * FP64 reductions differently (results agree to rounding, not bit for bit);
+ * the draws of x are keyed by site and do not depend on the shape.
+ * General graphs: shape 0 launches one kernel per color (256-thread blocks)
+ * and the finish kernel; shape 2 (a field of at most 122880 bytes, at most 32
+ * colors) runs the color passes and the draws in one 512-thread block with
+ * the field in LDS -- all the sweeps of a call in one launch, or, for the
+ * binomial model, one sweep per launch after the Polya-Gamma launches --
+ * bitwise the results of shape 0.  A new general-graph chain starts with
+ * shape 2 if it fits and no color has more than 1024 sites, else shape 0.
+ * gmrf_chain_get_tile reports the shape, the tile size (0 x 0 for a general
+ * graph) and the threads per block; any output pointer may be NULL.
+ * gmrf_chain_set_tile drops the chain's captured sweeps; a batch keeps the
+ * shapes its chains had when it was created (shape 2 is batched as shape 0).
+ * For a shape-2 chain gmrf_sweep_timed reports the duration of the single
+ * launch (draws included) as both kernel and span time (binomial: the
+ * Polya-Gamma launches and the one-block launch of each sweep).  Host-only
+ * calls. */
 int gmrf_chain_get_tile(const gmrf_chain *c, int32_t *tile, int32_t *tile_rows, int32_t *tile_cols,
                         int32_t *threads);
 int gmrf_chain_set_tile(gmrf_chain *c, int32_t tile);

@@ -776,77 +776,128 @@ template <typename Real> struct CsrArgs {
 // row order, i.e. ascending original neighbour id.
 constexpr int kCsrBatch = 8;
 
+// Scalars of the chain state that a color pass reads.
+struct CsrScalars {
+    double tau, lam, beta0;
+    unsigned t;
+    bool acc;                   // this sweep adds to the posterior accumulators
+};
+
+__device__ __forceinline__ CsrScalars csr_scalars(const SweepArgs &a, bool b0)
+{
+    CsrScalars v;
+    v.tau = a.st->tau;
+    v.lam = a.st->lam;
+    v.beta0 = b0 ? a.st->beta0 : 0.0;
+    v.t = (unsigned)a.st->sweep;
+    v.acc = (long long)v.t >= a.burn_in;
+    return v;
+}
+
+// Site p (slab position) of the color slab starting at lo: the update of
+// Algorithm 1 with the field read from and written to x (the global state,
+// or its copy in LDS), the accumulators, and this site's q / sse / rsum
+// terms added to rd.  Gaussian (Sec. 3.1): Qii = tau D_ii + lam,
+// m = (lam (y_i - beta0) + tau rho s_i) / Qii.  Binomial (BIN, Sec. 3.2 with
+// psi_p drawn beforehand): Qii = tau D_ii + psi_p,
+// m = (kappa_p - psi_p beta0 + tau rho s_i) / Qii, and the sse / rsum slots
+// take psi_p and kappa_p - psi_p x_p.
+template <typename Real, bool B0, bool BIN>
+__device__ __forceinline__ void csr_site(const CsrArgs<Real> &ca, const SweepArgs &a, Real *x,
+                                         const int p, const int lo, const CsrScalars &v, Red &rd)
+{
+    const Real tau = (Real)v.tau, tau_rho = (Real)(v.tau * a.rho);
+    const int e0 = ca.row_ptr[p], e1 = ca.row_ptr[p + 1];
+    const int deg = e1 - e0;
+    const Real yv = ca.y[p];
+    const double psi = BIN ? ca.psi[p] : 0.0;
+    const unsigned id = (unsigned)ca.orig[p];
+    double o1 = 0.0, o2 = 0.0;
+    if (v.acc) {
+        o1 = a.s1[p];
+        o2 = a.s2[p];
+    }
+    int cj[kCsrBatch];
+    Real nb[kCsrBatch];
+#pragma unroll
+    for (int k = 0; k < kCsrBatch; ++k)
+        cj[k] = ca.col[min(e0 + k, max(e1 - 1, 0))];   // clamped; used only if k < deg
+#pragma unroll
+    for (int k = 0; k < kCsrBatch; ++k)
+        nb[k] = x[cj[k]];
+    Real s = (Real)0;
+#pragma unroll
+    for (int k = 0; k < kCsrBatch; ++k)
+        if (k < deg)
+            s += nb[k];
+    for (int e = e0 + kCsrBatch; e < e1; ++e)
+        s += x[ca.col[e]];
+    const Real z = site_normal<Real>(draw_words(a.seed, id, v.t, a.instance, 0u));
+    Real xn;
+    if constexpr (BIN) {
+        const Real Q = fma(tau, (Real)deg, (Real)psi);
+        Real inv_q, isd;
+        if constexpr (sizeof(Real) == 8) {
+            inv_q = 1.0 / Q;
+            isd = 1.0 / sqrt(Q);
+        } else {
+            inv_q = 1.0f / Q;
+            isd = __builtin_amdgcn_rsqf(Q);
+        }
+        const Real beff = (Real)((double)yv - psi * v.beta0);
+        xn = fma(z, isd, fma(tau_rho, s, beff) * inv_q);
+    } else {
+        const Real lam = (Real)v.lam;
+        Real inv_q, isd;
+        site_scales<Real>(tau, lam, deg, inv_q, isd);
+        const Real yeff = B0 ? yv - (Real)v.beta0 : yv;
+        xn = site_draw<Real>(yeff, s, z, lam, tau_rho, inv_q, isd);
+    }
+    x[p] = xn;
+    const double xd = (double)xn;
+    double edge = 0.0;
+#pragma unroll
+    for (int k = 0; k < kCsrBatch; ++k)
+        if (k < deg && cj[k] < lo) {   // lower color: already final this sweep
+            const double d = xd - (double)nb[k];
+            edge += d * d;
+        }
+    for (int e = e0 + kCsrBatch; e < e1; ++e) {
+        const int j = ca.col[e];
+        if (j < lo) {
+            const double d = xd - (double)x[j];
+            edge += d * d;
+        }
+    }
+    rd.q += (1.0 - a.rho) * (double)deg * xd * xd + a.rho * edge;
+    if constexpr (BIN) {
+        rd.sse += psi;
+        rd.rsum += (double)yv - psi * xd;
+    } else {
+        const double rr = B0 ? (double)yv - v.beta0 - xd : (double)yv - xd;
+        rd.sse += rr * rr;
+        if (B0)
+            rd.rsum += rr;
+    }
+    if (v.acc) {
+        // accumulated image beta0 + x (the linear predictor for the binomial model)
+        const double phi = B0 ? xd + v.beta0 : xd;
+        a.s1[p] = o1 + phi;
+        a.s2[p] = o2 + phi * phi;
+    }
+}
+
 // Sites p0 + threadIdx.x of the color slab [lo, lo + cnt); partial slot `slot`.
-template <typename Real, bool B0>
+template <typename Real, bool B0, bool BIN>
 __device__ __forceinline__ void csr_pass_block(const CsrArgs<Real> &ca, const SweepArgs &a,
                                                const int lo, const int cnt, const int p0,
                                                const int slot)
 {
-    const unsigned t = (unsigned)a.st->sweep;
-    const double tau_d = a.st->tau, lam_d = a.st->lam;
-    const Real tau = (Real)tau_d, lam = (Real)lam_d, tau_rho = (Real)(tau_d * a.rho);
-    const double b0 = B0 ? a.st->beta0 : 0.0;
+    const CsrScalars v = csr_scalars(a, B0);
     const int p = p0 + (int)threadIdx.x;
     Red rd;
-    if (p < lo + cnt) {
-        const int e0 = ca.row_ptr[p], e1 = ca.row_ptr[p + 1];
-        const int deg = e1 - e0;
-        const Real yv = ca.y[p];
-        const unsigned id = (unsigned)ca.orig[p];
-        const bool acc = (long long)t >= a.burn_in;
-        double o1 = 0.0, o2 = 0.0;
-        if (acc) {
-            o1 = a.s1[p];
-            o2 = a.s2[p];
-        }
-        int cj[kCsrBatch];
-        Real nb[kCsrBatch];
-#pragma unroll
-        for (int k = 0; k < kCsrBatch; ++k)
-            cj[k] = ca.col[min(e0 + k, max(e1 - 1, 0))];   // clamped; used only if k < deg
-#pragma unroll
-        for (int k = 0; k < kCsrBatch; ++k)
-            nb[k] = ca.x[cj[k]];
-        Real s = (Real)0;
-#pragma unroll
-        for (int k = 0; k < kCsrBatch; ++k)
-            if (k < deg)
-                s += nb[k];
-        for (int e = e0 + kCsrBatch; e < e1; ++e)
-            s += ca.x[ca.col[e]];
-        const Words4 w = draw_words(a.seed, id, t, a.instance, 0u);
-        const Real z = site_normal<Real>(w);
-        Real inv_q, isd;
-        site_scales<Real>(tau, lam, deg, inv_q, isd);
-        const Real yeff = B0 ? yv - (Real)b0 : yv;
-        const Real xn = site_draw<Real>(yeff, s, z, lam, tau_rho, inv_q, isd);
-        ca.x[p] = xn;
-        const double xd = (double)xn;
-        double edge = 0.0;
-#pragma unroll
-        for (int k = 0; k < kCsrBatch; ++k)
-            if (k < deg && cj[k] < lo) {   // lower color: already final this sweep
-                const double d = xd - (double)nb[k];
-                edge += d * d;
-            }
-        for (int e = e0 + kCsrBatch; e < e1; ++e) {
-            const int j = ca.col[e];
-            if (j < lo) {
-                const double d = xd - (double)ca.x[j];
-                edge += d * d;
-            }
-        }
-        rd.q = (1.0 - a.rho) * (double)deg * xd * xd + a.rho * edge;
-        const double rr = B0 ? (double)yv - b0 - xd : (double)yv - xd;
-        rd.sse = rr * rr;
-        if (B0)
-            rd.rsum = rr;
-        if (acc) {
-            const double phi = B0 ? xd + b0 : xd;   // accumulated image beta0 + x
-            a.s1[p] = o1 + phi;
-            a.s2[p] = o2 + phi * phi;
-        }
-    }
+    if (p < lo + cnt)
+        csr_site<Real, B0, BIN>(ca, a, ca.x, p, lo, v, rd);
     write_partials<kThreads>(a, rd, slot);
 }
 
@@ -854,7 +905,7 @@ template <typename Real, bool B0>
 __global__ __launch_bounds__(kThreads) void csr_pass_kernel(CsrArgs<Real> ca, SweepArgs a, int lo,
                                                             int cnt, int slot_base)
 {
-    csr_pass_block<Real, B0>(ca, a, lo, cnt, lo + (int)blockIdx.x * kThreads,
+    csr_pass_block<Real, B0, false>(ca, a, lo, cnt, lo + (int)blockIdx.x * kThreads,
                              slot_base + (int)blockIdx.x);
 }
 
@@ -874,7 +925,134 @@ __global__ __launch_bounds__(kThreads) void csr_batch_kernel(const CsrJob<Real> 
 {
     const CsrBlock bk = blocks[blockIdx.x];
     const CsrJob<Real> &j = jobs[bk.job];
-    csr_pass_block<Real, B0>(j.ca, j.a, bk.lo, bk.cnt, bk.p0, bk.slot);
+    csr_pass_block<Real, B0, false>(j.ca, j.a, bk.lo, bk.cnt, bk.p0, bk.slot);
+}
+
+// ---------------------------------------------------------------------------
+// general graphs whose field fits in LDS: one block, the field in LDS
+// ---------------------------------------------------------------------------
+// The field of a small general graph (n values within kCsrLdsBytes) stays in
+// LDS for the whole launch, and one block does what the k color-pass
+// launches and the finish kernel do, in the same order of operations: each
+// color's slab is cut into the same groups of kThreads sites as the pass
+// kernels' blocks (each wavefront takes 64 consecutive sites of a group,
+// every site in the lane it has there), the groups' FP64 partials land in
+// the same slots, and the slots are summed as the finish kernel sums them.
+// So the results are bitwise those of the color passes, without their
+// k + 1 launches per sweep, whose dispatch latency dominates small graphs.
+// A Gaussian chain runs all the sweeps of a call in one launch; a binomial
+// chain one sweep per launch, after its Polya-Gamma launches.
+constexpr int kCsrPersistThreads = 512;
+constexpr int kCsrPersistColors = 32;           // most colors the slab table holds
+constexpr int kCsrLdsBytes = 122880;            // LDS for the field (gfx950: 160 KB per CU)
+constexpr int kCsrPersistSlots = 160;           // n / kThreads + k slots at most
+struct SlabTable {
+    int off[kCsrPersistColors + 1];             // first slab position of each color, then n
+    int k;
+};
+
+template <typename Real, bool B0, bool BIN>
+__global__ __launch_bounds__(kCsrPersistThreads) void csr_persistent_kernel(CsrArgs<Real> ca,
+                                                                            SweepArgs a,
+                                                                            SlabTable sl,
+                                                                            int nsweeps)
+{
+    constexpr int NT = kCsrPersistThreads, GW = kThreads / 64;   // wavefronts per group
+    constexpr int GPI = NT / kThreads;                           // groups per iteration
+    __shared__ Real xs[kCsrLdsBytes / sizeof(Real)];
+    __shared__ double wpart[kCsrPersistSlots * GW * kPartials];   // wavefront sums of a group
+    __shared__ double red[kPartials * GW];
+    __shared__ double hyp[3];
+    const int n = sl.off[sl.k];
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    for (int p = (int)threadIdx.x; p < n; p += NT)
+        xs[p] = ca.x[p];
+    CsrScalars v = csr_scalars(a, B0);
+    long long nacc = a.st->n_acc;
+    lds_barrier();
+    for (int s = 0; s < nsweeps; ++s) {
+        int slot0 = 0;
+        for (int c = 0; c < sl.k; ++c) {
+            const int lo = sl.off[c], hi = sl.off[c + 1];
+            const int groups = (hi - lo + kThreads - 1) / kThreads;
+            for (int g0 = 0; g0 < groups; g0 += GPI) {
+                const int g = g0 + wave / GW, w = wave % GW;
+                const int p = lo + g * kThreads + w * 64 + lane;
+                Red rd;
+                if (g < groups && p < hi)
+                    csr_site<Real, B0, BIN>(ca, a, xs, p, lo, v, rd);
+                rd.q = wave_sum(rd.q);
+                rd.sse = wave_sum(rd.sse);
+                rd.rsum = wave_sum(rd.rsum);
+                if (lane == 0 && g < groups) {
+                    double *const wp = wpart + ((slot0 + g) * GW + w) * kPartials;
+                    wp[0] = rd.q;
+                    wp[1] = rd.sse;
+                    wp[2] = rd.rsum;
+                }
+            }
+            slot0 += groups;
+            lds_barrier();
+        }
+        // the finish kernel's sum: thread i < kThreads adds slots i, i + kThreads,
+        // ... (each slot the pass block's sum of its wavefronts, in order), then
+        // the fixed tree over the first kThreads threads
+        Red r;
+        if ((int)threadIdx.x < kThreads) {
+            for (int i = (int)threadIdx.x; i < slot0; i += kThreads) {
+                const double *const wp = wpart + i * GW * kPartials;
+                double q = wp[0], e = wp[1], m = wp[2];
+                for (int w = 1; w < GW; ++w) {
+                    q += wp[w * kPartials];
+                    e += wp[w * kPartials + 1];
+                    m += wp[w * kPartials + 2];
+                }
+                r.q += q;
+                r.sse += e;
+                r.rsum += m;
+            }
+        }
+        r.q = wave_sum(r.q);
+        r.sse = wave_sum(r.sse);
+        r.rsum = wave_sum(r.rsum);
+        if (lane == 0 && wave < GW) {
+            red[wave] = r.q;
+            red[GW + wave] = r.sse;
+            red[2 * GW + wave] = r.rsum;
+        }
+        lds_barrier();
+        if (threadIdx.x < 64) {
+            r.q = red[0];
+            r.sse = red[GW];
+            r.rsum = red[2 * GW];
+            for (int w = 1; w < GW; ++w) {
+                r.q += red[w];
+                r.sse += red[GW + w];
+                r.rsum += red[2 * GW + w];
+            }
+            const HyperIn out = end_of_sweep_draws(a, v.t, r, HyperIn{v.tau, v.lam, v.beta0},
+                                                   lane);
+            if (lane == 0) {
+                hyp[0] = out.tau;
+                hyp[1] = out.lam;
+                hyp[2] = out.beta0;
+            }
+        }
+        if (v.acc)
+            ++nacc;
+        lds_barrier();
+        v.tau = hyp[0];
+        v.lam = hyp[1];
+        v.beta0 = B0 ? hyp[2] : 0.0;
+        ++v.t;
+        v.acc = (long long)v.t >= a.burn_in;
+    }
+    for (int p = (int)threadIdx.x; p < n; p += NT)
+        ca.x[p] = xs[p];
+    if (threadIdx.x == 0) {
+        a.st->n_acc = nacc;
+        a.st->sweep = (unsigned long long)v.t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -990,84 +1168,13 @@ __global__ __launch_bounds__(kThreads) void pg_psi_kernel(CsrArgs<Real> ca, int 
 }
 
 // One color pass of the binomial model, one site per thread (the PG terms
-// drawn beforehand).  Neighbours as in the Gaussian pass: the first kCsrBatch in
-// one batch, kept in registers for the edge terms, in row order.
+// and psi drawn beforehand).
 template <typename Real, bool B0>
 __global__ __launch_bounds__(kThreads) void csr_binomial_pass_kernel(CsrArgs<Real> ca, SweepArgs a,
                                                                      int lo, int cnt, int slot_base)
 {
-    const unsigned t = (unsigned)a.st->sweep;
-    const double tau_d = a.st->tau;
-    const double b0 = B0 ? a.st->beta0 : 0.0;
-    const Real tau = (Real)tau_d, tau_rho = (Real)(tau_d * a.rho);
-    const int p = lo + (int)blockIdx.x * kThreads + (int)threadIdx.x;
-    Red rd;
-    if (p < lo + cnt) {
-        const int e0 = ca.row_ptr[p], e1 = ca.row_ptr[p + 1];
-        const int deg = e1 - e0;
-        const double kappa = (double)ca.y[p];
-        const double psi = ca.psi[p];
-        const unsigned id = (unsigned)ca.orig[p];
-        const bool acc = (long long)t >= a.burn_in;
-        double o1 = 0.0, o2 = 0.0;
-        if (acc) {
-            o1 = a.s1[p];
-            o2 = a.s2[p];
-        }
-        int cj[kCsrBatch];
-        Real nb[kCsrBatch];
-#pragma unroll
-        for (int k = 0; k < kCsrBatch; ++k)
-            cj[k] = ca.col[min(e0 + k, max(e1 - 1, 0))];   // clamped; used only if k < deg
-#pragma unroll
-        for (int k = 0; k < kCsrBatch; ++k)
-            nb[k] = ca.x[cj[k]];
-        Real s = (Real)0;
-#pragma unroll
-        for (int k = 0; k < kCsrBatch; ++k)
-            if (k < deg)
-                s += nb[k];
-        for (int e = e0 + kCsrBatch; e < e1; ++e)
-            s += ca.x[ca.col[e]];
-        const Real Q = fma(tau, (Real)deg, (Real)psi);
-        Real inv_q, isd;
-        if constexpr (sizeof(Real) == 8) {
-            inv_q = 1.0 / Q;
-            isd = 1.0 / sqrt(Q);
-        } else {
-            inv_q = 1.0f / Q;
-            isd = __builtin_amdgcn_rsqf(Q);
-        }
-        const Real beff = (Real)(kappa - psi * b0);
-        const Real z = site_normal<Real>(draw_words(a.seed, id, t, a.instance, 0u));
-        const Real xn = fma(z, isd, fma(tau_rho, s, beff) * inv_q);
-        ca.x[p] = xn;
-        // edge terms of the lower-colored neighbours (already final this sweep)
-        const double xd = (double)xn;
-        double edge = 0.0;
-#pragma unroll
-        for (int k = 0; k < kCsrBatch; ++k)
-            if (k < deg && cj[k] < lo) {
-                const double d = xd - (double)nb[k];
-                edge += d * d;
-            }
-        for (int e = e0 + kCsrBatch; e < e1; ++e) {
-            const int j = ca.col[e];
-            if (j < lo) {
-                const double d = xd - (double)ca.x[j];
-                edge += d * d;
-            }
-        }
-        rd.q = (1.0 - a.rho) * (double)deg * xd * xd + a.rho * edge;
-        rd.sse = psi;
-        rd.rsum = kappa - psi * xd;
-        if (acc) {
-            const double eta = B0 ? xd + b0 : xd;   // accumulated linear predictor
-            a.s1[p] = o1 + eta;
-            a.s2[p] = o2 + eta * eta;
-        }
-    }
-    write_partials<kThreads>(a, rd, slot_base + (int)blockIdx.x);
+    csr_pass_block<Real, B0, true>(ca, a, lo, cnt, lo + (int)blockIdx.x * kThreads,
+                                   slot_base + (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1145,7 +1252,8 @@ struct gmrf_chain {
     double *d_partials = nullptr;
     double *d_stats = nullptr;
     int total_slots = 0;              // partial slots of one sweep (current tile shape)
-    int lat_tile = 0;                 // lattice tile shape (index into kTiles)
+    int lat_tile = 0;                 // shape: lattice tile (index into kTiles); general
+                                      // graph: 0 color passes, kPersistent one block
     bool binomial = false;            // binomial logit likelihood (general graphs only)
     int *d_trials = nullptr;          // binomial: m_i in slab order
     int *d_chunk_off = nullptr;       // binomial: PG term chunk tables (see pg_chunk_kernel)
@@ -1408,11 +1516,43 @@ void launch_persistent_typed(const gmrf_chain *c, const SweepArgs &a, int nsweep
         hipLaunchKernelGGL(kern, dim3(1), dim3(Cfg::NT), 0, s, la, a, nsweeps);
 }
 
+SlabTable slab_table(const HostGraph &h)
+{
+    SlabTable sl{};
+    sl.k = h.k;
+    for (int32_t col = 0; col <= h.k; ++col)
+        sl.off[col] = (int)h.slab_offsets[col];
+    return sl;
+}
+
+// nsweeps sweeps (binomial: one, after the Polya-Gamma launches) of a shape-2
+// general-graph chain in one launch of the persistent kernel.
+template <typename Real>
+void launch_csr_persistent(const gmrf_chain *c, const SweepArgs &a, int nsweeps, hipStream_t s,
+                           hipEvent_t ev0, hipEvent_t ev1)
+{
+    const CsrArgs<Real> ca = csr_args<Real>(c);
+    const SlabTable sl = slab_table(c->g->h);
+    const bool b0 = c->model.intercept;
+    auto kern = c->binomial ? (b0 ? csr_persistent_kernel<Real, true, true>
+                                  : csr_persistent_kernel<Real, false, true>)
+                            : (b0 ? csr_persistent_kernel<Real, true, false>
+                                  : csr_persistent_kernel<Real, false, false>);
+    if (ev0 || ev1)
+        hipExtLaunchKernelGGL(kern, dim3(1), dim3(kCsrPersistThreads), 0, s, ev0, ev1, 0, ca, a,
+                              sl, nsweeps);
+    else
+        hipLaunchKernelGGL(kern, dim3(1), dim3(kCsrPersistThreads), 0, s, ca, a, sl, nsweeps);
+}
+
 void launch_persistent(const gmrf_chain *c, const SweepArgs &a, int nsweeps, hipStream_t s,
                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
     const bool f64 = c->prec == GMRF_FP64;
-    if (c->g->h.stencil == 4)
+    if (!is_lattice(c->g))
+        f64 ? launch_csr_persistent<double>(c, a, nsweeps, s, ev0, ev1)
+            : launch_csr_persistent<float>(c, a, nsweeps, s, ev0, ev1);
+    else if (c->g->h.stencil == 4)
         f64 ? launch_persistent_typed<double, 4>(c, a, nsweeps, s, ev0, ev1)
             : launch_persistent_typed<float, 4>(c, a, nsweeps, s, ev0, ev1);
     else
@@ -1420,7 +1560,41 @@ void launch_persistent(const gmrf_chain *c, const SweepArgs &a, int nsweeps, hip
             : launch_persistent_typed<float, 8>(c, a, nsweeps, s, ev0, ev1);
 }
 
-bool is_persistent(const gmrf_chain *c) { return c->g->h.stencil != 0 && c->lat_tile == kPersistent; }
+// Can the persistent one-block kernel sweep this general graph (its field in
+// LDS, its colors in the slab table)?
+bool csr_persist_fits(const HostGraph &h, gmrf_precision p)
+{
+    if (h.stencil != 0 || h.k > kCsrPersistColors ||
+        h.n * (int64_t)real_size(p) > (int64_t)kCsrLdsBytes)
+        return false;
+    int64_t slots = 0;
+    for (int32_t col = 0; col < h.k; ++col)
+        slots += (h.slab_offsets[col + 1] - h.slab_offsets[col] + kThreads - 1) / kThreads;
+    return slots <= kCsrPersistSlots;
+}
+
+// Default shape of a general-graph chain: the one block while it covers
+// every color's slab in at most two rounds of its threads (measured on
+// MI355X with Delaunay graphs: one block 15.2 against 24.3 us per sweep at
+// 500 sites, 29.4 against 35.4 at 4,000, slower from ~5,000 sites on, where
+// its serial rounds outlast the k + 1 launches), else the color passes.
+int csr_default_shape(const HostGraph &h, gmrf_precision p)
+{
+    if (!csr_persist_fits(h, p))
+        return 0;
+    for (int32_t col = 0; col < h.k; ++col)
+        if (h.slab_offsets[col + 1] - h.slab_offsets[col] > 2 * kCsrPersistThreads)
+            return 0;
+    return kPersistent;
+}
+
+// Do all the sweeps of a call run in one launch?  (Shape 2, except for the
+// binomial model, whose Polya-Gamma launches come between sweeps.)
+bool is_persistent(const gmrf_chain *c) { return c->lat_tile == kPersistent && !c->binomial; }
+
+// Does the chain draw the hyperparameters inside its sweep kernel (no finish
+// kernel)?
+bool draws_in_sweep(const gmrf_chain *c) { return c->lat_tile == kPersistent; }
 
 // Launch configuration of the small element-wise kernels.
 int elementwise_blocks(int64_t n)
@@ -1470,6 +1644,10 @@ void launch_csr(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent
         else
             hipLaunchKernelGGL(pg_psi_kernel<Real>, dim3(pb), dim3(kThreads), 0, s, ca, 0, nsite);
         ev0 = nullptr;
+        if (c->lat_tile == kPersistent) {       // the color passes and draws in one block
+            launch_csr_persistent<Real>(c, a, 1, s, ev0, ev1);
+            return;
+        }
     }
     for (int32_t col = 0; col < h.k; ++col) {
         const int nb = c->pass_blocks[col];
@@ -1516,7 +1694,8 @@ void launch_finish(const SweepArgs &a, hipStream_t s)
 void launch_one_sweep(const gmrf_chain *c, const SweepArgs &a, hipStream_t s)
 {
     launch_sweep_kernels(c, a, s);
-    launch_finish(a, s);
+    if (!draws_in_sweep(c))
+        launch_finish(a, s);
 }
 
 int read_state(gmrf_chain *c, DevState *out, hipStream_t s)
@@ -2009,7 +2188,7 @@ static int chain_create_impl(const char *who, const gmrf_graph *g, const gmrf_mo
     c->instance = instance;
     c->rank = rank;
     c->binomial = binomial;
-    c->lat_tile = is_lattice(g) ? default_tile(g->h) : 0;
+    c->lat_tile = is_lattice(g) ? default_tile(g->h) : csr_default_shape(g->h, p);
     chain_layout(g, p, static_cast<char *>(d_ws), c, binomial, n_chunks);
 
     auto cleanup = [&](int rc) {
@@ -2177,7 +2356,8 @@ int gmrf_sweep_timed(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t
         hipError_t he = hipSuccess;
         for (int i = 0; i < nsweeps && he == hipSuccess; ++i) {
             launch_sweep_kernels(c, a, stream, ev[2 * i], ev[2 * i + 1]);
-            launch_finish(a, stream);
+            if (!draws_in_sweep(c))
+                launch_finish(a, stream);
             he = hipGetLastError();
         }
         if (he == hipSuccess)
@@ -2407,10 +2587,10 @@ int gmrf_chain_get_tile(const gmrf_chain *c, int32_t *tile, int32_t *tile_rows, 
     if (!c)
         return fail(GMRF_E_INVALID_ARG, "chain_get_tile: NULL chain");
     if (!is_lattice(c->g)) {
-        if (tile) *tile = -1;
+        if (tile) *tile = c->lat_tile;
         if (tile_rows) *tile_rows = 0;
         if (tile_cols) *tile_cols = 0;
-        if (threads) *threads = kThreads;
+        if (threads) *threads = c->lat_tile == kPersistent ? kCsrPersistThreads : kThreads;
         return GMRF_OK;
     }
     const TileShape &t = kTiles[c->lat_tile];
@@ -2424,9 +2604,20 @@ int gmrf_chain_get_tile(const gmrf_chain *c, int32_t *tile, int32_t *tile_rows, 
 int gmrf_chain_set_tile(gmrf_chain *c, int32_t tile)
 {
     clear_error();
-    if (!c || !is_lattice(c->g) || tile < 0 || tile >= GMRF_NUM_TILES)
-        return fail(GMRF_E_INVALID_ARG, "chain_set_tile: NULL or general-graph chain, or tile "
-                                        "not in 0 .. GMRF_NUM_TILES - 1");
+    if (!c || tile < 0 || tile >= GMRF_NUM_TILES)
+        return fail(GMRF_E_INVALID_ARG, "chain_set_tile: NULL chain, or tile not in 0 .. "
+                                        "GMRF_NUM_TILES - 1");
+    if (!is_lattice(c->g)) {
+        if (tile == 1 || (tile == kPersistent && !csr_persist_fits(c->g->h, c->prec)))
+            return fail(GMRF_E_INVALID_ARG, "chain_set_tile: a general graph takes shape 0, or "
+                                            "shape 2 when its field fits in LDS (at most 122880 "
+                                            "bytes of state) and it has at most 32 colors");
+        if (tile != c->lat_tile) {
+            c->lat_tile = tile;
+            drop_graphs(c);
+        }
+        return GMRF_OK;
+    }
     if (!tile_fits(c->g->h, tile))
         return fail(GMRF_E_INVALID_ARG, "chain_set_tile: shape 2 needs a lattice of at most "
                                         "64 x 64 sites");

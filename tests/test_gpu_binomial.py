@@ -54,12 +54,14 @@ def pair(G, orc, wl, precision=None, seed=3, instance=0, burn_in=0, intercept=Tr
     return g, ch, oc
 
 
+@pytest.mark.parametrize("shape", [0, 2])
 @pytest.mark.parametrize("rho", [0.995, 1.0])
-def test_binomial_one_sweep_from_injected_state(G, orc, rho):
+def test_binomial_one_sweep_from_injected_state(G, orc, rho, shape):
     wl = case(G, rho=rho)
     n = wl["n"]
     x0 = np.random.default_rng(1).normal(size=n) * 0.4
     g, ch, oc = pair(G, orc, wl, seed=11, instance=4)
+    ch.set_tile(shape)
     ch.set_state(x0, 2.5, 1.0, 6)
     ch.set_intercept(0.2)
     oc.set_state(x0, 2.5, 1.0, 6, beta0=0.2)
@@ -73,9 +75,11 @@ def test_binomial_one_sweep_from_injected_state(G, orc, rho):
     assert rel(tau, oc.tau) <= RTOL64 and rel(ch.beta0, oc.beta0) <= RTOL64
 
 
-def test_binomial_trajectory_fp64(G, orc):
+@pytest.mark.parametrize("shape", [0, 2])
+def test_binomial_trajectory_fp64(G, orc, shape):
     wl = case(G, n=1500, median=60.0, seed=8)
     g, ch, oc = pair(G, orc, wl, burn_in=10)
+    ch.set_tile(shape)
     worst = 0.0
     for block in range(4):
         for _ in range(10):
@@ -91,9 +95,11 @@ def test_binomial_trajectory_fp64(G, orc):
     assert nacc == 30 and rel(m, om) <= RTOL64 and rel(v, ov) <= 1e-9
 
 
-def test_binomial_without_intercept_and_capture(G, orc):
+@pytest.mark.parametrize("shape", [0, 2])
+def test_binomial_without_intercept_and_capture(G, orc, shape):
     wl = case(G, n=800, median=20.0, seed=2)
     g, ch, oc = pair(G, orc, wl, intercept=False, seed=5)
+    ch.set_tile(shape)
     ch.sweep(12, capture=True)
     oc.sweeps(12)
     x, tau, _, _ = ch.get_state()
@@ -171,6 +177,25 @@ def test_binomial_extreme_trial_counts(G, orc, layout):
             assert spsi == 0.0 and oc.sse == 0.0
         else:
             assert rel(spsi, oc.sse) <= RTOL64
+
+
+def test_binomial_one_block_is_bitwise_color_passes(G, orc):
+    wl = case(G, n=2500, median=40.0, seed=14)
+    _, a, _ = pair(G, orc, wl, seed=4, burn_in=2)
+    _, b, _ = pair(G, orc, wl, seed=4, burn_in=2)
+    a.set_tile(0)
+    b.set_tile(2)
+    assert a.tile[0] == 0 and b.tile[0] == 2
+    a.sweep(6)
+    b.sweep(6)
+    a.sweep(4, capture=True)
+    b.sweep(4, capture=True)
+    sa, sb = a.get_state(), b.get_state()
+    assert np.array_equal(sa[0], sb[0]) and sa[1:] == sb[1:] and a.beta0 == b.beta0
+    assert a.last_reductions() == b.last_reductions()
+    ma, va, _ = a.posterior_stats()
+    mb, vb, _ = b.posterior_stats()
+    assert np.array_equal(ma, mb) and np.array_equal(va, vb)
 
 
 def test_binomial_argument_errors(G):

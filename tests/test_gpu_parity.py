@@ -86,12 +86,14 @@ def test_lattice_one_sweep_from_injected_state(G, orc, rows, cols, st, shape):
     assert rel(tau, oc.tau) <= RTOL64 and rel(lam, oc.lam) <= RTOL64
 
 
+@pytest.mark.parametrize("shape", [0, 2])
 @pytest.mark.parametrize("rho", [1.0, 0.95])
-def test_csr_one_sweep_from_injected_state(G, orc, rho):
+def test_csr_one_sweep_from_injected_state(G, orc, rho, shape):
     wl = csr_case(3000, data_seed=5, rho=rho)
     n = wl["n"]
     x0 = np.random.default_rng(1).normal(size=n)
     g, ch, oc = pair(G, orc, wl, seed=11, instance=4)
+    ch.set_tile(shape)
     ch.set_state(x0, 2.0, 25.0, 17)
     oc.set_state(x0, 2.0, 25.0, 17)
     ch.sweep(1)
@@ -127,9 +129,11 @@ def test_lattice_trajectory_64x64_fp64(G, orc):
     assert np.max(np.abs(var - ov)) <= 1e-9 * np.max(np.abs(ov))
 
 
-def test_csr_trajectory_delaunay_fp64(G, orc):
+@pytest.mark.parametrize("shape", [0, 2])
+def test_csr_trajectory_delaunay_fp64(G, orc, shape):
     wl = csr_case(15000, data_seed=3)
     g, ch, oc = pair(G, orc, wl, seed=3, burn_in=10)
+    ch.set_tile(shape)
     ch.sweep(50)
     oc.sweeps(50)
     x, tau, lam, sw = ch.get_state()
@@ -254,7 +258,8 @@ def test_device_pointer_stats(G, orc):
     assert np.array_equal(m.cpu().numpy(), mean) and np.array_equal(v.cpu().numpy(), var)
 
 
-def test_isolated_sites_and_empty_color(G, orc):
+@pytest.mark.parametrize("shape", [0, 2])
+def test_isolated_sites_and_empty_color(G, orc, shape):
     # 3 components (one isolated site) and a coloring that leaves color 2 empty
     rp, cl = inputs.edges_to_csr(6, [0, 1, 3], [1, 2, 4])
     color = np.array([0, 1, 0, 0, 1, 3], dtype=np.int32)
@@ -262,6 +267,7 @@ def test_isolated_sites_and_empty_color(G, orc):
     g = G.Graph(row_ptr=rp, col_idx=cl, color=color, num_colors=4)
     assert g.components == 3
     ch = G.Chain(g, y, seed=4)
+    ch.set_tile(shape)
     oc = orc.Chain(rp, cl, color, y, seed=4)
     ch.sweep(25)
     oc.sweeps(25)
@@ -322,15 +328,49 @@ def test_lattice_checkpoint_resume_and_burn_in(G, orc, prec):
         assert nf == 8 and rel(s1f, oc.s1) <= RTOL64 and rel(s2f, oc.s2) <= RTOL64
 
 
-@pytest.mark.parametrize("kind", ["lattice", "csr"])
+@pytest.mark.parametrize("kind", ["lattice", "csr", "csr_one_block"])
 def test_sweep_timed_equals_sweep(G, orc, kind):
     wl = lattice_case(100, 120, 8) if kind == "lattice" else csr_case(4000, data_seed=2)
     g = gpu_graph(G, wl)
     a = G.Chain(g, wl["y"], seed=4)
     b = G.Chain(g, wl["y"], seed=4)
+    if kind.startswith("csr"):
+        shape = 2 if kind == "csr_one_block" else 0
+        a.set_tile(shape)
+        b.set_tile(shape)
     a.sweep(6)
     ms, span = b.sweep_timed(6, span=True)
-    assert 0.0 < ms < span
+    if kind == "csr_one_block":     # one launch carries the sweeps and their draws
+        assert b.tile[0] == 2 and 0.0 < ms == span
+    else:
+        assert 0.0 < ms < span
     sa, sb = a.get_state(), b.get_state()
     assert np.array_equal(sa[0], sb[0]) and sa[1:] == sb[1:]
     assert b.sweep_timed(0, span=True) == (0.0, 0.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("capture", [False, True])
+def test_csr_one_block_is_bitwise_color_passes(G, orc, prec, capture):
+    """The one-block kernel (field in LDS) repeats the color-pass kernels'
+    operations in their order, FP64 partial sums and draws included: the
+    chains stay bitwise equal, with and without capture, across calls."""
+    precision = G.FP64 if prec == "fp64" else G.FP32_ACC64
+    wl = csr_case(5000, data_seed=8, rho=0.95)
+    g = gpu_graph(G, wl)
+    a = G.Chain(g, wl["y"], precision=precision, seed=6, burn_in=3)
+    b = G.Chain(g, wl["y"], precision=precision, seed=6, burn_in=3)
+    a.set_tile(0)
+    b.set_tile(2)
+    assert a.tile[0] == 0 and b.tile[0] == 2
+    for n in (1, 7, 12):
+        a.sweep(n, capture=capture)
+        b.sweep(n, capture=capture)
+    a.sweep(5, hyper=False)
+    b.sweep(5, hyper=False)
+    sa, sb = a.get_state(), b.get_state()
+    assert np.array_equal(sa[0], sb[0]) and sa[1:] == sb[1:]
+    assert a.last_reductions() == b.last_reductions()
+    ma, va, na = a.posterior_stats()
+    mb, vb, nb = b.posterior_stats()
+    assert na == nb == 22 and np.array_equal(ma, mb) and np.array_equal(va, vb)

@@ -1,4 +1,5 @@
-"""Lattice tile shapes and their autotuner (through the C ABI).
+"""Lattice tile shapes and their autotuner, and the two general-graph shapes
+(through the C ABI).
 
 Both shapes must reproduce the CPU oracle (FP64 within 1e-12 relative over
 many sweeps: the shapes differ only in how the FP64 reductions are grouped),
@@ -42,13 +43,28 @@ def test_default_shapes(G):
     color, k = G.greedy_coloring(wl["row_ptr"], wl["col"])
     csr = G.Chain(G.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color, num_colors=k,
                           rho=0.95), wl["y"])
-    assert csr.tile[0] == -1
+    assert csr.tile == (2, 0, 0, 512)          # the field fits in LDS: one block
+    csr.set_tile(0)
+    assert csr.tile == (0, 0, 0, 256)          # one launch per color
     with pytest.raises(G.GmrfError):
-        csr.set_tile(0)
+        csr.set_tile(1)
     with pytest.raises(G.GmrfError):
         small.set_tile(2)
     with pytest.raises(G.GmrfError):
         csr.autotune()
+    big_wl = inputs.delaunay_workload(20000, data_seed=3)
+    bcolor, bk = G.greedy_coloring(big_wl["row_ptr"], big_wl["col"])
+    bg = G.Graph(row_ptr=big_wl["row_ptr"], col_idx=big_wl["col"], color=bcolor, num_colors=bk,
+                 rho=0.95)
+    # 20,000 sites: color slabs beyond two rounds of the block, so the color
+    # passes by default; FP64 (160 KB) does not fit in LDS, FP32 (80 KB) does
+    c64 = G.Chain(bg, big_wl["y"])
+    c32 = G.Chain(bg, big_wl["y"], precision=G.FP32_ACC64)
+    assert c64.tile[0] == 0 and c32.tile[0] == 0
+    with pytest.raises(G.GmrfError):
+        c64.set_tile(2)
+    c32.set_tile(2)
+    assert c32.tile == (2, 0, 0, 512)
 
 
 @pytest.mark.parametrize("shape", [0, 1])
