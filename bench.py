@@ -179,11 +179,12 @@ def bench_batch(torch, gmrf, inputs, args):
             g = gmrf.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color, num_colors=k,
                            rho=wl["rho"])
         ch = gmrf.Chain(g, wl["y"], precision=gmrf.FP32_ACC64, seed=1 + i, instance=i)
-        if wl["kind"] == "lattice":
-            ch.set_tile(1)       # throughput: the 32x32 tile wastes least when the chip is full
         chains.append(ch)
         sites += wl["n"]
     batch = gmrf.Batch(chains)
+    tile, tile_us = batch.autotune(reps=10)     # the lattices' tile shape for the shared launch
+    log(f"[bench] batch autotune: shape {tile}, lattice pass {tile_us[0]:.1f} us (64x64) / "
+        f"{tile_us[1]:.1f} us (32x32)")
     batch.sweep(args.warmup, capture=False)
     batch.sweep(steps, capture=True)            # record the graph once
     torch.cuda.synchronize()
@@ -221,6 +222,8 @@ def bench_batch(torch, gmrf, inputs, args):
                    "sites_per_sweep": sites, "instances": len(chains)},
         "unbatched_site_updates_per_s": sites / t_solo,
         "batching_speedup": t_solo * steps / t_batch,
+        "lattice_tile_autotune": {"chosen_shape": tile, "us_per_pass_64x64": tile_us[0],
+                                  "us_per_pass_32x32": tile_us[1]},
     }
     print(json.dumps(line), flush=True)
 

@@ -332,9 +332,11 @@ int gmrf_chain_set_tile(gmrf_chain *c, int32_t tile);
 /* Autotune the tile shape of a lattice chain: time `reps` (1 .. 100000)
  * whole sweeps (draws included) of each shape that fits the lattice on the
  * chain itself and keep the fastest.  The timed sweeps run in a dry mode:
- * accumulation off, the draws computed but not stored, so only scratch (the
- * other state buffer and the partial slots) is written and the chain's state,
- * accumulators, trace and sweep count are unchanged.  us_per_sweep (NULL or
+ * the draws are computed but not stored, and an accumulating chain's
+ * accumulator updates go to its statistics scratch (the same memory traffic),
+ * so only scratch (the other state buffer, the partial slots, the statistics
+ * area) is written and the chain's state, accumulators, trace and sweep count
+ * are unchanged.  us_per_sweep (NULL or
  * GMRF_NUM_TILES doubles) receives the mean time per sweep of each shape in
  * microseconds (0 for a shape that does not fit), best the chosen shape.
  * Synchronises the stream. */
@@ -351,8 +353,10 @@ int gmrf_last_reductions(gmrf_chain *c, double *q, double *sse, hipStream_t stre
 typedef struct gmrf_batch gmrf_batch;
 
 /* Device workspace bytes of a batch over `count` chains (the job tables of
- * the shared launches).  Returns 0 and sets the error message if the chains
- * cannot form a batch. */
+ * the shared launches, sized for the chains' own tile shapes and for every
+ * lattice chain in either tile configuration, as gmrf_batch_autotune lays
+ * them out).  Returns 0 and sets the error message if the chains cannot form
+ * a batch. */
 size_t gmrf_batch_footprint(gmrf_chain *const *chains, int32_t count);
 
 /* Group `count` distinct chains of one precision, each on its own graph or
@@ -375,6 +379,20 @@ int gmrf_batch_destroy(gmrf_batch *b);
 /* nsweeps sweeps of every chain of the batch; flags as for gmrf_sweep
  * (GMRF_WITH_HYPER, GMRF_CAPTURE). */
 int gmrf_batch_sweep(gmrf_batch *b, int32_t nsweeps, uint32_t flags, hipStream_t stream);
+
+/* Choose the tile shape of the batch's lattice chains for the shared launch:
+ * time `reps` (1 .. 100000) passes over the tiles of every lattice chain of
+ * the batch with all of them in shape 0 (64 x 64 tiles) and then in shape 1
+ * (32 x 32), in the dry mode of gmrf_chain_autotune (only scratch written:
+ * the chains' state, accumulators and sweep counts are unchanged), and give every
+ * lattice chain the faster shape (as gmrf_chain_set_tile does, also for its
+ * own sweeps).  The batch's tables are then laid out again and its captured
+ * sweeps dropped.  General-graph chains are not timed or changed.
+ * us_per_sweep (NULL or 2 doubles) receives the mean time of one pass in
+ * microseconds per shape, best the chosen shape (-1 if the batch has no
+ * lattice chain).  Synchronises the stream. */
+int gmrf_batch_autotune(gmrf_batch *b, int32_t reps, hipStream_t stream, int32_t *best,
+                        double *us_per_sweep);
 
 #ifdef __cplusplus
 }

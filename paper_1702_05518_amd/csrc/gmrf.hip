@@ -1283,6 +1283,7 @@ struct gmrf_batch {
     CsrBlock *csr_blocks[2] = {};
     std::vector<int> csr_color_off[2];            // per color index: first block
     SweepArgs *fin_args = nullptr;
+    char *ws = nullptr;                           // the caller's workspace (job tables)
     hipStream_t capture_stream = nullptr;
     std::map<std::pair<int, unsigned>, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_defs;
@@ -1416,6 +1417,18 @@ size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chai
     return off;
 }
 
+// Arguments of a timing run (dry): the draws are computed but not stored,
+// and the accumulator updates go to the chain's statistics scratch (2n
+// doubles) instead of S1 / S2, with the memory traffic of real ones, so that
+// the chain's state and accumulators stay as they are.
+SweepArgs dry_args(SweepArgs a, const gmrf_chain *c)
+{
+    a.dry = 1;
+    a.s1 = c->d_stats;
+    a.s2 = c->d_stats + c->g->h.n;
+    return a;
+}
+
 SweepArgs make_args(const gmrf_chain *c, unsigned flags)
 {
     SweepArgs a{};
@@ -1444,16 +1457,18 @@ SweepArgs make_args(const gmrf_chain *c, unsigned flags)
     return a;
 }
 
-template <typename Real> LatArgs<Real> lattice_args(const gmrf_chain *c)
+template <typename Real> LatArgs<Real> lattice_args(const gmrf_chain *c, int shape = -1)
 {
     const HostGraph &h = c->g->h;
+    if (shape < 0)
+        shape = c->lat_tile;
     LatArgs<Real> la;
     la.x0 = static_cast<Real *>(c->d_x[0]);
     la.x1 = static_cast<Real *>(c->d_x[1]);
     la.y = static_cast<const Real *>(c->d_y);
     la.rows = h.rows;
     la.cols = h.cols;
-    la.tiles_c = (h.cols + kTiles[c->lat_tile].tw - 1) / kTiles[c->lat_tile].tw;
+    la.tiles_c = (h.cols + kTiles[shape].tw - 1) / kTiles[shape].tw;
     return la;
 }
 
@@ -1824,8 +1839,12 @@ template <typename T> size_t append(std::vector<char> &img, const std::vector<T>
     return at;
 }
 
+// Job tables of a batch.  force >= 0 lays every lattice chain out in tile
+// configuration `force` instead of its own shape, and dry makes the lattice
+// jobs timing runs (dry_args), for the batch autotuner.
 template <typename Real>
-void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im)
+void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im, int force = -1,
+                       bool dry = false)
 {
     std::vector<LatJob<Real>> ljobs[8];
     std::vector<LatTile> ltiles[8];
@@ -1838,10 +1857,13 @@ void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im)
         const HostGraph &h = c->g->h;
         const int g = c->model.intercept ? 1 : 0;
         if (is_lattice(c->g)) {
-            const int w = (h.stencil == 8 ? 1 : 0) + 2 * g + 4 * tile_cfg(c->lat_tile);
+            const int cfg = force >= 0 ? force : tile_cfg(c->lat_tile);
+            const int w = (h.stencil == 8 ? 1 : 0) + 2 * g + 4 * cfg;
             const int job = (int)ljobs[w].size();
-            ljobs[w].push_back(LatJob<Real>{lattice_args<Real>(c), a});
-            for (int t = 0; t < c->total_slots; ++t)
+            const SweepArgs la_args = dry ? dry_args(a, c) : a;
+            ljobs[w].push_back(LatJob<Real>{lattice_args<Real>(c, cfg), la_args});
+            const int tiles = lattice_blocks(h, cfg);
+            for (int t = 0; t < tiles; ++t)
                 ltiles[w].push_back(LatTile{job, t});
         } else {
             const int job = (int)cjobs[g].size();
@@ -1899,16 +1921,55 @@ int check_batch_chains(gmrf_chain *const *chains, int32_t count, gmrf_precision 
     return GMRF_OK;
 }
 
-int build_image(gmrf_chain *const *chains, int32_t count, BatchImage &im, gmrf_precision *prec)
+int build_image(gmrf_chain *const *chains, int32_t count, BatchImage &im, gmrf_precision *prec,
+                int force = -1, bool dry = false)
 {
     const int rc = check_batch_chains(chains, count, prec);
     if (rc != GMRF_OK)
         return rc;
     const std::vector<gmrf_chain *> cs(chains, chains + count);
     if (*prec == GMRF_FP64)
-        build_batch_image<double>(cs, im);
+        build_batch_image<double>(cs, im, force, dry);
     else
-        build_batch_image<float>(cs, im);
+        build_batch_image<float>(cs, im, force, dry);
+    return GMRF_OK;
+}
+
+// Workspace of a batch: the largest of its tables with the chains' own
+// shapes and with every lattice chain in either tile configuration (the
+// autotuner lays the tables out again in the same workspace).
+int batch_bytes(gmrf_chain *const *chains, int32_t count, size_t *bytes)
+{
+    size_t most = 0;
+    for (int force = -1; force <= 1; ++force) {
+        BatchImage im;
+        gmrf_precision prec;
+        const int rc = build_image(chains, count, im, &prec, force);
+        if (rc != GMRF_OK)
+            return rc;
+        most = std::max(most, align_up(im.bytes.size()));
+    }
+    *bytes = most;
+    return GMRF_OK;
+}
+
+// Point the batch at the tables of image im, uploaded into its workspace.
+int install_image(gmrf_batch *b, const BatchImage &im, hipStream_t stream)
+{
+    GMRF_HIP(hipMemcpyAsync(b->ws, im.bytes.data(), im.bytes.size(), hipMemcpyHostToDevice,
+                            stream));
+    GMRF_HIP(hipStreamSynchronize(stream));
+    for (int w = 0; w < 8; ++w) {
+        b->lat_jobs[w] = b->ws + im.off_lat_jobs[w];
+        b->lat_tiles[w] = reinterpret_cast<LatTile *>(b->ws + im.off_lat_tiles[w]);
+        b->lat_tile_count[w] = im.lat_tile_count[w];
+    }
+    for (int g = 0; g < 2; ++g) {
+        b->csr_jobs[g] = b->ws + im.off_csr_jobs[g];
+        b->csr_blocks[g] = reinterpret_cast<CsrBlock *>(b->ws + im.off_csr_blocks[g]);
+        b->csr_color_off[g] = im.csr_color_off[g];
+    }
+    b->fin_args = reinterpret_cast<SweepArgs *>(b->ws + im.off_fin);
     return GMRF_OK;
 }
 
@@ -1935,7 +1996,7 @@ template <typename Real, bool B0> void launch_csr_group(const gmrf_batch *b, siz
                            b->csr_blocks[g] + b->csr_color_off[g][col]);
 }
 
-template <typename Real> void launch_batch_sweep_kernels(const gmrf_batch *b, hipStream_t s)
+template <typename Real> void launch_batch_lattice_kernels(const gmrf_batch *b, hipStream_t s)
 {
     launch_lattice_group<Real, 4, false, 0>(b, s);
     launch_lattice_group<Real, 8, false, 0>(b, s);
@@ -1945,6 +2006,11 @@ template <typename Real> void launch_batch_sweep_kernels(const gmrf_batch *b, hi
     launch_lattice_group<Real, 8, false, 1>(b, s);
     launch_lattice_group<Real, 4, true, 1>(b, s);
     launch_lattice_group<Real, 8, true, 1>(b, s);
+}
+
+template <typename Real> void launch_batch_sweep_kernels(const gmrf_batch *b, hipStream_t s)
+{
+    launch_batch_lattice_kernels<Real>(b, s);
     // color c of every general-graph chain before color c + 1 of any
     const size_t ncol = std::max(b->csr_color_off[0].size(), b->csr_color_off[1].size());
     for (size_t col = 0; col + 1 < ncol; ++col) {
@@ -2649,14 +2715,11 @@ int gmrf_chain_autotune(gmrf_chain *c, int32_t reps, hipStream_t stream, int32_t
         c->lat_tile = k;
         c->total_slots = lattice_blocks(c->g->h, k);
         // Whole sweeps (sweep kernels and the finish, or the persistent
-        // kernel) in dry mode: accumulation off, draws computed but nothing
-        // stored, so the sweep kernels write only the other state buffer and
-        // the partial slots (scratch until the next sweep) and the chain is
-        // unchanged; the persistent kernel runs an odd number of sweeps so
-        // that it too ends in the other state buffer.
-        SweepArgs a = make_args(c, GMRF_WITH_HYPER);
-        a.burn_in = (long long)(~0ull >> 1);
-        a.dry = 1;
+        // kernel) in dry mode (dry_args), so the sweep kernels write only the
+        // other state buffer, the partial slots and the statistics scratch
+        // and the chain is unchanged; the persistent kernel runs an odd
+        // number of sweeps so that it too ends in the other state buffer.
+        const SweepArgs a = dry_args(make_args(c, GMRF_WITH_HYPER), c);
         const int odd = reps | 1;
         if (k == kPersistent) {
             launch_persistent(c, a, 1, stream);
@@ -2715,11 +2778,10 @@ int gmrf_last_reductions(gmrf_chain *c, double *q, double *sse, hipStream_t stre
 size_t gmrf_batch_footprint(gmrf_chain *const *chains, int32_t count)
 {
     clear_error();
-    BatchImage im;
-    gmrf_precision prec;
-    if (build_image(chains, count, im, &prec) != GMRF_OK)
+    size_t bytes = 0;
+    if (batch_bytes(chains, count, &bytes) != GMRF_OK)
         return 0;
-    return align_up(im.bytes.size());
+    return bytes;
 }
 
 int gmrf_batch_create(gmrf_chain *const *chains, int32_t count, void *d_ws, size_t ws_bytes,
@@ -2734,30 +2796,113 @@ int gmrf_batch_create(gmrf_chain *const *chains, int32_t count, void *d_ws, size
     int rc = build_image(chains, count, im, &prec);
     if (rc != GMRF_OK)
         return rc;
-    const size_t need = align_up(im.bytes.size());
+    size_t need = 0;
+    rc = batch_bytes(chains, count, &need);
+    if (rc != GMRF_OK)
+        return rc;
     if (!d_ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0)
         return fail(GMRF_E_WORKSPACE, "batch_create: workspace NULL, misaligned or smaller than "
                                       "gmrf_batch_footprint (" +
                                           std::to_string(need) + " bytes)");
-    char *base = static_cast<char *>(d_ws);
-    GMRF_HIP(hipMemcpyAsync(base, im.bytes.data(), im.bytes.size(), hipMemcpyHostToDevice, stream));
-    GMRF_HIP(hipStreamSynchronize(stream));
     gmrf_batch *b = new gmrf_batch();
     b->chains.assign(chains, chains + count);
     b->prec = prec;
-    for (int w = 0; w < 8; ++w) {
-        b->lat_jobs[w] = base + im.off_lat_jobs[w];
-        b->lat_tiles[w] = reinterpret_cast<LatTile *>(base + im.off_lat_tiles[w]);
-        b->lat_tile_count[w] = im.lat_tile_count[w];
+    b->ws = static_cast<char *>(d_ws);
+    rc = install_image(b, im, stream);
+    if (rc != GMRF_OK) {
+        delete b;
+        return rc;
     }
-    for (int g = 0; g < 2; ++g) {
-        b->csr_jobs[g] = base + im.off_csr_jobs[g];
-        b->csr_blocks[g] = reinterpret_cast<CsrBlock *>(base + im.off_csr_blocks[g]);
-        b->csr_color_off[g] = im.csr_color_off[g];
-    }
-    b->fin_args = reinterpret_cast<SweepArgs *>(base + im.off_fin);
     *out = b;
     return GMRF_OK;
+}
+
+int gmrf_batch_autotune(gmrf_batch *b, int32_t reps, hipStream_t stream, int32_t *best,
+                        double *us_per_sweep)
+{
+    clear_error();
+    if (!b || reps < 1 || reps > 100000)
+        return fail(GMRF_E_INVALID_ARG, "batch_autotune: NULL batch or reps not in 1 .. 100000");
+    if (best)
+        *best = -1;
+    if (us_per_sweep)
+        us_per_sweep[0] = us_per_sweep[1] = 0.0;
+    std::vector<gmrf_chain *> lat;
+    for (gmrf_chain *c : b->chains)
+        if (is_lattice(c->g))
+            lat.push_back(c);
+    if (lat.empty())
+        return GMRF_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    GMRF_HIP(hipEventCreate(&e0));
+    const hipError_t ce = hipEventCreate(&e1);
+    if (ce != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(GMRF_E_DEVICE, std::string("batch_autotune: ") + hipGetErrorString(ce));
+    }
+    double us[2] = {0.0, 0.0};
+    int rc = GMRF_OK;
+    for (int k = 0; k < 2 && rc == GMRF_OK; ++k) {
+        BatchImage im;
+        gmrf_precision prec;
+        rc = build_image(b->chains.data(), (int32_t)b->chains.size(), im, &prec, k, true);
+        if (rc == GMRF_OK)
+            rc = install_image(b, im, stream);
+        if (rc != GMRF_OK)
+            break;
+        // one untimed pass, then reps timed passes of the lattice tiles
+        hipError_t he = hipSuccess;
+        for (int r = 0; r <= reps && he == hipSuccess; ++r) {
+            if (r == 1)
+                he = hipEventRecord(e0, stream);
+            if (he == hipSuccess) {
+                b->prec == GMRF_FP64 ? launch_batch_lattice_kernels<double>(b, stream)
+                                     : launch_batch_lattice_kernels<float>(b, stream);
+                he = hipGetLastError();
+            }
+        }
+        if (he == hipSuccess)
+            he = hipEventRecord(e1, stream);
+        if (he == hipSuccess)
+            he = hipStreamSynchronize(stream);
+        float ms = 0.0f;
+        if (he == hipSuccess)
+            he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess)
+            rc = fail(GMRF_E_DEVICE, std::string("batch_autotune: ") + hipGetErrorString(he));
+        us[k] = 1e3 * (double)ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == GMRF_OK) {
+        const int k = us[1] < us[0] ? 1 : 0;
+        for (gmrf_chain *c : lat) {
+            if (c->lat_tile != k) {
+                c->lat_tile = k;
+                c->total_slots = lattice_blocks(c->g->h, k);
+                drop_graphs(c);
+            }
+        }
+        if (best)
+            *best = k;
+        if (us_per_sweep) {
+            us_per_sweep[0] = us[0];
+            us_per_sweep[1] = us[1];
+        }
+    }
+    // the batch's own tables again (with the chosen shapes), and no stale graphs
+    BatchImage im;
+    gmrf_precision prec;
+    int rc2 = build_image(b->chains.data(), (int32_t)b->chains.size(), im, &prec);
+    if (rc2 == GMRF_OK)
+        rc2 = install_image(b, im, stream);
+    for (auto &kv : b->graphs)
+        (void)hipGraphExecDestroy(kv.second);
+    for (hipGraph_t gdef : b->graph_defs)
+        (void)hipGraphDestroy(gdef);
+    b->graphs.clear();
+    b->graph_defs.clear();
+    return rc != GMRF_OK ? rc : rc2;
 }
 
 int gmrf_batch_destroy(gmrf_batch *b)

@@ -100,6 +100,8 @@ _SIGS = {
                            C.POINTER(C.c_void_p)], C.c_int),
     "gmrf_batch_destroy": ([C.c_void_p], C.c_int),
     "gmrf_batch_sweep": ([C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p], C.c_int),
+    "gmrf_batch_autotune": ([C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int32),
+                             C.POINTER(C.c_double)], C.c_int),
 }
 
 
@@ -436,3 +438,13 @@ class Batch:
         flags = (WITH_HYPER if hyper else 0) | (CAPTURE if capture else 0)
         _check(lib().gmrf_batch_sweep(self.handle, int(nsweeps), flags, _stream_handle(stream)))
         return self
+
+    def autotune(self, reps: int = 10, stream=None):
+        """Time the batch's lattice tiles in shapes 0 and 1 (chain state
+        unchanged) and keep the faster; returns (best shape or -1, [us per
+        pass of each shape])."""
+        best = C.c_int32()
+        us = (C.c_double * 2)()
+        _check(lib().gmrf_batch_autotune(self.handle, int(reps), _stream_handle(stream),
+                                         C.byref(best), us))
+        return best.value, list(us)

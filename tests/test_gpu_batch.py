@@ -135,3 +135,40 @@ def test_full_512_instance_mix(G, orc):
         x, tau, lam, _ = chains[i].get_state()
         assert np.max(np.abs(x - oc.x)) <= 1e-12 * np.max(np.abs(oc.x))
         assert abs(tau / oc.tau - 1) <= 1e-12 and abs(lam / oc.lam - 1) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_autotune_keeps_state_and_equality(G, prec):
+    """gmrf_batch_autotune times the lattice tiles in both shapes without
+    touching the chains' state, gives every lattice chain the faster shape,
+    and the re-laid-out batch still ends where standalone sweeps end."""
+    p = G.FP32_ACC64 if prec == "fp32" else G.FP64
+    wls = workloads(G)
+    chains = make_chains(G, wls, p, 300)
+    twins = make_chains(G, wls, p, 300)
+    batch = G.Batch(chains)
+    batch.sweep(3, capture=True)
+    for t in twins:
+        t.sweep(3)
+    before = [(c.get_state(), c.posterior_stats()) for c in chains]
+    best, us = batch.autotune(reps=3)
+    assert best in (0, 1) and us[0] > 0.0 and us[1] > 0.0
+    assert best == (1 if us[1] < us[0] else 0)
+    for c, (st, ps) in zip(chains, before):
+        st2, ps2 = c.get_state(), c.posterior_stats()
+        assert np.array_equal(st[0], st2[0]) and st[1:] == st2[1:]
+        # one accumulated sweep so far: the variance is NaN (N - 1 = 0) on both sides
+        assert np.array_equal(ps[0], ps2[0]) and ps[2] == ps2[2] == 1
+        assert np.array_equal(ps[1], ps2[1], equal_nan=True)
+    for c, t, (g, _) in zip(chains, twins, wls):
+        if g.lattice is not None:
+            assert c.tile[0] == best
+            t.set_tile(best)
+    batch.sweep(4, capture=True)
+    batch.sweep(2)
+    for t in twins:
+        t.sweep(6)
+    for c, t in zip(chains, twins):
+        assert same(c, t)
+    only_csr = G.Batch(make_chains(G, wls[5:], p, 900))
+    assert only_csr.autotune(reps=1) == (-1, [0.0, 0.0])
