@@ -102,6 +102,21 @@ def test_bad_arguments():
     assert gmrf.validate_graph(n=15, lattice=(4, 4, 4)) == gmrf.E_INVALID_ARG
 
 
+def test_null_handles_are_rejected_without_a_device():
+    """Entry points refuse NULL handles and out-of-range counts before any
+    device work."""
+    import ctypes as C
+    L = gmrf.lib()
+    best, us = C.c_int32(), (C.c_double * 2)()
+    assert L.gmrf_batch_autotune(None, 5, None, C.byref(best), us) == gmrf.E_INVALID_ARG
+    assert L.gmrf_chain_autotune(None, 5, None, C.byref(best), None) == gmrf.E_INVALID_ARG
+    assert L.gmrf_chain_set_tile(None, 0) == gmrf.E_INVALID_ARG
+    assert L.gmrf_sweep(None, 1, 0, None) == gmrf.E_INVALID_ARG
+    assert L.gmrf_batch_sweep(None, 1, 0, None) == gmrf.E_INVALID_ARG
+    assert L.gmrf_batch_footprint(None, 0) == 0
+    assert b"batch" in L.gmrf_last_error()
+
+
 def test_lattice_descriptions():
     for st in (4, 8):
         assert gmrf.validate_graph(lattice=(7, 5, st)) == gmrf.OK
