@@ -5,7 +5,8 @@
 //
 //   * Lattice graphs (4- and 8-neighbour stencils, parity colorings): ONE
 //     kernel per sweep.  Each workgroup owns a TH x TW tile of the lattice,
-//     stages the tile plus a halo of depth k (the number of colors) in LDS,
+//     stages the tile plus the halo its phases read (k rings, k the number
+//     of colors; for 8 neighbours one ring fewer before the tile) in LDS,
 //     and runs the k color phases in LDS.  Phase j updates the sites of color
 //     j on the tile grown by k-1-j rings, so the values that later phases read
 //     at the tile border are recomputed locally instead of being exchanged:
@@ -328,13 +329,21 @@ template <typename Real> struct SiteCtx {
 };
 
 // Tile geometry of the fused lattice kernel: TH x TW interior sites, NT
-// threads, halo of depth k (= number of colors); the accumulator
-// read-modify-write of the interior is issued CH sites per thread at a time.
+// threads, the halo (see below); the accumulator read-modify-write of the
+// interior is issued CH sites per thread at a time.
 template <int ST_, int TH_, int TW_, int NT_, int CH_> struct LatCfg {
     static constexpr int ST = ST_, TH = TH_, TW = TW_, NT = NT_, CH = CH_;
     static constexpr int K = ST == 4 ? 2 : 4;
-    static constexpr int H = K;
-    static constexpr int LH = TH + 2 * H, LW = TW + 2 * H;
+    // Halo rings.  With the tile at an even (r0, c0), phase J computes the
+    // color-J sites of the tile grown by K - 1 - J rings and reads one ring
+    // further.  8 neighbours: phase 0's sites (even rows and columns) reach
+    // ring 2 before the tile and ring 3 after it (rows r0 - 2 and
+    // r0 + TH + 2, likewise for columns), so the phases read 3 rings before
+    // and 4 after; 4 neighbours: 2 and 2.  H (rings before, the LDS offset of
+    // the tile) and HH (rings after):
+    static constexpr int H = ST == 8 ? K - 1 : K;
+    static constexpr int HH = K;
+    static constexpr int LH = TH + H + HH, LW = TW + H + HH;
     static_assert(TH % 2 == 0 && TW % 2 == 0, "tile sides must be even");
     static_assert(NT % 64 == 0, "whole wavefronts");
 };
@@ -559,7 +568,8 @@ __device__ __forceinline__ void lattice_sweep_block(const LatArgs<Real> &la, con
     lds_barrier();
 
     Red rd;
-    const bool interior = r0 >= H && c0 >= H && r0 + TH + H <= rows && c0 + TW + H <= cols;
+    const bool interior = r0 >= H && c0 >= H && r0 + TH + Cfg::HH <= rows &&
+                          c0 + TW + Cfg::HH <= cols;
     if (interior)
         lattice_phases<Real, Cfg, true, B0>(xs, la.y, r0, c0, rows, cols, sc, rd);
     else
