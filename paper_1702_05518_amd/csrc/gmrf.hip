@@ -1086,14 +1086,7 @@ __global__ __launch_bounds__(kCsrPersistThreads) void csr_persistent_kernel(CsrA
 // Each color pass then runs one thread per site: x_p ~ N(m, 1/Q) with
 // Q = tau D_pp + psi_p, m = (kappa_p - psi_p beta0 + tau rho sum_{j~p} x_j) / Q.
 constexpr int kPsiSites = kThreads / 64;        // sites per block of the psi kernel
-#ifndef GMRF_PG_CHUNK
-#define GMRF_PG_CHUNK 2
-#endif
-constexpr int kPgChunk = GMRF_PG_CHUNK;         // PG(1, .) terms per chunk
-#ifndef GMRF_PG_ENV_PREPASS
-#define GMRF_PG_ENV_PREPASS 1
-#endif
-constexpr bool kPgEnvPrepass = GMRF_PG_ENV_PREPASS;
+constexpr int kPgChunk = 2;                     // PG(1, .) terms per chunk
 
 // The PG envelope of sites lo .. lo + cnt - 1 (tilt beta0 + x_p), so that
 // the term kernel's threads need not each evaluate its erfc and exp.  Run
@@ -1126,9 +1119,8 @@ __global__ __launch_bounds__(kThreads) void pg_chunk_kernel(CsrArgs<Real> ca, Sw
         const int j0 = (q - ca.chunk_off[p]) * kPgChunk;
         const int j1 = min(j0 + kPgChunk, m);
         const unsigned t = (unsigned)a.st->sweep;
-        const double b0 = B0 ? a.st->beta0 : 0.0;
         const unsigned id = (unsigned)ca.orig[p];
-        const PgEnvelope env = kPgEnvPrepass ? ca.env[p] : pg_envelope(b0 + (double)ca.x[p]);
+        const PgEnvelope env = ca.env[p];      // drawn with beta0 by pg_env_kernel<Real, B0>
         bool ok = true;
         for (int j = j0; j < j1; ++j) {
             double v = 0.0;
@@ -1647,7 +1639,7 @@ void launch_csr(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent
         auto tk = c->model.intercept ? pg_chunk_kernel<Real, true> : pg_chunk_kernel<Real, false>;
         const int eb = (nsite + kThreads - 1) / kThreads, tb = (nq + kThreads - 1) / kThreads;
         const int pb = (nsite + kPsiSites - 1) / kPsiSites;
-        if (nq > 0 && kPgEnvPrepass) {
+        if (nq > 0) {
             if (ev0)
                 hipExtLaunchKernelGGL(ek, dim3(eb), dim3(kThreads), 0, s, ev0, nullptr, 0, ca, a,
                                       0, nsite);
