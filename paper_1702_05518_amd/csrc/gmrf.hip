@@ -2708,7 +2708,7 @@ int gmrf_chain_autotune(gmrf_chain *c, int32_t reps, hipStream_t stream, int32_t
     hipEvent_t e0 = nullptr, e1 = nullptr;
     GMRF_HIP(hipEventCreate(&e0));
     hipError_t he = hipEventCreate(&e1);
-    double t[GMRF_NUM_TILES];
+    double t[GMRF_NUM_TILES] = {};
     int win = keep;
     for (int k = 0; k < GMRF_NUM_TILES && he == hipSuccess; ++k) {
         t[k] = 0.0;
