@@ -780,11 +780,30 @@ template <typename Real> struct CsrArgs {
     double *psi;                // binomial: each site's psi for the current sweep
 };
 
-// One site per thread.  The first kCsrBatch neighbours are gathered in one
-// batch (all column indices, then all values) and kept in registers for the
-// q terms; longer rows continue in a plain loop.  The summation order is the
-// row order, i.e. ascending original neighbour id.
-constexpr int kCsrBatch = 8;
+// One site per thread.  Neighbours are gathered in batches of NB (all column
+// indices of a batch, then all values), so a row costs two dependent loads
+// per batch rather than per neighbour; the first batch stays in registers for
+// the q terms.  The summation order is the row order, i.e. ascending
+// original neighbour id, whatever NB.  A wide batch suits launches bound by
+// load latency (one chain's color pass: most Delaunay rows, up to 12 entries,
+// in one round); a narrow one suits the batched launch, which is bound by
+// load throughput and pays for the clamped repeats of short rows.
+constexpr int kCsrBatch = 12;          // per-chain kernels
+constexpr int kCsrBatchShared = 8;     // the batched color pass
+
+// Row entries eb .. eb + NB - 1, each clamped to the row's last entry e1 - 1:
+// their column indices and the neighbour values.
+template <int NB, typename Real>
+__device__ __forceinline__ void csr_gather(const int *col, const Real *x, int eb, int e1,
+                                           int (&j)[NB], Real (&v)[NB])
+{
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+        j[k] = col[min(eb + k, e1 - 1)];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+        v[k] = x[j[k]];
+}
 
 // Scalars of the chain state that a color pass reads.
 struct CsrScalars {
@@ -812,7 +831,7 @@ __device__ __forceinline__ CsrScalars csr_scalars(const SweepArgs &a, bool b0)
 // psi_p drawn beforehand): Qii = tau D_ii + psi_p,
 // m = (kappa_p - psi_p beta0 + tau rho s_i) / Qii, and the sse / rsum slots
 // take psi_p and kappa_p - psi_p x_p.
-template <typename Real, bool B0, bool BIN>
+template <typename Real, bool B0, bool BIN, int NB = kCsrBatch>
 __device__ __forceinline__ void csr_site(const CsrArgs<Real> &ca, const SweepArgs &a, Real *x,
                                          const int p, const int lo, const CsrScalars &v, Red &rd)
 {
@@ -827,21 +846,23 @@ __device__ __forceinline__ void csr_site(const CsrArgs<Real> &ca, const SweepArg
         o1 = a.s1[p];
         o2 = a.s2[p];
     }
-    int cj[kCsrBatch];
-    Real nb[kCsrBatch];
-#pragma unroll
-    for (int k = 0; k < kCsrBatch; ++k)
-        cj[k] = ca.col[min(e0 + k, max(e1 - 1, 0))];   // clamped; used only if k < deg
-#pragma unroll
-    for (int k = 0; k < kCsrBatch; ++k)
-        nb[k] = x[cj[k]];
+    int cj[NB];
+    Real nb[NB];
+    csr_gather<NB>(ca.col, x, e0, max(e1, 1), cj, nb);   // clamped; entry k used only if k < deg
     Real s = (Real)0;
 #pragma unroll
-    for (int k = 0; k < kCsrBatch; ++k)
+    for (int k = 0; k < NB; ++k)
         if (k < deg)
             s += nb[k];
-    for (int e = e0 + kCsrBatch; e < e1; ++e)
-        s += x[ca.col[e]];
+    for (int eb = e0 + NB; eb < e1; eb += NB) {
+        int tj[NB];
+        Real tv[NB];
+        csr_gather<NB>(ca.col, x, eb, e1, tj, tv);
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+            if (eb + k < e1)
+                s += tv[k];
+    }
     const Real z = site_normal<Real>(draw_words(a.seed, id, v.t, a.instance, 0u));
     Real xn;
     if constexpr (BIN) {
@@ -867,17 +888,21 @@ __device__ __forceinline__ void csr_site(const CsrArgs<Real> &ca, const SweepArg
     const double xd = (double)xn;
     double edge = 0.0;
 #pragma unroll
-    for (int k = 0; k < kCsrBatch; ++k)
+    for (int k = 0; k < NB; ++k)
         if (k < deg && cj[k] < lo) {   // lower color: already final this sweep
             const double d = xd - (double)nb[k];
             edge += d * d;
         }
-    for (int e = e0 + kCsrBatch; e < e1; ++e) {
-        const int j = ca.col[e];
-        if (j < lo) {
-            const double d = xd - (double)x[j];
-            edge += d * d;
-        }
+    for (int eb = e0 + NB; eb < e1; eb += NB) {
+        int tj[NB];
+        Real tv[NB];
+        csr_gather<NB>(ca.col, x, eb, e1, tj, tv);
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+            if (eb + k < e1 && tj[k] < lo) {
+                const double d = xd - (double)tv[k];
+                edge += d * d;
+            }
     }
     rd.q += (1.0 - a.rho) * (double)deg * xd * xd + a.rho * edge;
     if constexpr (BIN) {
@@ -898,7 +923,7 @@ __device__ __forceinline__ void csr_site(const CsrArgs<Real> &ca, const SweepArg
 }
 
 // Sites p0 + threadIdx.x of the color slab [lo, lo + cnt); partial slot `slot`.
-template <typename Real, bool B0, bool BIN>
+template <typename Real, bool B0, bool BIN, int NB = kCsrBatch>
 __device__ __forceinline__ void csr_pass_block(const CsrArgs<Real> &ca, const SweepArgs &a,
                                                const int lo, const int cnt, const int p0,
                                                const int slot)
@@ -907,7 +932,7 @@ __device__ __forceinline__ void csr_pass_block(const CsrArgs<Real> &ca, const Sw
     const int p = p0 + (int)threadIdx.x;
     Red rd;
     if (p < lo + cnt)
-        csr_site<Real, B0, BIN>(ca, a, ca.x, p, lo, v, rd);
+        csr_site<Real, B0, BIN, NB>(ca, a, ca.x, p, lo, v, rd);
     write_partials<kThreads>(a, rd, slot);
 }
 
@@ -935,7 +960,7 @@ __global__ __launch_bounds__(kThreads) void csr_batch_kernel(const CsrJob<Real> 
 {
     const CsrBlock bk = blocks[blockIdx.x];
     const CsrJob<Real> &j = jobs[bk.job];
-    csr_pass_block<Real, B0, false>(j.ca, j.a, bk.lo, bk.cnt, bk.p0, bk.slot);
+    csr_pass_block<Real, B0, false, kCsrBatchShared>(j.ca, j.a, bk.lo, bk.cnt, bk.p0, bk.slot);
 }
 
 // ---------------------------------------------------------------------------
@@ -2092,13 +2117,16 @@ int gmrf_graph_create(const gmrf_graph_desc *d, void *d_ws, size_t ws_bytes, hip
         g->d_row_ptr = reinterpret_cast<int *>(b);
         b += align_up(sizeof(int) * (size_t)(g->h.n + 1));
         g->d_col = reinterpret_cast<int *>(b);
-        b += align_up(sizeof(int) * (size_t)g->h.nnz);
+        b += align_up(sizeof(int) * (size_t)std::max<int64_t>(g->h.nnz, 1));
         g->d_orig = reinterpret_cast<int *>(b);
+        static const int kNoNeighbour = 0;   // the column entry of a graph without edges
         hipError_t e = hipMemcpyAsync(g->d_row_ptr, g->h.row_ptr.data(),
                                       sizeof(int) * (g->h.n + 1), hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess && g->h.nnz > 0)
-            e = hipMemcpyAsync(g->d_col, g->h.col.data(), sizeof(int) * g->h.nnz,
-                               hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = g->h.nnz > 0 ? hipMemcpyAsync(g->d_col, g->h.col.data(), sizeof(int) * g->h.nnz,
+                                              hipMemcpyHostToDevice, stream)
+                             : hipMemcpyAsync(g->d_col, &kNoNeighbour, sizeof(int),
+                                              hipMemcpyHostToDevice, stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(g->d_orig, g->h.orig_of_slab.data(), sizeof(int) * g->h.n,
                                hipMemcpyHostToDevice, stream);

@@ -132,7 +132,10 @@ size_t graph_device_bytes(int64_t n, int64_t nnz, bool lattice)
 {
     if (lattice)
         return 0;
-    return align_up(sizeof(int32_t) * (size_t)(n + 1)) + align_up(sizeof(int32_t) * (size_t)nnz) +
+    // at least one column entry: a site without neighbours still loads entry 0
+    // (clamped gathers), which must hold a valid site index
+    return align_up(sizeof(int32_t) * (size_t)(n + 1)) +
+           align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1)) +
            align_up(sizeof(int32_t) * (size_t)n);
 }
 

@@ -97,3 +97,27 @@ def test_hub_graph_binomial_sweeps(G, orc, name, shape):
         assert rel(x, oc.x) <= RTOL64
         assert rel(q, oc.q) <= RTOL64 and rel(spsi, oc.sse) <= RTOL64
         assert rel(tau, oc.tau) <= RTOL64 and rel(ch.beta0, oc.beta0) <= RTOL64
+
+
+@pytest.mark.parametrize("shape", [0, 2])
+@pytest.mark.parametrize("rho", [1.0, 0.95])
+def test_graph_without_edges(G, orc, rho, shape):
+    """Every site isolated (no column entries at all): x_i ~ N(y_i, 1 / lam)
+    each sweep, q = 0, tau drawn from its prior."""
+    n = 700
+    rp = np.zeros(n + 1, dtype=np.int64)
+    cl = np.zeros(0, dtype=np.int32)
+    color = np.zeros(n, dtype=np.int32)
+    y = np.cos(np.arange(n) * 0.21)
+    g = G.Graph(row_ptr=rp, col_idx=cl, color=color, num_colors=1, rho=rho)
+    assert g.components == n
+    ch = G.Chain(g, y, seed=5)
+    ch.set_tile(shape)
+    oc = orc.Chain(rp, cl, color, y, rho=rho, seed=5)
+    ch.sweep(10)
+    oc.sweeps(10)
+    x, tau, lam, _ = ch.get_state()
+    q, sse = ch.last_reductions()
+    assert q == 0.0 and oc.q == 0.0
+    assert rel(x, oc.x) <= RTOL64 and rel(sse, oc.sse) <= RTOL64
+    assert rel(tau, oc.tau) <= RTOL64 and rel(lam, oc.lam) <= RTOL64
