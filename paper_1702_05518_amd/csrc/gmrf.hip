@@ -780,14 +780,16 @@ template <typename Real> struct CsrArgs {
     double *psi;                // binomial: each site's psi for the current sweep
 };
 
-// One site per thread.  Neighbours are gathered in batches of NB (all column
-// indices of a batch, then all values), so a row costs two dependent loads
-// per batch rather than per neighbour; the first batch stays in registers for
-// the q terms.  The summation order is the row order, i.e. ascending
-// original neighbour id, whatever NB.  A wide batch suits launches bound by
-// load latency (one chain's color pass: most Delaunay rows, up to 12 entries,
-// in one round); a narrow one suits the batched launch, which is bound by
-// load throughput and pays for the clamped repeats of short rows.
+// One site per thread.  The first NB neighbours are gathered in one batch
+// (all column indices, then all values) and stay in registers for the q
+// terms.  With WIDE, longer rows continue in batches of NB, so a row costs
+// two dependent loads per batch rather than per neighbour; otherwise one
+// entry at a time.  The summation order is the row order, i.e. ascending
+// original neighbour id, in every variant.  Wide batches suit launches bound
+// by load latency (one chain's color pass: most Delaunay rows, up to 12
+// entries, in one round); the batched launch is bound by load throughput and
+// pays for the clamped repeats of short rows, so it gathers 8 and continues
+// entry by entry.
 constexpr int kCsrBatch = 12;          // per-chain kernels
 constexpr int kCsrBatchShared = 8;     // the batched color pass
 
@@ -831,7 +833,7 @@ __device__ __forceinline__ CsrScalars csr_scalars(const SweepArgs &a, bool b0)
 // psi_p drawn beforehand): Qii = tau D_ii + psi_p,
 // m = (kappa_p - psi_p beta0 + tau rho s_i) / Qii, and the sse / rsum slots
 // take psi_p and kappa_p - psi_p x_p.
-template <typename Real, bool B0, bool BIN, int NB = kCsrBatch>
+template <typename Real, bool B0, bool BIN, int NB = kCsrBatch, bool WIDE = true>
 __device__ __forceinline__ void csr_site(const CsrArgs<Real> &ca, const SweepArgs &a, Real *x,
                                          const int p, const int lo, const CsrScalars &v, Red &rd)
 {
@@ -854,14 +856,19 @@ __device__ __forceinline__ void csr_site(const CsrArgs<Real> &ca, const SweepArg
     for (int k = 0; k < NB; ++k)
         if (k < deg)
             s += nb[k];
-    for (int eb = e0 + NB; eb < e1; eb += NB) {
-        int tj[NB];
-        Real tv[NB];
-        csr_gather<NB>(ca.col, x, eb, e1, tj, tv);
+    if constexpr (WIDE) {
+        for (int eb = e0 + NB; eb < e1; eb += NB) {
+            int tj[NB];
+            Real tv[NB];
+            csr_gather<NB>(ca.col, x, eb, e1, tj, tv);
 #pragma unroll
-        for (int k = 0; k < NB; ++k)
-            if (eb + k < e1)
-                s += tv[k];
+            for (int k = 0; k < NB; ++k)
+                if (eb + k < e1)
+                    s += tv[k];
+        }
+    } else {
+        for (int e = e0 + NB; e < e1; ++e)
+            s += x[ca.col[e]];
     }
     const Real z = site_normal<Real>(draw_words(a.seed, id, v.t, a.instance, 0u));
     Real xn;
@@ -893,16 +900,26 @@ __device__ __forceinline__ void csr_site(const CsrArgs<Real> &ca, const SweepArg
             const double d = xd - (double)nb[k];
             edge += d * d;
         }
-    for (int eb = e0 + NB; eb < e1; eb += NB) {
-        int tj[NB];
-        Real tv[NB];
-        csr_gather<NB>(ca.col, x, eb, e1, tj, tv);
+    if constexpr (WIDE) {
+        for (int eb = e0 + NB; eb < e1; eb += NB) {
+            int tj[NB];
+            Real tv[NB];
+            csr_gather<NB>(ca.col, x, eb, e1, tj, tv);
 #pragma unroll
-        for (int k = 0; k < NB; ++k)
-            if (eb + k < e1 && tj[k] < lo) {
-                const double d = xd - (double)tv[k];
+            for (int k = 0; k < NB; ++k)
+                if (eb + k < e1 && tj[k] < lo) {
+                    const double d = xd - (double)tv[k];
+                    edge += d * d;
+                }
+        }
+    } else {
+        for (int e = e0 + NB; e < e1; ++e) {
+            const int j = ca.col[e];
+            if (j < lo) {
+                const double d = xd - (double)x[j];
                 edge += d * d;
             }
+        }
     }
     rd.q += (1.0 - a.rho) * (double)deg * xd * xd + a.rho * edge;
     if constexpr (BIN) {
@@ -923,7 +940,7 @@ __device__ __forceinline__ void csr_site(const CsrArgs<Real> &ca, const SweepArg
 }
 
 // Sites p0 + threadIdx.x of the color slab [lo, lo + cnt); partial slot `slot`.
-template <typename Real, bool B0, bool BIN, int NB = kCsrBatch>
+template <typename Real, bool B0, bool BIN, int NB = kCsrBatch, bool WIDE = true>
 __device__ __forceinline__ void csr_pass_block(const CsrArgs<Real> &ca, const SweepArgs &a,
                                                const int lo, const int cnt, const int p0,
                                                const int slot)
@@ -932,7 +949,7 @@ __device__ __forceinline__ void csr_pass_block(const CsrArgs<Real> &ca, const Sw
     const int p = p0 + (int)threadIdx.x;
     Red rd;
     if (p < lo + cnt)
-        csr_site<Real, B0, BIN, NB>(ca, a, ca.x, p, lo, v, rd);
+        csr_site<Real, B0, BIN, NB, WIDE>(ca, a, ca.x, p, lo, v, rd);
     write_partials<kThreads>(a, rd, slot);
 }
 
@@ -960,7 +977,8 @@ __global__ __launch_bounds__(kThreads) void csr_batch_kernel(const CsrJob<Real> 
 {
     const CsrBlock bk = blocks[blockIdx.x];
     const CsrJob<Real> &j = jobs[bk.job];
-    csr_pass_block<Real, B0, false, kCsrBatchShared>(j.ca, j.a, bk.lo, bk.cnt, bk.p0, bk.slot);
+    csr_pass_block<Real, B0, false, kCsrBatchShared, false>(j.ca, j.a, bk.lo, bk.cnt, bk.p0,
+                                                         bk.slot);
 }
 
 // ---------------------------------------------------------------------------
