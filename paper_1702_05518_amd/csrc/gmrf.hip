@@ -156,41 +156,62 @@ struct HyperIn {
     double tau, lam, beta0;
 };
 
+// The random parts of the draws after sweep t, which do not depend on the
+// sweep's reductions: the beta0 normal (tag-3 normal at counter (0, t)) and,
+// in lane 0 for tau (tag 1) and lane 1 for lam (tag 2), the Marsaglia-Tsang
+// variate d v of the conditional's shape at rate 1.  Its accept / reject
+// decisions involve only the shape, and the draw at rate b is (d v) / b, the
+// division gamma_draw ends with, so drawing the unit variate early changes
+// no bit of the result.
+struct UnitDraws {
+    double z, g;
+    bool ok;
+};
+
+__device__ __forceinline__ UnitDraws unit_draws(const SweepArgs &a, unsigned t, int lane)
+{
+    UnitDraws u{0.0, 0.0, false};
+    if (a.with_hyper && a.intercept)
+        u.z = normal_f64(draw_words(a.seed, 0u, t, a.instance, 3u));
+    if (a.with_hyper && lane < (a.likelihood ? 1 : 2))    // no noise precision if binomial
+        u.ok = gamma_draw(lane == 0 ? a.g_tau : a.g_lam, 1.0, a.seed, t, a.instance,
+                          (unsigned)(lane + 1), &u.g);
+    return u;
+}
+
 // The draws after sweep t (Sec. 3.1 conjugate conditionals, precisions in
-// rate form), in lanes 0 and 1 of one wavefront; `r` holds the reductions of
-// sweep t, `in` the state the sweep ran with.  With an intercept, first
+// rate form), in lanes 0 and 1 of one wavefront, from the lane's unit
+// variates `u`; `r` holds the reductions of sweep t, `in` the state the
+// sweep ran with.  With an intercept, first
 //     beta0 ~ N(mean(y - x), 1 / (n lam))      (flat prior on beta0)
-// from the tag-3 normal at counter (0, t); both lanes draw it, and sse and
-// rsum move to the new beta0:  with d = beta0' - beta0,
+// and sse and rsum move to the new beta0:  with d = beta0' - beta0,
 //     sum (r_i - d)^2 = sse - 2 d rsum + n d^2,   sum (r_i - d) = rsum - n d.
 // Then tau (lane 0) and lam (lane 1).  Lane 0 stores the reductions and
 // beta0; the trace row t, if any, gets (tau, lam, beta0) after the draws.
 __device__ __forceinline__ HyperIn end_of_sweep_draws(const SweepArgs &a, unsigned t, Red r,
-                                                      const HyperIn &in, int lane)
+                                                      const HyperIn &in, int lane,
+                                                      const UnitDraws &u)
 {
     double b0 = in.beta0;
     if (a.with_hyper && a.intercept) {
-        const double z = normal_f64(draw_words(a.seed, 0u, t, a.instance, 3u));
         if (a.likelihood) {
             // binomial (Sec. 3.2 augmented model): beta0 | x, psi ~
             // N(sum(kappa - psi x) / P, 1 / P), P = sum psi + prior precision
             const double P = r.sse + a.b0_prec;
-            b0 = r.rsum / P + z / sqrt(P);
+            b0 = r.rsum / P + u.z / sqrt(P);
         } else {
             const double mean = in.beta0 + r.rsum / a.n_sites;
-            b0 = mean + z / sqrt(a.n_sites * in.lam);
+            b0 = mean + u.z / sqrt(a.n_sites * in.lam);
             const double d = b0 - in.beta0;
             r.sse = r.sse - 2.0 * d * r.rsum + a.n_sites * d * d;
             r.rsum = r.rsum - a.n_sites * d;
         }
     }
     double v = lane == 0 ? in.tau : in.lam;
-    if (a.with_hyper && lane < (a.likelihood ? 1 : 2)) {   // no noise precision if binomial
-        const GammaShape g = lane == 0 ? a.g_tau : a.g_lam;
+    if (a.with_hyper && lane < (a.likelihood ? 1 : 2)) {
         const double rate = lane == 0 ? a.b_tau + 0.5 * r.q : a.b_lam + 0.5 * r.sse;
-        double draw = 0.0;
-        const bool ok = gamma_draw(g, rate, a.seed, t, a.instance, (unsigned)(lane + 1), &draw);
-        if (ok && isfinite(draw) && draw > 0.0 && isfinite(b0)) {
+        const double draw = u.ok ? u.g / rate : 0.0;
+        if (u.ok && isfinite(draw) && draw > 0.0 && isfinite(b0)) {
             v = draw;
             if (!a.dry) {
                 if (lane == 0)
@@ -218,29 +239,60 @@ __device__ __forceinline__ HyperIn end_of_sweep_draws(const SweepArgs &a, unsign
     return HyperIn{v, other, b0};    // valid in lane 0
 }
 
+// The same with the unit variates drawn in place.
+__device__ __forceinline__ HyperIn end_of_sweep_draws(const SweepArgs &a, unsigned t, Red r,
+                                                      const HyperIn &in, int lane)
+{
+    return end_of_sweep_draws(a, t, r, in, lane, unit_draws(a, t, lane));
+}
+
 // End of a sweep (one block): sum the partials of every block of the sweep
 // in slot order, store q / sse, draw tau / lam, count the accumulated sweep
-// and advance the sweep index.
+// and advance the sweep index.  kFinishThreads threads sum the partials
+// (thread i takes slots i, i + kFinishThreads, ..., then a fixed tree); one
+// more wavefront draws the unit variates meanwhile, so that only the
+// divisions by the rates wait for the sums.
 constexpr int kFinishThreads = 256;
+constexpr int kFinishBlock = kFinishThreads + 64;
 
 __device__ __forceinline__ void finish_sweep_block(const SweepArgs &a)
 {
-    __shared__ double red[kPartials * (kFinishThreads / 64)];
+    constexpr int W = kFinishThreads / 64;
+    __shared__ double red[kPartials * W];
+    __shared__ UnitDraws units[2];
     const unsigned t = (unsigned)a.st->sweep;
     const HyperIn in{a.st->tau, a.st->lam, a.st->beta0};
-    Red r;
-    for (int i = threadIdx.x; i < a.total_slots; i += kFinishThreads) {
-        r.q += a.partials[kPartials * i];
-        r.sse += a.partials[kPartials * i + 1];
-        r.rsum += a.partials[kPartials * i + 2];
+    const int lane = (int)threadIdx.x & 63, wid = (int)threadIdx.x >> 6;
+    if (wid < W) {
+        Red r;
+        for (int i = threadIdx.x; i < a.total_slots; i += kFinishThreads) {
+            r.q += a.partials[kPartials * i];
+            r.sse += a.partials[kPartials * i + 1];
+            r.rsum += a.partials[kPartials * i + 2];
+        }
+        r.q = wave_sum(r.q);
+        r.sse = wave_sum(r.sse);
+        r.rsum = wave_sum(r.rsum);
+        if (lane == 0) {
+            red[wid] = r.q;
+            red[W + wid] = r.sse;
+            red[2 * W + wid] = r.rsum;
+        }
+    } else if (lane < 2) {
+        units[lane] = unit_draws(a, t, lane);
     }
-    block_sum3<kFinishThreads>(r.q, r.sse, r.rsum, red);
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
-        r.q = __shfl(r.q, 0, 64);
-        r.sse = __shfl(r.sse, 0, 64);
-        r.rsum = __shfl(r.rsum, 0, 64);
-        end_of_sweep_draws(a, t, r, in, lane);
+    lds_barrier();
+    if (wid == 0) {
+        Red r;
+        r.q = red[0];
+        r.sse = red[W];
+        r.rsum = red[2 * W];
+        for (int w = 1; w < W; ++w) {
+            r.q += red[w];
+            r.sse += red[W + w];
+            r.rsum += red[2 * W + w];
+        }
+        end_of_sweep_draws(a, t, r, in, lane, units[lane < 2 ? lane : 0]);
         if (lane == 0 && !a.dry) {
             if ((long long)t >= a.burn_in)
                 a.st->n_acc += 1;
@@ -249,13 +301,13 @@ __device__ __forceinline__ void finish_sweep_block(const SweepArgs &a)
     }
 }
 
-__global__ __launch_bounds__(kFinishThreads) void finish_sweep_kernel(SweepArgs a)
+__global__ __launch_bounds__(kFinishBlock) void finish_sweep_kernel(SweepArgs a)
 {
     finish_sweep_block(a);
 }
 
 // Batched finish: block b ends the sweep of chain b.
-__global__ __launch_bounds__(kFinishThreads) void finish_batch_kernel(const SweepArgs *args,
+__global__ __launch_bounds__(kFinishBlock) void finish_batch_kernel(const SweepArgs *args,
                                                                      int with_hyper)
 {
     SweepArgs a = args[blockIdx.x];
@@ -1748,7 +1800,7 @@ void launch_sweep_kernels(const gmrf_chain *c, const SweepArgs &a, hipStream_t s
 
 void launch_finish(const SweepArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(finish_sweep_kernel, dim3(1), dim3(kFinishThreads), 0, s, a);
+    hipLaunchKernelGGL(finish_sweep_kernel, dim3(1), dim3(kFinishBlock), 0, s, a);
 }
 
 void launch_one_sweep(const gmrf_chain *c, const SweepArgs &a, hipStream_t s)
@@ -2071,7 +2123,7 @@ void launch_batch_sweep(const gmrf_batch *b, unsigned flags, hipStream_t s)
     else
         launch_batch_sweep_kernels<float>(b, s);
     hipLaunchKernelGGL(finish_batch_kernel, dim3((unsigned)b->chains.size()),
-                       dim3(kFinishThreads), 0, s, b->fin_args,
+                       dim3(kFinishBlock), 0, s, b->fin_args,
                        (flags & GMRF_WITH_HYPER) ? 1 : 0);
 }
 
