@@ -246,6 +246,23 @@ __device__ __forceinline__ HyperIn end_of_sweep_draws(const SweepArgs &a, unsign
     return end_of_sweep_draws(a, t, r, in, lane, unit_draws(a, t, lane));
 }
 
+// The persistent kernels draw the unit variates of kUnitBatch sweeps at a
+// time, one thread per (sweep, lane), ahead of the sweeps: they depend only on
+// the sweep index, so no sweep then waits for a Gamma draw.
+constexpr int kUnitBatch = 128;
+
+// Unit variates of sweeps t .. t + cnt - 1 (cnt <= kUnitBatch) into
+// ub[sweep - t][lane]; the caller synchronises before reading them.
+template <int NT>
+__device__ __forceinline__ void unit_draw_batch(const SweepArgs &a, unsigned t, int cnt,
+                                                UnitDraws (*ub)[2])
+{
+    static_assert(NT >= 2 * kUnitBatch, "one thread per sweep and lane");
+    const int i = (int)threadIdx.x;
+    if (i < 2 * cnt)
+        ub[i >> 1][i & 1] = unit_draws(a, t + (unsigned)(i >> 1), i & 1);
+}
+
 // End of a sweep (one block): sum the partials of every block of the sweep
 // in slot order, store q / sse, draw tau / lam, count the accumulated sweep
 // and advance the sweep index.  kFinishThreads threads sum the partials
@@ -690,6 +707,7 @@ __global__ __launch_bounds__(Cfg::NT) void lattice_persistent_kernel(LatArgs<Rea
     __shared__ Real xs[LH * LW];
     __shared__ double red[kPartials * (NT / 64)];
     __shared__ double hyp[3];
+    __shared__ UnitDraws ub[kUnitBatch][2];
     const int rows = la.rows, cols = la.cols;
     const int lane = (int)threadIdx.x & 63;
     unsigned t = (unsigned)a.st->sweep;
@@ -728,6 +746,10 @@ __global__ __launch_bounds__(Cfg::NT) void lattice_persistent_kernel(LatArgs<Rea
     bool accumulated = false;
     lds_barrier();
     for (int s = 0; s < nsweeps; ++s) {
+        if (s % kUnitBatch == 0) {
+            unit_draw_batch<NT>(a, t, min(kUnitBatch, nsweeps - s), ub);
+            lds_barrier();
+        }
         SiteCtx<Real> sc;
         sc.tau = (Real)tau;
         sc.lam = (Real)lam;
@@ -762,7 +784,8 @@ __global__ __launch_bounds__(Cfg::NT) void lattice_persistent_kernel(LatArgs<Rea
             rd.q = __shfl(rd.q, 0, 64);
             rd.sse = __shfl(rd.sse, 0, 64);
             rd.rsum = __shfl(rd.rsum, 0, 64);
-            const HyperIn out = end_of_sweep_draws(a, t, rd, HyperIn{tau, lam, b0}, lane);
+            const HyperIn out = end_of_sweep_draws(a, t, rd, HyperIn{tau, lam, b0}, lane,
+                                                   ub[s % kUnitBatch][lane < 2 ? lane : 0]);
             if (lane == 0) {
                 hyp[0] = out.tau;
                 hyp[1] = out.lam;
@@ -1068,6 +1091,7 @@ __global__ __launch_bounds__(kCsrPersistThreads) void csr_persistent_kernel(CsrA
     __shared__ double wpart[kCsrPersistSlots * GW * kPartials];   // wavefront sums of a group
     __shared__ double red[kPartials * GW];
     __shared__ double hyp[3];
+    __shared__ UnitDraws ub[kUnitBatch][2];
     const int n = sl.off[sl.k];
     const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
     for (int p = (int)threadIdx.x; p < n; p += NT)
@@ -1076,6 +1100,10 @@ __global__ __launch_bounds__(kCsrPersistThreads) void csr_persistent_kernel(CsrA
     long long nacc = a.st->n_acc;
     lds_barrier();
     for (int s = 0; s < nsweeps; ++s) {
+        if (s % kUnitBatch == 0) {
+            unit_draw_batch<NT>(a, v.t, min(kUnitBatch, nsweeps - s), ub);
+            lds_barrier();
+        }
         int slot0 = 0;
         for (int c = 0; c < sl.k; ++c) {
             const int lo = sl.off[c], hi = sl.off[c + 1];
@@ -1136,7 +1164,7 @@ __global__ __launch_bounds__(kCsrPersistThreads) void csr_persistent_kernel(CsrA
                 r.rsum += red[2 * GW + w];
             }
             const HyperIn out = end_of_sweep_draws(a, v.t, r, HyperIn{v.tau, v.lam, v.beta0},
-                                                   lane);
+                                                   lane, ub[s % kUnitBatch][lane < 2 ? lane : 0]);
             if (lane == 0) {
                 hyp[0] = out.tau;
                 hyp[1] = out.lam;
