@@ -1028,12 +1028,16 @@ __device__ __forceinline__ void csr_pass_block(const CsrArgs<Real> &ca, const Sw
     write_partials<kThreads>(a, rd, slot);
 }
 
+// Block b takes chunk xcd_tile(b) of the slab (kThreads sites each), so each
+// XCD sweeps a contiguous eighth of the slab; the breadth-first slab order
+// keeps that eighth's neighbours in nearby stretches of the other slabs,
+// inside the XCD's own L2.  A chunk's partial slot is slot_base + chunk.
 template <typename Real, bool B0>
 __global__ __launch_bounds__(kThreads) void csr_pass_kernel(CsrArgs<Real> ca, SweepArgs a, int lo,
                                                             int cnt, int slot_base)
 {
-    csr_pass_block<Real, B0, false>(ca, a, lo, cnt, lo + (int)blockIdx.x * kThreads,
-                             slot_base + (int)blockIdx.x);
+    const int chunk = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    csr_pass_block<Real, B0, false>(ca, a, lo, cnt, lo + chunk * kThreads, slot_base + chunk);
 }
 
 // Batched color pass: one entry per block over the color-c slabs of every
@@ -1050,7 +1054,7 @@ template <typename Real, bool B0>
 __global__ __launch_bounds__(kThreads) void csr_batch_kernel(const CsrJob<Real> *jobs,
                                                              const CsrBlock *blocks)
 {
-    const CsrBlock bk = blocks[blockIdx.x];
+    const CsrBlock bk = blocks[xcd_tile((int)blockIdx.x, (int)gridDim.x)];   // chains per XCD
     const CsrJob<Real> &j = jobs[bk.job];
     csr_pass_block<Real, B0, false, kCsrBatchShared, false>(j.ca, j.a, bk.lo, bk.cnt, bk.p0,
                                                          bk.slot);
@@ -1298,8 +1302,8 @@ template <typename Real, bool B0>
 __global__ __launch_bounds__(kThreads) void csr_binomial_pass_kernel(CsrArgs<Real> ca, SweepArgs a,
                                                                      int lo, int cnt, int slot_base)
 {
-    csr_pass_block<Real, B0, true>(ca, a, lo, cnt, lo + (int)blockIdx.x * kThreads,
-                                   slot_base + (int)blockIdx.x);
+    const int chunk = xcd_tile((int)blockIdx.x, (int)gridDim.x);   // as csr_pass_kernel
+    csr_pass_block<Real, B0, true>(ca, a, lo, cnt, lo + chunk * kThreads, slot_base + chunk);
 }
 
 // ---------------------------------------------------------------------------
