@@ -35,6 +35,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <unordered_set>
 #include <utility>
 #include <vector>
 
@@ -2031,12 +2032,13 @@ int check_batch_chains(gmrf_chain *const *chains, int32_t count, gmrf_precision 
 {
     if (!chains || count < 1)
         return fail(GMRF_E_INVALID_ARG, "batch: need at least one chain");
-    std::vector<const gmrf_chain *> seen;
+    std::unordered_set<const gmrf_chain *> seen;
+    seen.reserve((size_t)count);
     for (int32_t i = 0; i < count; ++i) {
         const gmrf_chain *c = chains[i];
         if (!c)
             return fail(GMRF_E_INVALID_ARG, "batch: NULL chain at index " + std::to_string(i));
-        if (std::find(seen.begin(), seen.end(), c) != seen.end())
+        if (!seen.insert(c).second)
             return fail(GMRF_E_INVALID_ARG, "batch: chain at index " + std::to_string(i) +
                                                 " appears twice");
         if (c->prec != chains[0]->prec)
@@ -2044,7 +2046,6 @@ int check_batch_chains(gmrf_chain *const *chains, int32_t count, gmrf_precision 
         if (c->binomial)
             return fail(GMRF_E_INVALID_ARG, "batch: binomial chains are swept on their own "
                                             "(chain at index " + std::to_string(i) + ")");
-        seen.push_back(c);
     }
     *prec = chains[0]->prec;
     return GMRF_OK;
@@ -2066,11 +2067,17 @@ int build_image(gmrf_chain *const *chains, int32_t count, BatchImage &im, gmrf_p
 
 // Workspace of a batch: the largest of its tables with the chains' own
 // shapes and with every lattice chain in either tile configuration (the
-// autotuner lays the tables out again in the same workspace).
-int batch_bytes(gmrf_chain *const *chains, int32_t count, size_t *bytes)
+// autotuner lays the tables out again in the same workspace).  `own`, if
+// given, is the image with the chains' own shapes, already built; without
+// lattice chains the three layouts are one.
+int batch_bytes(gmrf_chain *const *chains, int32_t count, size_t *bytes,
+                const BatchImage *own = nullptr)
 {
-    size_t most = 0;
-    for (int force = -1; force <= 1; ++force) {
+    size_t most = own ? align_up(own->bytes.size()) : 0;
+    bool lattices = false;
+    for (int32_t i = 0; chains && i < count && !lattices; ++i)
+        lattices = chains[i] && is_lattice(chains[i]->g);
+    for (int force = own ? 0 : -1; force <= (lattices ? 1 : -1); ++force) {
         BatchImage im;
         gmrf_precision prec;
         const int rc = build_image(chains, count, im, &prec, force);
@@ -2929,7 +2936,7 @@ int gmrf_batch_create(gmrf_chain *const *chains, int32_t count, void *d_ws, size
     if (rc != GMRF_OK)
         return rc;
     size_t need = 0;
-    rc = batch_bytes(chains, count, &need);
+    rc = batch_bytes(chains, count, &need, &im);
     if (rc != GMRF_OK)
         return rc;
     if (!d_ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0)
