@@ -172,3 +172,39 @@ def test_batch_autotune_keeps_state_and_equality(G, prec):
         assert same(c, t)
     only_csr = G.Batch(make_chains(G, wls[5:], p, 900))
     assert only_csr.autotune(reps=1) == (-1, [0.0, 0.0])
+
+
+@pytest.mark.parametrize("kinds", ["lattice", "csr", "mixed"])
+def test_batch_workspace_is_the_footprint(G, kinds):
+    """gmrf_batch_create accepts a workspace of exactly gmrf_batch_footprint
+    bytes and refuses one byte less (lattice-only, general-only and mixed
+    batches: the sizing builds the forced tile layouts only with lattices),
+    and the autotuner's re-laid-out tables fit the same workspace."""
+    import ctypes as C
+
+    import torch
+
+    wls = workloads(G)
+    pick = {"lattice": wls[:5], "csr": wls[5:], "mixed": wls}[kinds]
+    chains = make_chains(G, pick, G.FP32_ACC64, 7)
+    L = G.lib()
+    arr = (C.c_void_p * len(chains))(*[c.handle.value for c in chains])
+    need = L.gmrf_batch_footprint(arr, len(chains))
+    assert need > 0
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    h = C.c_void_p()
+    assert L.gmrf_batch_create(arr, len(chains), C.c_void_p(ws.data_ptr()), need - 1, None,
+                               C.byref(h)) == G.E_WORKSPACE
+    assert L.gmrf_batch_create(arr, len(chains), C.c_void_p(ws.data_ptr()), need, None,
+                               C.byref(h)) == G.OK
+    best, us = C.c_int32(), (C.c_double * 2)()
+    assert L.gmrf_batch_autotune(h, 2, None, C.byref(best), us) == G.OK
+    assert (best.value == -1) == (kinds == "csr")
+    assert L.gmrf_batch_sweep(h, 4, G.WITH_HYPER, None) == G.OK   # 2 past the burn-in
+    torch.cuda.synchronize()
+    assert L.gmrf_batch_destroy(h) == G.OK
+    solo = make_chains(G, pick, G.FP32_ACC64, 7)
+    for a, b in zip(solo, chains):
+        a.set_tile(b.tile[0])          # the shape the autotuner gave the batched chain
+        a.sweep(4)
+        assert same(a, b)
