@@ -189,3 +189,46 @@ def test_persistent_shape_rules_and_autotune(G):
     a.sweep(6)
     G.Batch([b]).sweep(6)
     assert np.array_equal(a.get_state()[0], b.get_state()[0])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", ["lattice8_b0", "lattice4", "csr"])
+def test_one_block_long_call_is_bitwise(G, orc, kind, prec):
+    """One call of 300 sweeps in a one-block kernel (shape 2), which draws
+    the rate-free parts of the hyperparameter draws 128 sweeps at a time
+    ahead of the sweeps (so the call refills them twice, the last time for
+    44 sweeps), ends bitwise where 300 separate sweeps of the multi-launch
+    shape end; FP64 also against the oracle."""
+    p = G.FP64 if prec == "fp64" else G.FP32_ACC64
+    if kind == "csr":
+        wl = inputs.delaunay_workload(2000, data_seed=9, rho=0.95)
+        wl["color"], wl["k"] = G.greedy_coloring(wl["row_ptr"], wl["col"])
+        g = G.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=wl["color"],
+                    num_colors=wl["k"], rho=0.95)
+        kw = {}
+    else:
+        st = 8 if kind == "lattice8_b0" else 4
+        side = 50 if st == 8 else 64
+        wl = inputs.lattice_workload(side, side, st)
+        g = G.Graph(lattice=(side, side, st))
+        kw = {"intercept": True} if st == 8 else {}
+    a = G.Chain(g, wl["y"], precision=p, seed=12, burn_in=40, **kw)
+    b = G.Chain(g, wl["y"], precision=p, seed=12, burn_in=40, **kw)
+    a.set_tile(2)
+    b.set_tile(0)
+    a.sweep(300)
+    for _ in range(300):
+        b.sweep(1)
+    sa, sb = a.get_state(), b.get_state()
+    assert sa[3] == sb[3] == 300
+    assert np.array_equal(sa[0], sb[0]) and sa[1:] == sb[1:]
+    ma, va, na = a.posterior_stats()
+    mb, vb, nb = b.posterior_stats()
+    assert na == nb == 260 and np.array_equal(ma, mb) and np.array_equal(va, vb)
+    if p == G.FP64:
+        rho = 0.95 if kind == "csr" else 1.0
+        oc = orc.Chain(wl["row_ptr"], wl["col"], wl["color"], wl["y"], rho=rho, seed=12,
+                       burn_in=40, **kw)
+        oc.sweeps(300)
+        x, tau, lam, _ = a.get_state()
+        assert rel(x, oc.x) <= RTOL64 and rel(tau, oc.tau) <= RTOL64 and rel(lam, oc.lam) <= RTOL64
