@@ -42,14 +42,16 @@ def jobs_for(serve, graphs, prec):
     return out
 
 
+@pytest.mark.parametrize("overlap", [False, True])
 @pytest.mark.parametrize("prec_name", ["fp32", "fp64"])
-def test_served_results_equal_standalone(S, prec_name):
+def test_served_results_equal_standalone(S, prec_name, overlap):
     gmrf, serve = S
     prec = gmrf.FP32_ACC64 if prec_name == "fp32" else gmrf.FP64
     graphs = pool(gmrf)
     jobs = jobs_for(serve, graphs, prec)
     one = serve.chain_bytes(graphs[0][0], prec)
-    server = serve.Server(budget_bytes=3 * one + 1, step_sweeps=10, max_active=3)
+    server = serve.Server(budget_bytes=3 * one + 1, step_sweeps=10, max_active=3,
+                          overlap=overlap)
     server.run(jobs, realtime=False)
     assert len(server.finished) == len(jobs)
     assert server.rebuilds > 2            # the mix changed while jobs were running
@@ -61,12 +63,13 @@ def test_served_results_equal_standalone(S, prec_name):
         assert np.array_equal(mean, job.mean) and np.array_equal(var, job.var)
 
 
-def test_admission_respects_budget(S):
+@pytest.mark.parametrize("overlap", [False, True])
+def test_admission_respects_budget(S, overlap):
     gmrf, serve = S
     graphs = pool(gmrf)
     jobs = jobs_for(serve, graphs, gmrf.FP32_ACC64)
     budget = max(serve.chain_bytes(g, gmrf.FP32_ACC64) for g, _ in graphs) * 2
-    server = serve.Server(budget_bytes=budget, step_sweeps=10)
+    server = serve.Server(budget_bytes=budget, step_sweeps=10, overlap=overlap)
     orig_step = server.step
     seen = []
 
@@ -86,12 +89,14 @@ def test_admission_respects_budget(S):
         serve.Server(budget_bytes=budget, step_sweeps=7).submit(jobs[0])
 
 
-def test_full_config_stream_equals_standalone(S):
+@pytest.mark.parametrize("overlap", [False, True])
+def test_full_config_stream_equals_standalone(S, overlap):
     """The benchmark's serving configuration: Poisson arrivals at 200/s for
     2 s of 1000-sweep jobs on Delaunay graphs of 15,000 sites (probability
     0.98) or 1,000,000 sites (0.02), served in real time with continuous
-    batching; sampled jobs (every 1M-site job among them) equal a standalone
-    run bit for bit."""
+    batching (host work overlapped with the sweeps, or synchronised after
+    every step); sampled jobs (every 1M-site job among them) equal a
+    standalone run bit for bit."""
     gmrf, serve = S
     graphs = []
     for n, ds in [(15000, 11), (15000, 12), (15000, 13), (1_000_000, 14)]:
@@ -112,7 +117,8 @@ def test_full_config_stream_equals_standalone(S):
     import torch
 
     free, _ = torch.cuda.mem_get_info()
-    server = serve.Server(budget_bytes=int(0.5 * free), step_sweeps=10, max_active=1024)
+    server = serve.Server(budget_bytes=int(0.5 * free), step_sweeps=10, max_active=1024,
+                          overlap=overlap)
     server.run(jobs, realtime=True)
     assert len(server.finished) == len(jobs) > 300
     big = [j for j in jobs if j.sites == 1_000_000]
