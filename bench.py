@@ -471,7 +471,7 @@ def main():
                          "scale reference for FETCH_SIZE / WRITE_SIZE), then --steps sweeps")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on exactly one GPU (independent chains shard across "
+        print("bench.py: the benchmark runs on exactly one GPU (independent chains shard across "
               "GPUs without communication); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
