@@ -112,6 +112,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                                "(there is no CPU fallback)")
+        # Device memory and streams come from torch: let torch bring up the
+        # HIP runtime before the library's first HIP call, so that both use
+        # the devices torch sees.
+        _torch().cuda.is_available()
         L = C.CDLL(LIB_PATH)
         for name, (args, res) in _SIGS.items():
             f = getattr(L, name)

@@ -380,3 +380,26 @@ def test_csr_one_block_is_bitwise_color_passes(G, orc, prec, n, capture):
     ma, va, na = a.posterior_stats()
     mb, vb, nb = b.posterior_stats()
     assert na == nb == 22 and np.array_equal(ma, mb) and np.array_equal(va, vb)
+
+
+def test_library_first_load_order(G):
+    """A program that uses the library before it touches torch (a lattice
+    graph needs no device memory, so the first chain is the first device
+    call) still finds the device: the binding lets torch bring up the HIP
+    runtime before loading the library.  Fresh process, so that nothing has
+    initialised the device yet."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    prog = ("import numpy as np\n"
+            "from paper_1702_05518_amd import gmrf\n"
+            "g = gmrf.Graph(lattice=(32, 32, 4))\n"
+            "ch = gmrf.Chain(g, np.zeros(32 * 32), seed=1)\n"
+            "ch.sweep(5)\n"
+            "assert ch.get_state()[3] == 5\n"
+            "print('first-load ok')\n")
+    r = subprocess.run([sys.executable, "-c", prog], cwd=root, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0 and "first-load ok" in r.stdout, r.stderr[-2000:]
