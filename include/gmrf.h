@@ -225,20 +225,27 @@ int gmrf_chain_create_binomial(const gmrf_graph *g, const gmrf_model *m, const d
  * every sweep on the device; without it they stay fixed.  GMRF_CAPTURE
  * records the nsweeps sweeps as a HIP graph the first time a (nsweeps, flags)
  * pair is seen on this chain and replays it afterwards.  No host
- * synchronisation. */
+ * synchronisation.  Launches: a lattice sweep is one kernel, which first
+ * ends the previous sweep of the call (sums its reductions and draws the
+ * hyperparameters, in every block); a one-block commit kernel ends the
+ * call's last sweep.  A general graph runs one kernel per color and the
+ * commit kernel after every sweep.  With GMRF_WITH_HYPER a small kernel
+ * draws the rate-free parts of the hyperparameter draws (which depend only
+ * on the sweep index) before every 128 sweeps.  Sec. 2.3, Algorithm 1; the
+ * draws: Sec. 3.1 conjugate conditionals. */
 int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream);
 
 /* Profiling form of gmrf_sweep (plain launches, no capture): the same sweeps,
  * with a pair of HIP events that the dispatches themselves record at the
- * start and the end of the sweep kernels of every sweep (the lattice kernel;
- * on a general graph, from its first launch, which for the binomial model is
- * the first Polya-Gamma kernel, to the last color pass), excluding the
- * one-block finish kernel that sums the reductions and draws
- * the hyperparameters.  Synchronises and returns in *kernel_ms the summed
- * event time of the sweep kernels over the nsweeps sweeps and, if span_ms is
- * not NULL, the elapsed time from the start of the first sweep kernel to the
- * end of the last sweep's finish kernel (all events are created before the
- * first launch, so host work is not in the span). */
+ * start and the end of the sweep kernels of every sweep (the lattice kernel,
+ * which includes the end of the previous sweep; on a general graph, from
+ * its first launch, which for the binomial model is the first Polya-Gamma
+ * kernel, to the last color pass), excluding the one-block commit kernels
+ * and the unit-variate kernels.  Synchronises and returns in *kernel_ms the
+ * summed event time of the sweep kernels over the nsweeps sweeps and, if
+ * span_ms is not NULL, the elapsed time from the start of the first sweep
+ * kernel to the end of the call's last kernel (all events are created
+ * before the first launch, so host work is not in the span). */
 int gmrf_sweep_timed(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream,
                      double *kernel_ms, double *span_ms);
 
@@ -311,7 +318,7 @@ int gmrf_set_trace(gmrf_chain *c, double *d_trace, int64_t capacity, hipStream_t
  * FP64 reductions differently (results agree to rounding, not bit for bit);
  * the draws of x are keyed by site and do not depend on the shape.
  * General graphs: shape 0 launches one kernel per color (256-thread blocks)
- * and the finish kernel; shape 2 (a field of at most 122880 bytes, at most 32
+ * and the commit kernel; shape 2 (a field of at most 122880 bytes, at most 32
  * colors) runs the color passes and the draws in one 512-thread block with
  * the field in LDS -- all the sweeps of a call in one launch, or, for the
  * binomial model, one sweep per launch after the Polya-Gamma launches --
@@ -362,9 +369,12 @@ size_t gmrf_batch_footprint(gmrf_chain *const *chains, int32_t count);
 /* Group `count` distinct chains of one precision, each on its own graph or
  * sharing graphs, so that gmrf_batch_sweep advances all of them with shared
  * launches: one lattice launch per stencil covering the tiles of every
- * lattice chain, one launch per color index covering that color's slab of
- * every general-graph chain, and one finish launch with a block per chain
- * (Sec. 2.3, Algorithm 1, for every chain; the independent chains need no
+ * lattice chain (each lattice chain's sweep kernel ends its previous sweep),
+ * one launch per color index covering that color's slab of every
+ * general-graph chain followed by one commit launch with a block per
+ * general-graph chain, and at the end of the call one commit launch with a
+ * block per lattice chain (Sec. 2.3, Algorithm 1, for every chain; the
+ * independent chains need no
  * communication).  Each chain keeps its own workspace, state, reductions and
  * random streams, so its results equal those of gmrf_sweep on that chain bit
  * for bit.  The tables are uploaded to d_ws (ws_bytes >=

@@ -20,11 +20,17 @@
 //   * Every sweep kernel fuses the reductions q = x'(D - rho W)x (each edge
 //     counted once, by its higher-colored endpoint, after both ends are final)
 //     and sse = ||y - x||^2 in FP64, and the posterior accumulators.  Blocks
-//     leave FP64 partials; a one-block finish kernel sums them in fixed slot
-//     order and draws tau and lam on the device, so a sweep has no host round
-//     trip.  (The Gamma draw lives in its own kernel because its FP64
-//     transcendentals would otherwise set the register budget, and so the
-//     occupancy, of the sweep kernel.)
+//     leave FP64 partials; the end of a sweep sums them in fixed slot order
+//     and draws tau and lam on the device, so a sweep has no host round trip.
+//     A lattice sweep kernel begins by ending the previous sweep of its call:
+//     every block sums that sweep's partials and draws the same tau and lam
+//     while its tile loads are in flight (one block records them), so a
+//     lattice sweep is ONE launch; a one-block commit kernel ends the last
+//     sweep of each call.  General graphs end every sweep with that kernel.
+//     The rate-free parts of the draws (the Marsaglia-Tsang variate at rate
+//     1, the beta0 normal) depend only on the sweep index: a small kernel
+//     draws them up to kUnitBatch sweeps ahead, so no sweep kernel carries
+//     the Gamma sampler's registers.
 //   * The sweep index t lives in device memory, so a captured HIP graph of
 //     sweeps can be replayed.
 #include <hip/hip_ext.h>
@@ -55,15 +61,40 @@ struct DevState {
     double q, sse;              // reductions of the last completed sweep (sse at beta0)
     unsigned long long sweep;   // completed sweeps
     long long n_acc;            // accumulated sweeps
-    unsigned int status;        // bit 0: Gamma draw failed / non-finite
+    unsigned int status;        // bit 0: Gamma draw failed / non-finite; bit 1: no unit variates
     unsigned int pad;
     double beta0;               // intercept (0 without one)
     double rsum;                // sum_i (y_i - beta0 - x_i) of the last completed sweep
     double *trace;              // NULL, or (tau, lam, beta0) per completed sweep
     long long trace_cap;        // rows of trace
+    unsigned long long unit_base;   // sweep index of the first row of the unit-variate ring
+    // Within one call of lattice sweeps: (tau, lam, beta0) that relative sweep
+    // j >= 1 of the call runs with, at hs[j & 1] (relative sweep 0 runs with
+    // the committed tau, lam, beta0 above).  The commit at the end of the call
+    // moves the last draws into the committed fields.
+    double hs[2][3];
 };
 
 constexpr unsigned kStatusGamma = 1u;
+constexpr unsigned kStatusUnits = 2u;
+
+// The random parts of the draws after sweep t, which do not depend on the
+// sweep's reductions: the beta0 normal (tag-3 normal at counter (0, t)) and,
+// in lane 0 for tau (tag 1) and lane 1 for lam (tag 2), the Marsaglia-Tsang
+// variate d v of the conditional's shape at rate 1.  Its accept / reject
+// decisions involve only the shape, and the draw at rate b is (d v) / b, the
+// division gamma_draw ends with, so drawing the unit variate early changes
+// no bit of the result.
+struct UnitDraws {
+    double z, g;
+    bool ok;
+};
+
+// Sweeps of a call between two unit-variate launches, and the rows of the
+// ring (one more: a lattice call's sweep at the start of a group ends the
+// previous group's last sweep).
+constexpr int kUnitBatch = 128;
+constexpr int kUnitRows = kUnitBatch + 1;
 
 struct SweepArgs {
     DevState *st;
@@ -82,11 +113,14 @@ struct SweepArgs {
     int dry;                    // timing runs: write no chain state, trace or accumulators
     double b0_prec;             // binomial: prior precision of beta0 (0 = flat)
     double n_sites;
+    UnitDraws *units;           // ring of 2 kUnitRows unit variates (sweep - unit_base, lane)
+    int slot_stride;            // lattice: doubles between the two partial buffers / kPartials
+    int deferred;               // 1: lattice sweeps end in the next sweep kernel of the call
 };
 
 constexpr int kPartials = 3;
 
-constexpr int kThreads = 256;   // CSR passes, finish and stats kernels
+constexpr int kThreads = 256;   // CSR passes and stats kernels
 
 template <typename T> __device__ __forceinline__ T wave_sum(T v)
 {
@@ -140,33 +174,23 @@ struct Red {
     double q = 0.0, sse = 0.0, rsum = 0.0;
 };
 
-// A sweep block's partials, summed later in slot order.
-template <int NT> __device__ __forceinline__ void write_partials(const SweepArgs &a, Red r, int slot)
+// A sweep block's partials, summed later in slot order (P: the sweep's
+// partial buffer).
+template <int NT>
+__device__ __forceinline__ void write_partials(double *P, Red r, int slot)
 {
     __shared__ double red[kPartials * (NT / 64)];
     block_sum3<NT>(r.q, r.sse, r.rsum, red);
     if (threadIdx.x == 0) {
-        a.partials[kPartials * slot] = r.q;
-        a.partials[kPartials * slot + 1] = r.sse;
-        a.partials[kPartials * slot + 2] = r.rsum;
+        P[kPartials * slot] = r.q;
+        P[kPartials * slot + 1] = r.sse;
+        P[kPartials * slot + 2] = r.rsum;
     }
 }
 
 // Values of the chain state that the end-of-sweep draws read.
 struct HyperIn {
     double tau, lam, beta0;
-};
-
-// The random parts of the draws after sweep t, which do not depend on the
-// sweep's reductions: the beta0 normal (tag-3 normal at counter (0, t)) and,
-// in lane 0 for tau (tag 1) and lane 1 for lam (tag 2), the Marsaglia-Tsang
-// variate d v of the conditional's shape at rate 1.  Its accept / reject
-// decisions involve only the shape, and the draw at rate b is (d v) / b, the
-// division gamma_draw ends with, so drawing the unit variate early changes
-// no bit of the result.
-struct UnitDraws {
-    double z, g;
-    bool ok;
 };
 
 __device__ __forceinline__ UnitDraws unit_draws(const SweepArgs &a, unsigned t, int lane)
@@ -187,11 +211,13 @@ __device__ __forceinline__ UnitDraws unit_draws(const SweepArgs &a, unsigned t, 
 //     beta0 ~ N(mean(y - x), 1 / (n lam))      (flat prior on beta0)
 // and sse and rsum move to the new beta0:  with d = beta0' - beta0,
 //     sum (r_i - d)^2 = sse - 2 d rsum + n d^2,   sum (r_i - d) = rsum - n d.
-// Then tau (lane 0) and lam (lane 1).  Lane 0 stores the reductions and
-// beta0; the trace row t, if any, gets (tau, lam, beta0) after the draws.
+// Then tau (lane 0) and lam (lane 1).  Lane 0 stores the reductions; the
+// trace row t, if any, gets (tau, lam, beta0) after the draws.  With commit
+// the draws also become the chain's committed tau, lam and beta0 (without
+// it, inside a call of lattice sweeps, the caller keeps them).
 __device__ __forceinline__ HyperIn end_of_sweep_draws(const SweepArgs &a, unsigned t, Red r,
                                                       const HyperIn &in, int lane,
-                                                      const UnitDraws &u)
+                                                      const UnitDraws &u, bool commit = true)
 {
     double b0 = in.beta0;
     if (a.with_hyper && a.intercept) {
@@ -214,7 +240,7 @@ __device__ __forceinline__ HyperIn end_of_sweep_draws(const SweepArgs &a, unsign
         const double draw = u.ok ? u.g / rate : 0.0;
         if (u.ok && isfinite(draw) && draw > 0.0 && isfinite(b0)) {
             v = draw;
-            if (!a.dry) {
+            if (!a.dry && commit) {
                 if (lane == 0)
                     a.st->tau = v;
                 else
@@ -229,7 +255,8 @@ __device__ __forceinline__ HyperIn end_of_sweep_draws(const SweepArgs &a, unsign
         a.st->q = r.q;
         a.st->sse = r.sse;
         a.st->rsum = r.rsum;
-        a.st->beta0 = b0;
+        if (commit)
+            a.st->beta0 = b0;
         double *const tr = a.st->trace;   // read at run time: batches and graphs see changes
         if (tr && (long long)t < a.st->trace_cap) {
             tr[3 * (size_t)t] = v;
@@ -250,8 +277,6 @@ __device__ __forceinline__ HyperIn end_of_sweep_draws(const SweepArgs &a, unsign
 // The persistent kernels draw the unit variates of kUnitBatch sweeps at a
 // time, one thread per (sweep, lane), ahead of the sweeps: they depend only on
 // the sweep index, so no sweep then waits for a Gamma draw.
-constexpr int kUnitBatch = 128;
-
 // Unit variates of sweeps t .. t + cnt - 1 (cnt <= kUnitBatch) into
 // ub[sweep - t][lane]; the caller synchronises before reading them.
 template <int NT>
@@ -264,29 +289,92 @@ __device__ __forceinline__ void unit_draw_batch(const SweepArgs &a, unsigned t, 
         ub[i >> 1][i & 1] = unit_draws(a, t + (unsigned)(i >> 1), i & 1);
 }
 
-// End of a sweep (one block): sum the partials of every block of the sweep
-// in slot order, store q / sse, draw tau / lam, count the accumulated sweep
-// and advance the sweep index.  kFinishThreads threads sum the partials
-// (thread i takes slots i, i + kFinishThreads, ..., then a fixed tree); one
-// more wavefront draws the unit variates meanwhile, so that only the
-// divisions by the rates wait for the sums.
-constexpr int kFinishThreads = 256;
-constexpr int kFinishBlock = kFinishThreads + 64;
-
-__device__ __forceinline__ void finish_sweep_block(const SweepArgs &a)
+// The unit-variate ring.  Before a group of at most kUnitBatch sweeps a
+// small kernel draws the unit variates of the sweeps the group ends, one
+// thread per (sweep, lane), so that the end of a sweep only divides by the
+// rates.  Its rows start at sweep st->sweep + first (the committed sweep
+// count plus the sweeps of the call not yet committed); for a lattice call
+// the rows of a later group start one sweep before it, whose end the
+// group's first sweep kernel computes.
+__device__ __forceinline__ void unit_ring_fill(const SweepArgs &a, int first, int cnt)
 {
+    const unsigned t = (unsigned)(a.st->sweep + (unsigned long long)first);
+    for (int i = (int)threadIdx.x; i < 2 * cnt; i += (int)blockDim.x)
+        a.units[i] = unit_draws(a, t + (unsigned)(i >> 1), i & 1);
+    if (threadIdx.x == 0)
+        a.st->unit_base = (unsigned long long)t;
+}
+
+// Rows (first, count) of the ring for the group of the call's sweeps g ..
+// g + n - 1 (host and device).
+__host__ __device__ inline void unit_rows(int deferred, int g, int n, int *first, int *cnt)
+{
+    const int back = deferred && g > 0 ? 1 : 0;   // the previous group's last sweep
+    *first = deferred ? g - back : 0;             // general graphs commit every sweep
+    *cnt = n + back;
+}
+
+constexpr int kUnitThreads = 256;
+
+__global__ __launch_bounds__(kUnitThreads) void unit_draw_kernel(SweepArgs a, int g, int n)
+{
+    int first, cnt;
+    unit_rows(a.deferred, g, n, &first, &cnt);
+    unit_ring_fill(a, first, cnt);
+}
+
+// Batched form: block b fills the ring of chain b.
+__global__ __launch_bounds__(kUnitThreads) void unit_draw_batch_kernel(const SweepArgs *args,
+                                                                        int g, int n)
+{
+    SweepArgs a = args[blockIdx.x];
+    a.with_hyper = 1;
+    int first, cnt;
+    unit_rows(a.deferred, g, n, &first, &cnt);
+    unit_ring_fill(a, first, cnt);
+}
+
+// Partial buffer of relative sweep rel of a call (lattice chains alternate
+// two buffers, so a sweep kernel can read its predecessor's partials while
+// its blocks write their own).
+__device__ __forceinline__ double *partials_of(const SweepArgs &a, int rel)
+{
+    return a.partials + (size_t)kPartials * (size_t)a.slot_stride * (size_t)(rel & 1);
+}
+
+// The state relative sweep rel of a call runs with: the committed values
+// for rel 0, else the ones the sweep before it drew.
+__device__ __forceinline__ HyperIn inputs_of(const SweepArgs &a, int rel)
+{
+    if (rel == 0)
+        return HyperIn{a.st->tau, a.st->lam, a.st->beta0};
+    const double *h = a.st->hs[rel & 1];
+    return HyperIn{h[0], h[1], h[2]};
+}
+
+// End of sweep t, run by a whole block (NT >= kFinishThreads threads): sum
+// its partials P in slot order (thread i < kFinishThreads takes slots i,
+// i + kFinishThreads, ..., then a fixed tree), and draw beta0 / tau / lam
+// from the ring's unit variates (end_of_sweep_draws, which also stores q /
+// sse and the trace row unless a.dry).  Returns the draws in every thread.
+constexpr int kFinishThreads = 256;
+
+template <int NT>
+__device__ __forceinline__ HyperIn end_sweep_block(const SweepArgs &a, const double *P, unsigned t,
+                                                   const HyperIn &in, bool commit)
+{
+    static_assert(NT >= kFinishThreads && NT % 64 == 0, "the finish needs kFinishThreads threads");
     constexpr int W = kFinishThreads / 64;
     __shared__ double red[kPartials * W];
-    __shared__ UnitDraws units[2];
-    const unsigned t = (unsigned)a.st->sweep;
-    const HyperIn in{a.st->tau, a.st->lam, a.st->beta0};
+    __shared__ double hyp[3];
     const int lane = (int)threadIdx.x & 63, wid = (int)threadIdx.x >> 6;
     if (wid < W) {
         Red r;
+#pragma unroll 4
         for (int i = threadIdx.x; i < a.total_slots; i += kFinishThreads) {
-            r.q += a.partials[kPartials * i];
-            r.sse += a.partials[kPartials * i + 1];
-            r.rsum += a.partials[kPartials * i + 2];
+            r.q += P[kPartials * i];
+            r.sse += P[kPartials * i + 1];
+            r.rsum += P[kPartials * i + 2];
         }
         r.q = wave_sum(r.q);
         r.sse = wave_sum(r.sse);
@@ -296,8 +384,6 @@ __device__ __forceinline__ void finish_sweep_block(const SweepArgs &a)
             red[W + wid] = r.sse;
             red[2 * W + wid] = r.rsum;
         }
-    } else if (lane < 2) {
-        units[lane] = unit_draws(a, t, lane);
     }
     lds_barrier();
     if (wid == 0) {
@@ -310,27 +396,57 @@ __device__ __forceinline__ void finish_sweep_block(const SweepArgs &a)
             r.sse += red[W + w];
             r.rsum += red[2 * W + w];
         }
-        end_of_sweep_draws(a, t, r, in, lane, units[lane < 2 ? lane : 0]);
-        if (lane == 0 && !a.dry) {
-            if ((long long)t >= a.burn_in)
-                a.st->n_acc += 1;
-            a.st->sweep = (unsigned long long)t + 1ull;
+        UnitDraws u{0.0, 0.0, false};
+        if (a.with_hyper && lane < 2) {
+            const unsigned long long row = (unsigned long long)t - a.st->unit_base;
+            if (row < (unsigned long long)kUnitRows)
+                u = a.units[2 * row + lane];
+            else if (!a.dry)
+                atomicOr(&a.st->status, kStatusUnits);
         }
+        const HyperIn out = end_of_sweep_draws(a, t, r, in, lane, u, commit);
+        if (lane == 0) {
+            hyp[0] = out.tau;
+            hyp[1] = out.lam;
+            hyp[2] = out.beta0;
+        }
+    }
+    lds_barrier();
+    return HyperIn{hyp[0], hyp[1], hyp[2]};
+}
+
+// Commit the end of a call: end its relative sweep rel (the last of the
+// call's count sweeps) and make the draws the chain's state, count the
+// call's accumulated sweeps and advance the sweep count.  General graphs
+// commit every sweep (rel 0, count 1).
+__device__ __forceinline__ void commit_block(const SweepArgs &a, int rel, int count)
+{
+    const unsigned long long t0 = a.st->sweep;
+    const unsigned t = (unsigned)(t0 + (unsigned long long)rel);
+    const HyperIn in = inputs_of(a, rel);
+    end_sweep_block<kFinishThreads>(a, partials_of(a, rel), t, in, true);
+    if (threadIdx.x == 0 && !a.dry) {
+        const long long lo = (long long)t0 > a.burn_in ? (long long)t0 : a.burn_in;
+        const long long acc = (long long)t0 + count - lo;
+        if (acc > 0)
+            a.st->n_acc += acc;
+        a.st->sweep = t0 + (unsigned long long)count;
     }
 }
 
-__global__ __launch_bounds__(kFinishBlock) void finish_sweep_kernel(SweepArgs a)
+__global__ __launch_bounds__(kFinishThreads) void commit_kernel(SweepArgs a, int rel, int count)
 {
-    finish_sweep_block(a);
+    commit_block(a, rel, count);
 }
 
-// Batched finish: block b ends the sweep of chain b.
-__global__ __launch_bounds__(kFinishBlock) void finish_batch_kernel(const SweepArgs *args,
-                                                                     int with_hyper)
+// Batched form: block b commits chain b of the table; with_hyper: this call's
+// GMRF_WITH_HYPER (the tables are built once).
+__global__ __launch_bounds__(kFinishThreads) void commit_batch_kernel(const SweepArgs *args, int rel,
+                                                                       int count, int with_hyper)
 {
     SweepArgs a = args[blockIdx.x];
     a.with_hyper = with_hyper;
-    finish_sweep_block(a);
+    commit_block(a, rel, count);
 }
 
 // ---------------------------------------------------------------------------
@@ -392,6 +508,7 @@ template <typename Real> struct SiteCtx {
     Real beta0_r;               // intercept in the state precision
     double beta0;
     Real inv_q_full, isd_full;  // 1/Qii and Qii^-1/2 of a site with all k neighbours
+    const Real *qtab;           // LDS: 1/Qii for degree 0 .. ST, then Qii^-1/2 (qtab_fill)
     double one_minus_rho, rho;
     unsigned t;
     unsigned long long seed;
@@ -418,28 +535,41 @@ template <int ST_, int TH_, int TW_, int NT_, int CH_> struct LatCfg {
     static_assert(NT % 64 == 0, "whole wavefronts");
 };
 
+// 1/Qii and Qii^-1/2 for every degree 0 .. ST into the LDS table (threads
+// 0 .. ST), with site_scales, so a lookup is bitwise the per-site value.  The
+// caller synchronises before the table is read.
+template <typename Real, int ST>
+__device__ __forceinline__ void qtab_fill(Real *qtab, Real tau, Real lam)
+{
+    const int d = (int)threadIdx.x;
+    if (d <= ST)
+        site_scales<Real>(tau, lam, d, qtab[d], qtab[ST + 1 + d]);
+}
+
 // One site of Algorithm 1 on the LDS tile: neighbour sum in ascending
 // original-id order, conditional mean and precision, the draw; for interior
-// sites also the q / sse terms.
+// sites also the q / sse terms.  Cells of the tile outside the lattice hold
+// 0 (lattice_stage), so the neighbour sum adds every stencil cell: a missing
+// neighbour adds 0, which leaves each partial sum of the in-lattice
+// neighbours unchanged.  INTERIOR: the tile and its halo lie inside the
+// lattice, so every site has all its neighbours (compile-time flags).
 template <typename Real, typename Cfg, int J, bool INTERIOR, bool B0>
 __device__ __forceinline__ void lattice_site(Real *xs, Real yv, int r, int c, int r0, int c0,
                                              int rows, int cols, const SiteCtx<Real> &sc, Red &rd)
 {
     constexpr int ST = Cfg::ST, H = Cfg::H, LW = Cfg::LW;
     Real *p = xs + (r - r0 + H) * LW + (c - c0 + H);
-    // on an interior tile every computed site has all its neighbours
     const bool up = INTERIOR || r > 0, dn = INTERIOR || r + 1 < rows;
     const bool lf = INTERIOR || c > 0, rt = INTERIOR || c + 1 < cols;
     Real s = (Real)0;
-    int deg = 0;
-    if (ST == 8 && up && lf) { s += p[-LW - 1]; ++deg; }
-    if (up) { s += p[-LW]; ++deg; }
-    if (ST == 8 && up && rt) { s += p[-LW + 1]; ++deg; }
-    if (lf) { s += p[-1]; ++deg; }
-    if (rt) { s += p[1]; ++deg; }
-    if (ST == 8 && dn && lf) { s += p[LW - 1]; ++deg; }
-    if (dn) { s += p[LW]; ++deg; }
-    if (ST == 8 && dn && rt) { s += p[LW + 1]; ++deg; }
+    if (ST == 8) s += p[-LW - 1];
+    s += p[-LW];
+    if (ST == 8) s += p[-LW + 1];
+    s += p[-1];
+    s += p[1];
+    if (ST == 8) s += p[LW - 1];
+    s += p[LW];
+    if (ST == 8) s += p[LW + 1];
 
     const unsigned site = (unsigned)r * (unsigned)cols + (unsigned)c;
     const Words4 w = draw_words(sc.seed, site, sc.t, sc.instance, 0u);
@@ -449,7 +579,10 @@ __device__ __forceinline__ void lattice_site(Real *xs, Real yv, int r, int c, in
         inv_q = sc.inv_q_full;
         isd = sc.isd_full;
     } else {
-        site_scales<Real>(sc.tau, sc.lam, deg, inv_q, isd);
+        const int nr = 1 + (int)up + (int)dn, nc = 1 + (int)lf + (int)rt;
+        const int deg = ST == 8 ? nr * nc - 1 : nr + nc - 2;
+        inv_q = sc.qtab[deg];
+        isd = sc.qtab[ST + 1 + deg];
     }
     const Real yeff = B0 ? yv - sc.beta0_r : yv;
     const Real xn = site_draw<Real>(yeff, s, z, sc.lam, sc.tau_rho, inv_q, isd);
@@ -472,6 +605,11 @@ __device__ __forceinline__ void lattice_site(Real *xs, Real yv, int r, int c, in
         GMRF_EDGE(dn, 1, 0, LW)
         if (ST == 8) GMRF_EDGE(dn && rt, 1, 1, LW + 1)
 #undef GMRF_EDGE
+        int deg = ST;
+        if constexpr (!INTERIOR) {
+            const int nr = 1 + (int)up + (int)dn, nc = 1 + (int)lf + (int)rt;
+            deg = ST == 8 ? nr * nc - 1 : nr + nc - 2;
+        }
         rd.q += sc.one_minus_rho * (double)deg * xd * xd + sc.rho * edge;
         if constexpr (B0) {
             const double rr = (double)yv - sc.beta0 - xd;
@@ -580,34 +718,76 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     return x * per + min(x, rem) + (b >> 3);
 }
 
+// Stage the tile whose top-left interior site is (r0, c0), with its halo,
+// into LDS, in two steps so that other work can run while the loads are in
+// flight: lattice_load issues every load of the thread (cells outside the
+// lattice become 0, their loads using an address clamped into the lattice,
+// which the site update relies on), lattice_store writes them to LDS.
+template <typename Cfg> constexpr int tile_loads()
+{
+    return (Cfg::LH * Cfg::LW + Cfg::NT - 1) / Cfg::NT;
+}
+
+template <typename Real, typename Cfg>
+__device__ __forceinline__ void lattice_load(Real (&v)[tile_loads<Cfg>()],
+                                             const Real *__restrict__ src, int r0, int c0,
+                                             int rows, int cols)
+{
+    constexpr int H = Cfg::H, LW = Cfg::LW, NT = Cfg::NT;
+#pragma unroll
+    for (int k = 0; k < tile_loads<Cfg>(); ++k) {
+        const int idx = (int)threadIdx.x + k * NT;
+        const int lr = idx / LW, lc = idx - (idx / LW) * LW;
+        const int r = r0 - H + lr, c = c0 - H + lc;
+        const int rc = min(max(r, 0), rows - 1), cc = min(max(c, 0), cols - 1);
+        v[k] = src[(size_t)rc * cols + cc];
+        if (r != rc || c != cc)
+            v[k] = (Real)0;
+    }
+}
+
+template <typename Real, typename Cfg>
+__device__ __forceinline__ void lattice_store(Real *xs, const Real (&v)[tile_loads<Cfg>()])
+{
+    constexpr int NL = tile_loads<Cfg>(), NT = Cfg::NT;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int idx = (int)threadIdx.x + k * NT;
+        if (k < NL - 1 || idx < Cfg::LH * Cfg::LW)
+            xs[idx] = v[k];
+    }
+}
+
+// Tiles of a lattice take one of two compiled paths, an interior one (tile
+// and halo inside the lattice: compile-time neighbour flags and scales) and
+// the general one, or the general one alone.  The second halves the
+// kernel's code, which on this target decides more than the per-site
+// arithmetic once the code outgrows the instruction cache.
+#ifndef GMRF_LAT_SPLIT
+#define GMRF_LAT_SPLIT 1
+#endif
+
 // B0: the chain has an intercept (compile time, so that chains without one
-// run code with no trace of it).
+// run code with no trace of it).  rel: the sweep's index within its call
+// (sweep t = committed count + rel).  fold: the sweep before it in the call
+// has not been ended: every block ends it first (sums its partials and draws
+// tau, lam, beta0, identically in every block; the tile loads wait, since
+// holding them across the draws would cost the kernel its occupancy), and
+// the block of tile 0 records the draws for the next sweep kernel and the
+// commit.  Without fold the sweep runs with the committed
+// state (the first sweep of a call, and timing runs).
 template <typename Real, typename Cfg, bool B0>
 __device__ __forceinline__ void lattice_sweep_block(const LatArgs<Real> &la, const SweepArgs &a,
-                                                    const int tile)
+                                                    const int tile, const int rel, const int fold)
 {
     constexpr int H = Cfg::H, LH = Cfg::LH, LW = Cfg::LW, NT = Cfg::NT;
     constexpr int TH = Cfg::TH, TW = Cfg::TW;
-    constexpr int NL = (LH * LW + NT - 1) / NT;        // tile loads per thread
     constexpr int NPT = (TH * TW + NT - 1) / NT;       // interior sites per thread
     constexpr int CH = Cfg::CH < NPT ? Cfg::CH : NPT;  // accumulator batch
     __shared__ Real xs[LH * LW];
+    __shared__ Real qtab[2 * (Cfg::ST + 1)];
 
-    const unsigned t = (unsigned)a.st->sweep;
-    SiteCtx<Real> sc;
-    const double tau = a.st->tau, lam = a.st->lam;
-    sc.tau = (Real)tau;
-    sc.lam = (Real)lam;
-    sc.tau_rho = (Real)(tau * a.rho);
-    site_scales<Real>(sc.tau, sc.lam, Cfg::ST, sc.inv_q_full, sc.isd_full);
-    sc.beta0 = B0 ? a.st->beta0 : 0.0;
-    sc.beta0_r = (Real)sc.beta0;
-    sc.one_minus_rho = 1.0 - a.rho;
-    sc.rho = a.rho;
-    sc.t = t;
-    sc.seed = a.seed;
-    sc.instance = a.instance;
-
+    const unsigned t = (unsigned)(a.st->sweep + (unsigned long long)rel);
     const Real *src = (t & 1u) ? la.x1 : la.x0;
     Real *dst = (t & 1u) ? la.x0 : la.x1;
     const int rows = la.rows, cols = la.cols;
@@ -615,34 +795,50 @@ __device__ __forceinline__ void lattice_sweep_block(const LatArgs<Real> &la, con
     const int r0 = tr * TH, c0 = tc * TW;
     const bool acc = (long long)t >= a.burn_in;
 
-    // Stage the tile and its halo: all loads of a thread are issued before
-    // the first LDS store.  Addresses are clamped into the lattice; cells
-    // outside the lattice are never read by the phases.
-    {
-        Real v[NL];
-#pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int idx = (int)threadIdx.x + k * NT;
-            const int lr = idx / LW, lc = idx - (idx / LW) * LW;
-            const int r = min(max(r0 - H + lr, 0), rows - 1);
-            const int c = min(max(c0 - H + lc, 0), cols - 1);
-            v[k] = src[(size_t)r * cols + c];
+    HyperIn hin;
+    if (fold) {
+        SweepArgs fa = a;
+        fa.dry = a.dry || tile != 0;      // one block stores the reductions and the trace
+        hin = end_sweep_block<NT>(fa, partials_of(a, rel - 1), t - 1u, inputs_of(a, rel - 1),
+                                  false);
+        if (!fa.dry && threadIdx.x == 0) {
+            double *const h = a.st->hs[rel & 1];
+            h[0] = hin.tau;
+            h[1] = hin.lam;
+            h[2] = hin.beta0;
         }
-#pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int idx = (int)threadIdx.x + k * NT;
-            if (k < NL - 1 || idx < LH * LW)
-                xs[idx] = v[k];
-        }
+    } else {
+        hin = inputs_of(a, 0);
     }
+    Real v[tile_loads<Cfg>()];
+    lattice_load<Real, Cfg>(v, src, r0, c0, rows, cols);
+
+    SiteCtx<Real> sc;
+    sc.tau = (Real)hin.tau;
+    sc.lam = (Real)hin.lam;
+    sc.tau_rho = (Real)(hin.tau * a.rho);
+    site_scales<Real>(sc.tau, sc.lam, Cfg::ST, sc.inv_q_full, sc.isd_full);
+    sc.beta0 = B0 ? hin.beta0 : 0.0;
+    sc.beta0_r = (Real)sc.beta0;
+    sc.one_minus_rho = 1.0 - a.rho;
+    sc.rho = a.rho;
+    sc.t = t;
+    sc.seed = a.seed;
+    sc.instance = a.instance;
+    sc.qtab = qtab;
+
+    lattice_store<Real, Cfg>(xs, v);
+    qtab_fill<Real, Cfg::ST>(qtab, sc.tau, sc.lam);
     lds_barrier();
 
     Red rd;
+#if GMRF_LAT_SPLIT
     const bool interior = r0 >= H && c0 >= H && r0 + TH + Cfg::HH <= rows &&
                           c0 + TW + Cfg::HH <= cols;
     if (interior)
         lattice_phases<Real, Cfg, true, B0>(xs, la.y, r0, c0, rows, cols, sc, rd);
     else
+#endif
         lattice_phases<Real, Cfg, false, B0>(xs, la.y, r0, c0, rows, cols, sc, rd);
 
     // Write the interior back and update the accumulators, CH sites per
@@ -680,20 +876,22 @@ __device__ __forceinline__ void lattice_sweep_block(const LatArgs<Real> &la, con
             }
         }
     }
-    write_partials<NT>(a, rd, tile);
+    write_partials<NT>(partials_of(a, rel), rd, tile);
 }
 
 template <typename Real, typename Cfg, bool B0>
-__global__ __launch_bounds__(Cfg::NT) void lattice_sweep_kernel(LatArgs<Real> la, SweepArgs a)
+__global__ __launch_bounds__(Cfg::NT) void lattice_sweep_kernel(LatArgs<Real> la, SweepArgs a,
+                                                                int rel, int fold)
 {
-    lattice_sweep_block<Real, Cfg, B0>(la, a, xcd_tile((int)blockIdx.x, (int)gridDim.x));
+    lattice_sweep_block<Real, Cfg, B0>(la, a, xcd_tile((int)blockIdx.x, (int)gridDim.x), rel,
+                                       fold);
 }
 
 // A lattice that fits one tile, many sweeps in one launch (one block): the
 // field stays in LDS (after a sweep every site of the tile is final, so the
 // next sweep needs no reload), this thread's accumulators stay in registers,
 // and the end-of-sweep reductions and draws run in the block itself.  Every
-// operation is the one the tile kernel and the finish kernel perform for a
+// operation is the one the tile kernel and the end of its sweep perform for a
 // single-tile lattice, in the same order, so the results are bitwise those of
 // tile shape 0.  With a.dry set (timing) it writes only the state buffer that
 // the sweep after the last one would overwrite.
@@ -703,9 +901,9 @@ __global__ __launch_bounds__(Cfg::NT) void lattice_persistent_kernel(LatArgs<Rea
 {
     constexpr int H = Cfg::H, LH = Cfg::LH, LW = Cfg::LW, NT = Cfg::NT;
     constexpr int TH = Cfg::TH, TW = Cfg::TW;
-    constexpr int NL = (LH * LW + NT - 1) / NT;
     constexpr int NPT = (TH * TW + NT - 1) / NT;
     __shared__ Real xs[LH * LW];
+    __shared__ Real qtab[2 * (Cfg::ST + 1)];
     __shared__ double red[kPartials * (NT / 64)];
     __shared__ double hyp[3];
     __shared__ UnitDraws ub[kUnitBatch][2];
@@ -715,22 +913,9 @@ __global__ __launch_bounds__(Cfg::NT) void lattice_persistent_kernel(LatArgs<Rea
     long long nacc = a.st->n_acc;
     double tau = a.st->tau, lam = a.st->lam, b0 = B0 ? a.st->beta0 : 0.0;
     {
-        const Real *src = (t & 1u) ? la.x1 : la.x0;
-        Real v[NL];
-#pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int idx = (int)threadIdx.x + k * NT;
-            const int lr = idx / LW, lc = idx - (idx / LW) * LW;
-            const int r = min(max(lr - H, 0), rows - 1);
-            const int c = min(max(lc - H, 0), cols - 1);
-            v[k] = src[(size_t)r * cols + c];
-        }
-#pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int idx = (int)threadIdx.x + k * NT;
-            if (k < NL - 1 || idx < LH * LW)
-                xs[idx] = v[k];
-        }
+        Real v[tile_loads<Cfg>()];
+        lattice_load<Real, Cfg>(v, (t & 1u) ? la.x1 : la.x0, 0, 0, rows, cols);
+        lattice_store<Real, Cfg>(xs, v);
     }
     double s1r[NPT], s2r[NPT];
     int gi[NPT];
@@ -763,6 +948,9 @@ __global__ __launch_bounds__(Cfg::NT) void lattice_persistent_kernel(LatArgs<Rea
         sc.t = t;
         sc.seed = a.seed;
         sc.instance = a.instance;
+        sc.qtab = qtab;
+        qtab_fill<Real, Cfg::ST>(qtab, sc.tau, sc.lam);
+        lds_barrier();
         Red rd;
         lattice_phases<Real, Cfg, false, B0>(xs, la.y, 0, 0, rows, cols, sc, rd);
         if ((long long)t >= a.burn_in) {
@@ -781,7 +969,7 @@ __global__ __launch_bounds__(Cfg::NT) void lattice_persistent_kernel(LatArgs<Rea
         }
         block_sum3<NT>(rd.q, rd.sse, rd.rsum, red);
         if (threadIdx.x < 64) {
-            // the finish kernel's sum over one partial slot: x + 0 + ... = x
+            // the end-of-sweep sum over one partial slot: x + 0 + ... = x
             rd.q = __shfl(rd.q, 0, 64);
             rd.sse = __shfl(rd.sse, 0, 64);
             rd.rsum = __shfl(rd.rsum, 0, 64);
@@ -830,13 +1018,18 @@ struct LatTile {
     int job, tile;
 };
 
+// with_hyper: this call's GMRF_WITH_HYPER (the job tables are built once);
+// rel, fold: as for lattice_sweep_block, the same for every chain.
 template <typename Real, typename Cfg, bool B0>
 __global__ __launch_bounds__(Cfg::NT) void lattice_batch_kernel(const LatJob<Real> *jobs,
-                                                                const LatTile *tiles)
+                                                                const LatTile *tiles,
+                                                                int with_hyper, int rel, int fold)
 {
     const LatTile tl = tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
     const LatJob<Real> &j = jobs[tl.job];
-    lattice_sweep_block<Real, Cfg, B0>(j.la, j.a, tl.tile);
+    SweepArgs a = j.a;
+    a.with_hyper = with_hyper;
+    lattice_sweep_block<Real, Cfg, B0>(j.la, a, tl.tile, rel, fold);
 }
 
 // ---------------------------------------------------------------------------
@@ -1015,7 +1208,8 @@ __device__ __forceinline__ void csr_site(const CsrArgs<Real> &ca, const SweepArg
     }
 }
 
-// Sites p0 + threadIdx.x of the color slab [lo, lo + cnt); partial slot `slot`.
+// Sites p0 + threadIdx.x of the color slab [lo, lo + cnt); partial slot
+// `slot`.
 template <typename Real, bool B0, bool BIN, int NB = kCsrBatch, bool WIDE = true>
 __device__ __forceinline__ void csr_pass_block(const CsrArgs<Real> &ca, const SweepArgs &a,
                                                const int lo, const int cnt, const int p0,
@@ -1026,7 +1220,7 @@ __device__ __forceinline__ void csr_pass_block(const CsrArgs<Real> &ca, const Sw
     Red rd;
     if (p < lo + cnt)
         csr_site<Real, B0, BIN, NB, WIDE>(ca, a, ca.x, p, lo, v, rd);
-    write_partials<kThreads>(a, rd, slot);
+    write_partials<kThreads>(a.partials, rd, slot);
 }
 
 // Block b takes chunk xcd_tile(b) of the slab (kThreads sites each), so each
@@ -1053,11 +1247,14 @@ struct CsrBlock {
 
 template <typename Real, bool B0>
 __global__ __launch_bounds__(kThreads) void csr_batch_kernel(const CsrJob<Real> *jobs,
-                                                             const CsrBlock *blocks)
+                                                             const CsrBlock *blocks,
+                                                             int with_hyper)
 {
     const CsrBlock bk = blocks[xcd_tile((int)blockIdx.x, (int)gridDim.x)];   // chains per XCD
     const CsrJob<Real> &j = jobs[bk.job];
-    csr_pass_block<Real, B0, false, kCsrBatchShared, false>(j.ca, j.a, bk.lo, bk.cnt, bk.p0,
+    SweepArgs a = j.a;
+    a.with_hyper = with_hyper;
+    csr_pass_block<Real, B0, false, kCsrBatchShared, false>(j.ca, a, bk.lo, bk.cnt, bk.p0,
                                                          bk.slot);
 }
 
@@ -1066,11 +1263,11 @@ __global__ __launch_bounds__(kThreads) void csr_batch_kernel(const CsrJob<Real> 
 // ---------------------------------------------------------------------------
 // The field of a small general graph (n values within kCsrLdsBytes) stays in
 // LDS for the whole launch, and one block does what the k color-pass
-// launches and the finish kernel do, in the same order of operations: each
+// launches and the commit kernel do, in the same order of operations: each
 // color's slab is cut into the same groups of kThreads sites as the pass
 // kernels' blocks (each wavefront takes 64 consecutive sites of a group,
 // every site in the lane it has there), the groups' FP64 partials land in
-// the same slots, and the slots are summed as the finish kernel sums them.
+// the same slots, and the slots are summed as the commit kernel sums them.
 // So the results are bitwise those of the color passes, without their
 // k + 1 launches per sweep, whose dispatch latency dominates small graphs.
 // A Gaussian chain runs all the sweeps of a call in one launch; a binomial
@@ -1132,7 +1329,7 @@ __global__ __launch_bounds__(kCsrPersistThreads) void csr_persistent_kernel(CsrA
             slot0 += groups;
             lds_barrier();
         }
-        // the finish kernel's sum: thread i < kThreads adds slots i, i + kThreads,
+        // the commit kernel's sum: thread i < kThreads adds slots i, i + kThreads,
         // ... (each slot the pass block's sum of its wavefronts, in order), then
         // the fixed tree over the first kThreads threads
         Red r;
@@ -1311,7 +1508,8 @@ __global__ __launch_bounds__(kThreads) void csr_binomial_pass_kernel(CsrArgs<Rea
 // small kernels
 // ---------------------------------------------------------------------------
 // Redraw after the last completed sweep from its stored reductions (one
-// wavefront); bitwise what the finish kernel draws with hyperparameters on.
+// wavefront); bitwise what the end of that sweep draws with hyperparameters
+// on.
 __global__ void hyper_kernel(SweepArgs a)
 {
     const unsigned t = (unsigned)(a.st->sweep - 1ull);
@@ -1381,6 +1579,8 @@ struct gmrf_chain {
     double *d_s1 = nullptr, *d_s2 = nullptr;
     double *d_partials = nullptr;
     double *d_stats = nullptr;
+    UnitDraws *d_units = nullptr;     // ring of unit variates drawn ahead of the sweeps
+    int slot_stride = 0;              // partial slots reserved per buffer (lattice: two)
     int total_slots = 0;              // partial slots of one sweep (current tile shape)
     int lat_tile = 0;                 // shape: lattice tile (index into kTiles); general
                                       // graph: 0 color passes, kPersistent one block
@@ -1412,7 +1612,10 @@ struct gmrf_batch {
     void *csr_jobs[2] = {};
     CsrBlock *csr_blocks[2] = {};
     std::vector<int> csr_color_off[2];            // per color index: first block
-    SweepArgs *fin_args = nullptr;
+    SweepArgs *unit_args = nullptr;               // per chain, for the unit-variate launches
+    SweepArgs *csr_commit = nullptr;              // general-graph chains: commit every sweep
+    SweepArgs *lat_commit = nullptr;              // lattice chains: commit at the end of a call
+    int n_csr = 0, n_lat = 0;
     char *ws = nullptr;                           // the caller's workspace (job tables)
     hipStream_t capture_stream = nullptr;
     std::map<std::pair<int, unsigned>, hipGraphExec_t> graphs;
@@ -1518,7 +1721,10 @@ size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chai
     char *y = take(rs * n);
     char *s1 = take(8 * n);
     char *s2 = take(8 * n);
-    char *part = take(8 * kPartials * (size_t)std::max(reserve, 1));
+    // lattice sweeps alternate two partial buffers (a sweep kernel ends the
+    // previous sweep from its buffer while writing its own)
+    char *part = take(8 * kPartials * (size_t)std::max(reserve, 1) * (is_lattice(g) ? 2 : 1));
+    char *units = take(sizeof(UnitDraws) * 2 * kUnitRows);
     char *stats = take(16 * n);
     char *trials = binomial ? take(4 * n) : nullptr;
     char *chunk_off = binomial ? take(4 * (size_t)(n + 1)) : nullptr;
@@ -1541,6 +1747,8 @@ size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chai
         c->d_s2 = reinterpret_cast<double *>(s2);
         c->d_partials = reinterpret_cast<double *>(part);
         c->d_stats = reinterpret_cast<double *>(stats);
+        c->d_units = reinterpret_cast<UnitDraws *>(units);
+        c->slot_stride = std::max(reserve, 1);
         c->total_slots = slots;
         c->pass_blocks = pass_blocks;
     }
@@ -1584,6 +1792,9 @@ SweepArgs make_args(const gmrf_chain *c, unsigned flags)
     a.likelihood = c->binomial ? 1 : 0;
     a.b0_prec = c->binomial && c->model.beta0_var > 0.0 ? 1.0 / c->model.beta0_var : 0.0;
     a.n_sites = (double)c->g->h.n;
+    a.units = c->d_units;
+    a.slot_stride = c->slot_stride;
+    a.deferred = is_lattice(c->g) ? 1 : 0;
     return a;
 }
 
@@ -1623,7 +1834,7 @@ template <typename Real> CsrArgs<Real> csr_args(const gmrf_chain *c)
 // the end of the sweep kernel(s), for the profiling entry point.
 template <typename Real, int ST, int K>
 void launch_lattice_shape(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent_t ev0,
-                          hipEvent_t ev1)
+                          hipEvent_t ev1, int rel, int fold)
 {
     const LatArgs<Real> la = lattice_args<Real>(c);
     using Cfg = LatticeCfg<ST, K>;
@@ -1631,19 +1842,19 @@ void launch_lattice_shape(const gmrf_chain *c, const SweepArgs &a, hipStream_t s
                                    : lattice_sweep_kernel<Real, Cfg, false>;
     if (ev0 || ev1)
         hipExtLaunchKernelGGL(kern, dim3(c->total_slots), dim3(Cfg::NT), 0, s, ev0, ev1, 0, la,
-                              a);
+                              a, rel, fold);
     else
-        hipLaunchKernelGGL(kern, dim3(c->total_slots), dim3(Cfg::NT), 0, s, la, a);
+        hipLaunchKernelGGL(kern, dim3(c->total_slots), dim3(Cfg::NT), 0, s, la, a, rel, fold);
 }
 
 template <typename Real, int ST>
 void launch_lattice(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent_t ev0,
-                    hipEvent_t ev1)
+                    hipEvent_t ev1, int rel, int fold)
 {
     if (tile_cfg(c->lat_tile) == 0)
-        launch_lattice_shape<Real, ST, 0>(c, a, s, ev0, ev1);
+        launch_lattice_shape<Real, ST, 0>(c, a, s, ev0, ev1, rel, fold);
     else
-        launch_lattice_shape<Real, ST, 1>(c, a, s, ev0, ev1);
+        launch_lattice_shape<Real, ST, 1>(c, a, s, ev0, ev1, rel, fold);
 }
 
 // nsweeps sweeps of a shape-2 chain in one launch of the persistent kernel.
@@ -1737,7 +1948,7 @@ int csr_default_shape(const HostGraph &h, gmrf_precision p)
 // binomial model, whose Polya-Gamma launches come between sweeps.)
 bool is_persistent(const gmrf_chain *c) { return c->lat_tile == kPersistent && !c->binomial; }
 
-// Does the chain draw the hyperparameters inside its sweep kernel (no finish
+// Does the chain draw the hyperparameters inside its sweep kernel (no commit
 // kernel)?
 bool draws_in_sweep(const gmrf_chain *c) { return c->lat_tile == kPersistent; }
 
@@ -1814,33 +2025,69 @@ void launch_csr(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent
     }
 }
 
-// The sweep kernels of one sweep (everything but the finish kernel).
-void launch_sweep_kernels(const gmrf_chain *c, const SweepArgs &a, hipStream_t s,
+// The sweep kernels of relative sweep rel of a call (a lattice: one launch,
+// which ends the previous sweep of the call unless rel is 0; a general
+// graph: the color passes).  A timing run (a.dry) repeats relative sweep 0:
+// it never advances the sweep count, so every repetition reads the current
+// state buffer and writes only the other one.
+void launch_sweep_kernels(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, int rel,
                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
     const bool f64 = c->prec == GMRF_FP64;
+    if (a.dry)
+        rel = 0;
     if (is_lattice(c->g)) {
+        const int fold = rel > 0 ? 1 : 0;
         if (c->g->h.stencil == 4)
-            f64 ? launch_lattice<double, 4>(c, a, s, ev0, ev1)
-                : launch_lattice<float, 4>(c, a, s, ev0, ev1);
+            f64 ? launch_lattice<double, 4>(c, a, s, ev0, ev1, rel, fold)
+                : launch_lattice<float, 4>(c, a, s, ev0, ev1, rel, fold);
         else
-            f64 ? launch_lattice<double, 8>(c, a, s, ev0, ev1)
-                : launch_lattice<float, 8>(c, a, s, ev0, ev1);
+            f64 ? launch_lattice<double, 8>(c, a, s, ev0, ev1, rel, fold)
+                : launch_lattice<float, 8>(c, a, s, ev0, ev1, rel, fold);
     } else {
         f64 ? launch_csr<double>(c, a, s, ev0, ev1) : launch_csr<float>(c, a, s, ev0, ev1);
     }
 }
 
-void launch_finish(const SweepArgs &a, hipStream_t s)
+void launch_commit(const SweepArgs &a, int rel, int count, hipStream_t s)
 {
-    hipLaunchKernelGGL(finish_sweep_kernel, dim3(1), dim3(kFinishBlock), 0, s, a);
+    hipLaunchKernelGGL(commit_kernel, dim3(1), dim3(kFinishThreads), 0, s, a, rel, count);
 }
 
-void launch_one_sweep(const gmrf_chain *c, const SweepArgs &a, hipStream_t s)
+// Before relative sweep i of a call of nsweeps: the unit-variate launch of
+// its group (every kUnitBatch sweeps, when the sweeps draw the
+// hyperparameters and the chain's kernels do not draw their own).
+void launch_units_ahead(const gmrf_chain *c, const SweepArgs &a, int i, int nsweeps,
+                        hipStream_t s)
 {
-    launch_sweep_kernels(c, a, s);
-    if (!draws_in_sweep(c))
-        launch_finish(a, s);
+    if (!a.with_hyper || draws_in_sweep(c) || i % kUnitBatch != 0)
+        return;
+    hipLaunchKernelGGL(unit_draw_kernel, dim3(1), dim3(kUnitThreads), 0, s, a, i,
+                       std::min(kUnitBatch, nsweeps - i));
+}
+
+// After relative sweep i of a call of nsweeps: its commit where one is due
+// (a general graph after every sweep, a lattice after the call's last; none
+// where the kernels draw themselves, or for timing runs of a lattice).
+void launch_commit_after(const gmrf_chain *c, const SweepArgs &a, int i, int nsweeps,
+                         hipStream_t s)
+{
+    if (draws_in_sweep(c))
+        return;
+    if (!is_lattice(c->g))
+        launch_commit(a, 0, 1, s);
+    else if (i == nsweeps - 1 && !a.dry)
+        launch_commit(a, i, nsweeps, s);
+}
+
+// nsweeps sweeps of a chain with per-sweep launches.
+void launch_sweeps(const gmrf_chain *c, const SweepArgs &a, int nsweeps, hipStream_t s)
+{
+    for (int i = 0; i < nsweeps; ++i) {
+        launch_units_ahead(c, a, i, nsweeps, s);
+        launch_sweep_kernels(c, a, s, i);
+        launch_commit_after(c, a, i, nsweeps, s);
+    }
 }
 
 int read_state(gmrf_chain *c, DevState *out, hipStream_t s)
@@ -1955,7 +2202,9 @@ bool finite_array(const double *v, int64_t n)
 struct BatchImage {
     std::vector<char> bytes;
     size_t off_lat_jobs[8] = {}, off_lat_tiles[8] = {};
-    size_t off_csr_jobs[2] = {}, off_csr_blocks[2] = {}, off_fin = 0;
+    size_t off_csr_jobs[2] = {}, off_csr_blocks[2] = {}, off_units = 0;
+    size_t off_csr_commit = 0, off_lat_commit = 0;
+    int n_csr = 0, n_lat = 0;
     int lat_tile_count[8] = {};
     std::vector<int> csr_color_off[2];
 };
@@ -1980,24 +2229,27 @@ void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im, int 
     std::vector<LatTile> ltiles[8];
     std::vector<CsrJob<Real>> cjobs[2];
     std::vector<std::vector<CsrBlock>> cblocks[2];   // per color index
-    std::vector<SweepArgs> fin;
+    std::vector<SweepArgs> units, csr_commit, lat_commit;
     for (const gmrf_chain *c : cs) {
         const SweepArgs a = make_args(c, 0u);
-        fin.push_back(a);
+        units.push_back(a);
         const HostGraph &h = c->g->h;
         const int g = c->model.intercept ? 1 : 0;
         if (is_lattice(c->g)) {
             const int cfg = force >= 0 ? force : tile_cfg(c->lat_tile);
             const int w = (h.stencil == 8 ? 1 : 0) + 2 * g + 4 * cfg;
             const int job = (int)ljobs[w].size();
-            const SweepArgs la_args = dry ? dry_args(a, c) : a;
-            ljobs[w].push_back(LatJob<Real>{lattice_args<Real>(c, cfg), la_args});
             const int tiles = lattice_blocks(h, cfg);
+            SweepArgs la_args = dry ? dry_args(a, c) : a;
+            la_args.total_slots = tiles;       // the partial slots of this chain's sweep
+            ljobs[w].push_back(LatJob<Real>{lattice_args<Real>(c, cfg), la_args});
+            lat_commit.push_back(la_args);
             for (int t = 0; t < tiles; ++t)
                 ltiles[w].push_back(LatTile{job, t});
         } else {
             const int job = (int)cjobs[g].size();
             cjobs[g].push_back(CsrJob<Real>{csr_args<Real>(c), a});
+            csr_commit.push_back(a);
             if ((int)cblocks[g].size() < h.k)
                 cblocks[g].resize(h.k);
             int slot = 0;
@@ -2025,7 +2277,11 @@ void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im, int 
         im.off_csr_jobs[g] = append(im.bytes, cjobs[g]);
         im.off_csr_blocks[g] = append(im.bytes, flat);
     }
-    im.off_fin = append(im.bytes, fin);
+    im.off_units = append(im.bytes, units);
+    im.off_csr_commit = append(im.bytes, csr_commit);
+    im.off_lat_commit = append(im.bytes, lat_commit);
+    im.n_csr = (int)csr_commit.size();
+    im.n_lat = (int)lat_commit.size();
 }
 
 int check_batch_chains(gmrf_chain *const *chains, int32_t count, gmrf_precision *prec)
@@ -2105,22 +2361,28 @@ int install_image(gmrf_batch *b, const BatchImage &im, hipStream_t stream)
         b->csr_blocks[g] = reinterpret_cast<CsrBlock *>(b->ws + im.off_csr_blocks[g]);
         b->csr_color_off[g] = im.csr_color_off[g];
     }
-    b->fin_args = reinterpret_cast<SweepArgs *>(b->ws + im.off_fin);
+    b->unit_args = reinterpret_cast<SweepArgs *>(b->ws + im.off_units);
+    b->csr_commit = reinterpret_cast<SweepArgs *>(b->ws + im.off_csr_commit);
+    b->lat_commit = reinterpret_cast<SweepArgs *>(b->ws + im.off_lat_commit);
+    b->n_csr = im.n_csr;
+    b->n_lat = im.n_lat;
     return GMRF_OK;
 }
 
 template <typename Real, int ST, bool B0, int K>
-void launch_lattice_group(const gmrf_batch *b, hipStream_t s)
+void launch_lattice_group(const gmrf_batch *b, int hyper, int rel, int fold, hipStream_t s)
 {
     const int w = (ST == 8 ? 1 : 0) + (B0 ? 2 : 0) + 4 * K;
     using Cfg = LatticeCfg<ST, K>;
     if (b->lat_tile_count[w] > 0)
         hipLaunchKernelGGL((lattice_batch_kernel<Real, Cfg, B0>), dim3(b->lat_tile_count[w]),
                            dim3(Cfg::NT), 0, s,
-                           static_cast<const LatJob<Real> *>(b->lat_jobs[w]), b->lat_tiles[w]);
+                           static_cast<const LatJob<Real> *>(b->lat_jobs[w]), b->lat_tiles[w],
+                           hyper, rel, fold);
 }
 
-template <typename Real, bool B0> void launch_csr_group(const gmrf_batch *b, size_t col, hipStream_t s)
+template <typename Real, bool B0>
+void launch_csr_group(const gmrf_batch *b, size_t col, int hyper, hipStream_t s)
 {
     const int g = B0 ? 1 : 0;
     if (col + 1 >= b->csr_color_off[g].size())
@@ -2129,41 +2391,60 @@ template <typename Real, bool B0> void launch_csr_group(const gmrf_batch *b, siz
     if (nb > 0)
         hipLaunchKernelGGL((csr_batch_kernel<Real, B0>), dim3(nb), dim3(kThreads), 0, s,
                            static_cast<const CsrJob<Real> *>(b->csr_jobs[g]),
-                           b->csr_blocks[g] + b->csr_color_off[g][col]);
+                           b->csr_blocks[g] + b->csr_color_off[g][col], hyper);
 }
 
-template <typename Real> void launch_batch_lattice_kernels(const gmrf_batch *b, hipStream_t s)
+// rel, fold: as for lattice_sweep_block (relative sweep of the call; end the
+// previous one first).
+template <typename Real>
+void launch_batch_lattice_kernels(const gmrf_batch *b, int hyper, int rel, int fold,
+                                  hipStream_t s)
 {
-    launch_lattice_group<Real, 4, false, 0>(b, s);
-    launch_lattice_group<Real, 8, false, 0>(b, s);
-    launch_lattice_group<Real, 4, true, 0>(b, s);
-    launch_lattice_group<Real, 8, true, 0>(b, s);
-    launch_lattice_group<Real, 4, false, 1>(b, s);
-    launch_lattice_group<Real, 8, false, 1>(b, s);
-    launch_lattice_group<Real, 4, true, 1>(b, s);
-    launch_lattice_group<Real, 8, true, 1>(b, s);
+    launch_lattice_group<Real, 4, false, 0>(b, hyper, rel, fold, s);
+    launch_lattice_group<Real, 8, false, 0>(b, hyper, rel, fold, s);
+    launch_lattice_group<Real, 4, true, 0>(b, hyper, rel, fold, s);
+    launch_lattice_group<Real, 8, true, 0>(b, hyper, rel, fold, s);
+    launch_lattice_group<Real, 4, false, 1>(b, hyper, rel, fold, s);
+    launch_lattice_group<Real, 8, false, 1>(b, hyper, rel, fold, s);
+    launch_lattice_group<Real, 4, true, 1>(b, hyper, rel, fold, s);
+    launch_lattice_group<Real, 8, true, 1>(b, hyper, rel, fold, s);
 }
 
-template <typename Real> void launch_batch_sweep_kernels(const gmrf_batch *b, hipStream_t s)
+template <typename Real>
+void launch_batch_sweep_kernels(const gmrf_batch *b, int hyper, int rel, int fold, hipStream_t s)
 {
-    launch_batch_lattice_kernels<Real>(b, s);
+    launch_batch_lattice_kernels<Real>(b, hyper, rel, fold, s);
     // color c of every general-graph chain before color c + 1 of any
     const size_t ncol = std::max(b->csr_color_off[0].size(), b->csr_color_off[1].size());
     for (size_t col = 0; col + 1 < ncol; ++col) {
-        launch_csr_group<Real, false>(b, col, s);
-        launch_csr_group<Real, true>(b, col, s);
+        launch_csr_group<Real, false>(b, col, hyper, s);
+        launch_csr_group<Real, true>(b, col, hyper, s);
     }
 }
 
-void launch_batch_sweep(const gmrf_batch *b, unsigned flags, hipStream_t s)
+// nsweeps sweeps of every chain of a batch: the shared launches of each
+// sweep (the last launch covering a chain ends that chain's sweep), and with
+// hyperparameter draws, ahead of every kUnitBatch sweeps, one launch that
+// draws the unit variates of every chain.
+void launch_batch_sweeps(const gmrf_batch *b, int nsweeps, unsigned flags, hipStream_t s)
 {
-    if (b->prec == GMRF_FP64)
-        launch_batch_sweep_kernels<double>(b, s);
-    else
-        launch_batch_sweep_kernels<float>(b, s);
-    hipLaunchKernelGGL(finish_batch_kernel, dim3((unsigned)b->chains.size()),
-                       dim3(kFinishBlock), 0, s, b->fin_args,
-                       (flags & GMRF_WITH_HYPER) ? 1 : 0);
+    const int hyper = (flags & GMRF_WITH_HYPER) ? 1 : 0;
+    for (int i = 0; i < nsweeps; ++i) {
+        if (hyper && i % kUnitBatch == 0)
+            hipLaunchKernelGGL(unit_draw_batch_kernel, dim3((unsigned)b->chains.size()),
+                               dim3(kUnitThreads), 0, s, b->unit_args, i,
+                               std::min(kUnitBatch, nsweeps - i));
+        if (b->prec == GMRF_FP64)
+            launch_batch_sweep_kernels<double>(b, hyper, i, i > 0 ? 1 : 0, s);
+        else
+            launch_batch_sweep_kernels<float>(b, hyper, i, i > 0 ? 1 : 0, s);
+        if (b->n_csr > 0)       // general graphs: every sweep ends in its own commit
+            hipLaunchKernelGGL(commit_batch_kernel, dim3((unsigned)b->n_csr),
+                               dim3(kFinishThreads), 0, s, b->csr_commit, 0, 1, hyper);
+    }
+    if (b->n_lat > 0 && nsweeps > 0)   // lattices: the call's last sweep
+        hipLaunchKernelGGL(commit_batch_kernel, dim3((unsigned)b->n_lat), dim3(kFinishThreads), 0,
+                           s, b->lat_commit, nsweeps - 1, nsweeps, hyper);
 }
 
 // Destroy the cached captured sweeps of a chain.
@@ -2404,6 +2685,7 @@ static int chain_create_impl(const char *who, const gmrf_graph *g, const gmrf_mo
     st.tau = m->tau0;
     st.lam = m->lam0;
     st.beta0 = m->beta0;
+    st.unit_base = 1ull << 63;   // the ring holds no sweep's variates yet
     hipError_t e = hipMemcpyAsync(c->d_state, &st, sizeof st, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
         e = hipMemsetAsync(c->d_s1, 0, 8 * n, stream);
@@ -2490,8 +2772,7 @@ int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t strea
             if (is_persistent(c))
                 launch_persistent(c, a, nsweeps, c->capture_stream);
             else
-                for (int i = 0; i < nsweeps; ++i)
-                    launch_one_sweep(c, a, c->capture_stream);
+                launch_sweeps(c, a, nsweeps, c->capture_stream);
             hipGraph_t gdef = nullptr;
             const hipError_t le = hipGetLastError();
             GMRF_HIP(hipStreamEndCapture(c->capture_stream, &gdef));
@@ -2509,8 +2790,7 @@ int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t strea
         launch_persistent(c, a, nsweeps, stream);
         GMRF_HIP(hipGetLastError());
     } else {
-        for (int i = 0; i < nsweeps; ++i)
-            launch_one_sweep(c, a, stream);
+        launch_sweeps(c, a, nsweeps, stream);
         GMRF_HIP(hipGetLastError());
     }
     c->host_sweeps += (uint64_t)nsweeps;
@@ -2529,7 +2809,7 @@ int gmrf_sweep_timed(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t
         *span_ms = 0.0;
     const SweepArgs a = make_args(c, flags);
     // events are created before the first launch, so the span covers only
-    // device work: first sweep kernel's start to the end of the last finish
+    // device work: first sweep kernel's start to the end of the last commit
     std::vector<hipEvent_t> ev(2 * (size_t)nsweeps + 1, nullptr);
     int rc = GMRF_OK;
     for (auto &e : ev) {
@@ -2560,9 +2840,9 @@ int gmrf_sweep_timed(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t
     } else if (rc == GMRF_OK && nsweeps > 0) {
         hipError_t he = hipSuccess;
         for (int i = 0; i < nsweeps && he == hipSuccess; ++i) {
-            launch_sweep_kernels(c, a, stream, ev[2 * i], ev[2 * i + 1]);
-            if (!draws_in_sweep(c))
-                launch_finish(a, stream);
+            launch_units_ahead(c, a, i, nsweeps, stream);
+            launch_sweep_kernels(c, a, stream, i, ev[2 * i], ev[2 * i + 1]);
+            launch_commit_after(c, a, i, nsweeps, stream);
             he = hipGetLastError();
         }
         if (he == hipSuccess)
@@ -2853,7 +3133,7 @@ int gmrf_chain_autotune(gmrf_chain *c, int32_t reps, hipStream_t stream, int32_t
             continue;
         c->lat_tile = k;
         c->total_slots = lattice_blocks(c->g->h, k);
-        // Whole sweeps (sweep kernels and the finish, or the persistent
+        // Whole sweeps (the sweep kernels, or the persistent
         // kernel) in dry mode (dry_args), so the sweep kernels write only the
         // other state buffer, the partial slots and the statistics scratch
         // and the chain is unchanged; the persistent kernel runs an odd
@@ -2866,11 +3146,10 @@ int gmrf_chain_autotune(gmrf_chain *c, int32_t reps, hipStream_t stream, int32_t
             if (he == hipSuccess)
                 launch_persistent(c, a, odd, stream);
         } else {
-            for (int i = 0; i < 2; ++i)
-                launch_one_sweep(c, a, stream);
+            launch_sweeps(c, a, 2, stream);
             he = hipEventRecord(e0, stream);
-            for (int i = 0; i < reps && he == hipSuccess; ++i)
-                launch_one_sweep(c, a, stream);
+            if (he == hipSuccess)
+                launch_sweeps(c, a, reps, stream);
         }
         if (he == hipSuccess)
             he = hipEventRecord(e1, stream);
@@ -2995,8 +3274,9 @@ int gmrf_batch_autotune(gmrf_batch *b, int32_t reps, hipStream_t stream, int32_t
             if (r == 1)
                 he = hipEventRecord(e0, stream);
             if (he == hipSuccess) {
-                b->prec == GMRF_FP64 ? launch_batch_lattice_kernels<double>(b, stream)
-                                     : launch_batch_lattice_kernels<float>(b, stream);
+                // dry passes repeat relative sweep 0 (see launch_sweep_kernels)
+                b->prec == GMRF_FP64 ? launch_batch_lattice_kernels<double>(b, 1, 0, 0, stream)
+                                     : launch_batch_lattice_kernels<float>(b, 1, 0, 0, stream);
                 he = hipGetLastError();
             }
         }
@@ -3072,8 +3352,7 @@ int gmrf_batch_sweep(gmrf_batch *b, int32_t nsweeps, uint32_t flags, hipStream_t
             if (!b->capture_stream)
                 GMRF_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
             GMRF_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
-            for (int i = 0; i < nsweeps; ++i)
-                launch_batch_sweep(b, flags, b->capture_stream);
+            launch_batch_sweeps(b, nsweeps, flags, b->capture_stream);
             hipGraph_t gdef = nullptr;
             const hipError_t le = hipGetLastError();
             GMRF_HIP(hipStreamEndCapture(b->capture_stream, &gdef));
@@ -3089,8 +3368,7 @@ int gmrf_batch_sweep(gmrf_batch *b, int32_t nsweeps, uint32_t flags, hipStream_t
         }
         GMRF_HIP(hipGraphLaunch(it->second, stream));
     } else {
-        for (int i = 0; i < nsweeps; ++i)
-            launch_batch_sweep(b, flags, stream);
+        launch_batch_sweeps(b, nsweeps, flags, stream);
         GMRF_HIP(hipGetLastError());
     }
     for (gmrf_chain *c : b->chains)
