@@ -235,6 +235,26 @@ int gmrf_chain_create_binomial(const gmrf_graph *g, const gmrf_model *m, const d
  * draws: Sec. 3.1 conjugate conditionals. */
 int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream);
 
+/* gmrf_sweep for callers that cannot allocate device memory or must not have
+ * the library touch more of it than the chain (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same sweeps,
+ * bitwise the same results, but the kernels keep the sweep's scratch (the
+ * FP64 partial sums of the blocks and the ring of unit variates drawn ahead)
+ * in a fixed device array inside the library -- at most 8192 partial slots
+ * per sweep, about 400 KB, one copy per device held until the process ends
+ * -- instead of the chain's workspace.  The call allocates nothing.  The
+ * current device must be the chain's.  Every call on a device shares that
+ * device's array, so calls that overlap on one device (other streams, other
+ * host threads) race and must be serialised by the caller; the array keeps
+ * the last call's contents, and nothing in it needs to start at zero.
+ * flags: GMRF_WITH_HYPER only (no GMRF_CAPTURE; the caller may capture the
+ * launches itself).  Errors: GMRF_E_INVALID_ARG (NULL chain, bad flags, a
+ * binomial chain, whose Polya-Gamma scratch lives in its workspace, or a
+ * chain whose sweep needs more than 8192 partial slots: lattices up to
+ * 8192 tiles of the chain's shape, general graphs up to 8192 blocks of 256
+ * sites over all colors), GMRF_E_DEVICE. */
+int gmrf_sweep_static(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream);
+
 /* Profiling form of gmrf_sweep (plain launches, no capture): the same sweeps,
  * with a pair of HIP events that the dispatches themselves record at the
  * start and the end of the sweep kernels of every sweep (the lattice kernel,

@@ -40,6 +40,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <unordered_set>
 #include <utility>
@@ -1554,6 +1555,14 @@ __global__ void stats_kernel(const double *s1, const double *s2, const int *orig
     }
 }
 
+// Scratch of gmrf_sweep_static: the two partial buffers (kStaticSlots slots of
+// kPartials doubles each) and the unit-variate ring, in place of the ones in
+// the chain's workspace.  One copy per device, for the life of the process.
+constexpr int kStaticSlots = 8192;
+constexpr size_t kStaticPartialBytes = 2 * (size_t)kStaticSlots * kPartials * sizeof(double);
+constexpr size_t kScratchBytes = kStaticPartialBytes + 2 * (size_t)kUnitRows * sizeof(UnitDraws);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 } // namespace gmrf
 
 // ---------------------------------------------------------------------------
@@ -2447,6 +2456,30 @@ void launch_batch_sweeps(const gmrf_batch *b, int nsweeps, unsigned flags, hipSt
                            s, b->lat_commit, nsweeps - 1, nsweeps, hyper);
 }
 
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current (every device holds its own copy at its
+// own address; in host code the array's name is only a host-side stand-in).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch[kMaxDevices] = {};
+
+int scratch_address(unsigned char **out)
+{
+    int dev = -1;
+    GMRF_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(GMRF_E_DEVICE, "sweep_static: device index " + std::to_string(dev) +
+                                       " beyond the library's table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        GMRF_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch[dev] = static_cast<unsigned char *>(ptr);
+    }
+    *out = g_scratch[dev];
+    return GMRF_OK;
+}
+
 // Destroy the cached captured sweeps of a chain.
 void drop_graphs(gmrf_chain *c)
 {
@@ -2793,6 +2826,39 @@ int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t strea
         launch_sweeps(c, a, nsweeps, stream);
         GMRF_HIP(hipGetLastError());
     }
+    c->host_sweeps += (uint64_t)nsweeps;
+    return GMRF_OK;
+}
+
+int gmrf_sweep_static(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream)
+{
+    clear_error();
+    if (!c || nsweeps < 0 || (flags & ~GMRF_WITH_HYPER))
+        return fail(GMRF_E_INVALID_ARG, "sweep_static: NULL chain, negative count or a flag "
+                                        "other than GMRF_WITH_HYPER");
+    if (c->binomial)
+        return fail(GMRF_E_INVALID_ARG, "sweep_static: binomial chains keep their Polya-Gamma "
+                                        "scratch in the chain workspace; use gmrf_sweep");
+    if (c->total_slots > kStaticSlots)
+        return fail(GMRF_E_INVALID_ARG,
+                    "sweep_static: the chain needs " + std::to_string(c->total_slots) +
+                        " partial slots per sweep, more than the static scratch's " +
+                        std::to_string(kStaticSlots) + " (use gmrf_sweep)");
+    if (nsweeps == 0)
+        return GMRF_OK;
+    unsigned char *base = nullptr;
+    const int rc = scratch_address(&base);
+    if (rc != GMRF_OK)
+        return rc;
+    SweepArgs a = make_args(c, flags);
+    a.partials = reinterpret_cast<double *>(base);
+    a.slot_stride = kStaticSlots;
+    a.units = reinterpret_cast<UnitDraws *>(base + kStaticPartialBytes);
+    if (is_persistent(c))
+        launch_persistent(c, a, nsweeps, stream);
+    else
+        launch_sweeps(c, a, nsweeps, stream);
+    GMRF_HIP(hipGetLastError());
     c->host_sweeps += (uint64_t)nsweeps;
     return GMRF_OK;
 }

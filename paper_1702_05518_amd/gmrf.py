@@ -71,6 +71,7 @@ _SIGS = {
                                     C.c_uint64, C.c_uint32, C.c_void_p, C.c_size_t, C.c_void_p,
                                     C.POINTER(C.c_void_p)], C.c_int),
     "gmrf_sweep": ([C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p], C.c_int),
+    "gmrf_sweep_static": ([C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p], C.c_int),
     "gmrf_sweep_timed": ([C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p,
                           C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "gmrf_hyper_update": ([C.c_void_p, C.c_void_p], C.c_int),
@@ -295,6 +296,13 @@ class Chain:
     def sweep(self, nsweeps: int = 1, hyper: bool = True, capture: bool = False, stream=None):
         flags = (WITH_HYPER if hyper else 0) | (CAPTURE if capture else 0)
         _check(lib().gmrf_sweep(self.handle, int(nsweeps), flags, _stream_handle(stream)))
+        return self
+
+    def sweep_static(self, nsweeps: int = 1, hyper: bool = True, stream=None):
+        """gmrf_sweep_static: the same sweeps with the library's fixed device
+        scratch instead of the workspace's (allocates nothing)."""
+        _check(lib().gmrf_sweep_static(self.handle, int(nsweeps), WITH_HYPER if hyper else 0,
+                                       _stream_handle(stream)))
         return self
 
     def sweep_timed(self, nsweeps: int, hyper: bool = True, stream=None, span=False):
