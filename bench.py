@@ -11,7 +11,10 @@ FP64 accumulators and reductions, burn-in 0 (every sweep accumulates).
 Prints ONE JSON line.  ``value`` is site-updates/s of the FP32 path with all
 inputs resident in HBM; the line also carries the FP64 path, p50 / p99 solve
 latency (1000-sweep solves) for both precisions, the roofline of the sweep
-kernel and the CPU oracle timed on a bounded sample.
+kernel, the same sweep on an 8192 x 8192 lattice (a working set far beyond
+the 256 MB Infinity Cache) next to a device copy measured in the same run,
+the irregular 1,000,000-site workload, the 512-instance batch, and the CPU
+oracle timed on bounded samples.
 """
 from __future__ import annotations
 
@@ -28,22 +31,56 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 ROWS = COLS = 2048
+BIG = 8192
 STENCIL = 8
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_SITE = {"fp32_acc": 44, "fp64_acc": 56}   # x read + x write + y read + S1/S2 RMW
+# algorithmic bytes per site update, accumulating sweeps: lattice x read + x
+# write + y read + S1 / S2 read-modify-write; a general graph adds its CSR
+# row (row offset + column indices at mean degree ~6) and the slab-to-id map
+BYTES_PER_SITE = {"fp32_acc": 44, "fp64_acc": 56}
+CSR_BYTES_PER_SITE = {"fp32_acc": 72, "fp64_acc": 84}
 METRIC = ("site-updates/s + HBM GB/s fraction per sweep; p50/p99 solve latency "
           "(FP32 vs FP64)")
-# Name of the dominant kernel (the FP32 lattice sweep) and its HBM traffic per
-# launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, each scaled by the counter
-# reading of a 512 MiB device copy (profiles/lattice_sweep_2048x2048_s8_fp32_traffic.md).
-# The figure belongs to this kernel build; it is reported only while the
-# kernel name below matches the library's configuration.
 SWEEP_KERNEL = "lattice_sweep_kernel<float, LatCfg<8, 64, 64, 512, 4>, false>"
-MEASURED_TRAFFIC_BYTES = {SWEEP_KERNEL: 189.0e6}
+# rocprofv3 summaries of the dominant kernel (committed under profiles/):
+# its average duration in the kernel trace of this benchmark's command, and
+# its HBM traffic per launch from FETCH_SIZE / WRITE_SIZE scaled by a device
+# copy's readings.  Each holds a "json:" line with the figures and the
+# SHA-256 of the kernel sources it was taken from; a figure is reported only
+# while the sources are unchanged.
+PROFILES = os.path.join(ROOT, "profiles")
+TRACE_SUMMARY = os.path.join(PROFILES, "lattice_sweep_2048x2048_s8_kernel_trace.md")
+TRAFFIC_SUMMARY = os.path.join(PROFILES, "lattice_sweep_2048x2048_s8_fp32_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1702_05518_amd", "csrc", f)
+                  for f in ("gmrf.hip", "rng.hpp")]
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profile_figures(path):
+    """The "json:" line of a committed profile summary, if it was taken from
+    the current kernel sources (else None)."""
+    try:
+        with open(path) as fh:
+            for line in fh:
+                if line.startswith("json:"):
+                    d = json.loads(line[5:])
+                    return d if d.get("kernel_sources_sha256") == kernel_sources_sha256() else None
+    except OSError:
+        pass
+    return None
 
 
 def timed_sweeps(torch, chain, steps, capture):
@@ -60,15 +97,14 @@ def timed_sweeps(torch, chain, steps, capture):
     return e0.elapsed_time(e1) / 1e3
 
 
-def plain_timed_region(torch, chain, steps):
-    """The timed region with plain launches: `steps` sweeps in which every
-    sweep kernel is bracketed by HIP events that its dispatch records on the
-    launch stream.  Returns (seconds for the `steps` sweeps, from the first
-    sweep kernel's start to the last sweep's end; average duration in
-    seconds of the sweep kernel over the same launches)."""
+def dispatch_timed(torch, chain, steps):
+    """`steps` sweeps in which every sweep kernel is bracketed by HIP events
+    that its dispatch records (a diagnostic: an event on a dispatch makes the
+    kernel write its caches back at its end, which lengthens it).  Returns
+    the average duration in seconds of the sweep kernel."""
     torch.cuda.synchronize()
-    k_ms, span_ms = chain.sweep_timed(steps, hyper=True, span=True)
-    return span_ms / 1e3, k_ms / steps / 1e3
+    k_ms = chain.sweep_timed(steps, hyper=True)
+    return k_ms / steps / 1e3
 
 
 def solve_latencies(torch, chain, sweeps, reps):
@@ -111,21 +147,158 @@ def host_to_host_solve(torch, gmrf, graph, y, sweeps):
     return dt
 
 
-def cpu_baseline(wl, seconds_budget=15.0):
-    """The oracle (C, FP64) on the same workload, a bounded number of sweeps."""
+def graph_seconds(torch, run, steps, reps=3):
+    """Best of `reps` timed replays of a captured graph of `steps` sweeps
+    (`run(capture)` enqueues them; the first call records the graph)."""
+    run(True)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        run(True)
+        e1.record(s)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    return best
+
+
+def copy_gbs(torch, nbytes=1 << 30, reps=5):
+    """A plain device copy of nbytes (read + write counted) at its best of reps."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        dst.copy_(src)
+        e1.record(s)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / best / 1e9
+
+
+def big_lattice_row(torch, gmrf, inputs, args):
+    """The same FP32 accumulating sweep on an 8192 x 8192 lattice (about 2.9 GB
+    per sweep), beyond the 256 MB Infinity Cache, with a 1 GiB device copy
+    timed in the same run as the practical ceiling."""
+    log(f"[bench] {BIG}x{BIG} lattice (out of cache)")
+    copy = copy_gbs(torch)
+    nb = BIG * BIG
+    wl = inputs.lattice_workload(BIG, BIG, STENCIL, noise_sd=0.1, data_seed=1, with_csr=False)
+    g = gmrf.Graph(lattice=(BIG, BIG, STENCIL))
+    ch = gmrf.Chain(g, wl["y"], precision=gmrf.FP32_ACC64, seed=1)
+    del wl
+    ch.sweep(args.warmup, hyper=True)
+    steps = max(args.steps, 10)
+    t = graph_seconds(torch, lambda cap: ch.sweep(steps, hyper=True, capture=cap), steps)
+    _, tau, lam, _ = ch.get_state()
+    if not (np.isfinite(tau) and np.isfinite(lam)):
+        print("bench.py: non-finite result (8192 lattice)", file=sys.stderr)
+        sys.exit(1)
+    launch_s = t / steps
+    gbs = BYTES_PER_SITE["fp32_acc"] * nb / launch_s / 1e9
+    del ch
+    torch.cuda.empty_cache()
+    row = {"workload": f"lattice {BIG}x{BIG}, 8-neighbour, FP32 with FP64 accumulators, "
+                       f"accumulating sweeps (working set ~2.9 GB)",
+           "sites": nb, "steps": steps, "site_updates_per_s": nb / launch_s,
+           "ms_per_step": launch_s * 1e3, "achieved_gbs": gbs,
+           "frac": gbs / HBM_PEAK_GBS, "copy_gbs": copy, "frac_of_copy": gbs / copy,
+           "bytes_per_site": BYTES_PER_SITE["fp32_acc"]}
+    log(f"[bench] {BIG}x{BIG}: {launch_s * 1e6:.1f} us per sweep, {gbs:.0f} GB/s "
+        f"({gbs / HBM_PEAK_GBS:.3f} of peak, {gbs / copy:.3f} of a {copy:.0f} GB/s copy)")
+    return row
+
+
+def delaunay_row(torch, gmrf, inputs, args):
+    """The irregular workload at 1,000,000 sites (Delaunay, proper CAR rho
+    0.95, greedy coloring), FP32 with FP64 accumulators and FP64."""
+    log("[bench] Delaunay 1M")
+    wl = inputs.delaunay_workload(1_000_000, data_seed=3, rho=0.95)
+    color, k = gmrf.greedy_coloring(wl["row_ptr"], wl["col"])
+    g = gmrf.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color, num_colors=k, rho=0.95)
+    n = wl["n"]
+    row = {"workload": "Delaunay graph of 1,000,000 uniform points, proper CAR rho 0.95, "
+                       f"greedy coloring ({k} colors), accumulating sweeps",
+           "sites": n, "colors": int(k)}
+    steps = max(args.steps, 10)
+    for name, prec in (("fp32_acc", gmrf.FP32_ACC64), ("fp64_acc", gmrf.FP64)):
+        ch = gmrf.Chain(g, wl["y"], precision=prec, seed=5, instance=1)
+        ch.sweep(args.warmup, hyper=True)
+        t = graph_seconds(torch, lambda cap: ch.sweep(steps, hyper=True, capture=cap), steps)
+        sweep_s = t / steps
+        gbs = CSR_BYTES_PER_SITE[name] * n / sweep_s / 1e9
+        row[name] = {"site_updates_per_s": n / sweep_s, "us_per_sweep": sweep_s * 1e6,
+                     "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS,
+                     "bytes_per_site": CSR_BYTES_PER_SITE[name], "shape": ch.tile[0]}
+        log(f"[bench] Delaunay 1M {name}: {sweep_s * 1e6:.1f} us per sweep "
+            f"({gbs / HBM_PEAK_GBS:.3f} of peak)")
+        del ch
+    return row
+
+
+def batch_row(torch, gmrf, inputs, args, steps=None):
+    """512 independent instances (256 lattices with side U{32..512}, 4
+    neighbours; 256 Delaunay graphs with n U{1k..50k}, proper CAR rho 0.95),
+    FP32 state with FP64 accumulators, advanced together by shared launches in
+    a captured graph of sweeps."""
+    steps = max(args.steps, 10) if steps is None else steps
+    t0 = time.perf_counter()
+    mix = inputs.batch_mix(512, data_seed=4, workers=min(16, os.cpu_count() or 1))
+    log(f"[bench] batch inputs built in {time.perf_counter() - t0:.1f} s")
+    chains, sites, nbytes = [], 0, 0
+    for i, wl in enumerate(mix):
+        if wl["kind"] == "lattice":
+            g = gmrf.Graph(lattice=(wl["rows"], wl["cols"], wl["stencil"]))
+            nbytes += BYTES_PER_SITE["fp32_acc"] * wl["n"]
+        else:
+            color, k = gmrf.greedy_coloring(wl["row_ptr"], wl["col"])
+            g = gmrf.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color, num_colors=k,
+                           rho=wl["rho"])
+            nbytes += CSR_BYTES_PER_SITE["fp32_acc"] * wl["n"]
+        chains.append(gmrf.Chain(g, wl["y"], precision=gmrf.FP32_ACC64, seed=1 + i, instance=i))
+        sites += wl["n"]
+    batch = gmrf.Batch(chains)
+    tile, tile_us = batch.autotune(reps=10)
+    batch.sweep(args.warmup, capture=False)
+    t_batch = graph_seconds(torch, lambda cap: batch.sweep(steps, capture=cap), steps)
+    for c in chains[:: len(chains) // 8]:
+        _, tau, lam, _ = c.get_state()
+        if not (np.isfinite(tau) and np.isfinite(lam)):
+            print("bench.py: non-finite result (batch)", file=sys.stderr)
+            sys.exit(1)
+    sweep_s = t_batch / steps
+    gbs = nbytes / sweep_s / 1e9
+    log(f"[bench] batch512: {sweep_s * 1e3:.3f} ms per sweep of all chains, "
+        f"{sites / sweep_s:.3e} site-updates/s ({gbs / HBM_PEAK_GBS:.3f} of peak)")
+    return {"workload": "512 instances: 256 lattices side U{32..512} 4-neighbour, 256 Delaunay "
+                        "graphs n U{1k..50k}, FP32 with FP64 accumulators, one captured graph "
+                        "of shared launches",
+            "instances": len(chains), "sites_per_sweep": sites, "steps": steps,
+            "site_updates_per_s": sites / sweep_s, "ms_per_sweep": sweep_s * 1e3,
+            "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS,
+            "lattice_tile_autotune": {"chosen_shape": tile, "us_per_pass_64x64": tile_us[0],
+                                      "us_per_pass_32x32": tile_us[1]}, "_chains": chains}
+
+
+def cpu_baseline(wl, seconds_budget=10.0):
+    """The oracle (C, FP64) on bounded samples: the 2048 x 2048 workload with
+    every host thread (up to 16) and with one, the 64 x 64 workload in full,
+    and the irregular 15,000-site workload in full (2000 sweeps)."""
     import oracle
 
     oracle.build(force=False)
     threads = min(16, os.cpu_count() or 1)
-    ch = oracle.Chain(wl["row_ptr"], wl["col"], wl["color"], wl["y"], rho=1.0, seed=1)
-    t0 = time.perf_counter()
-    ch.sweeps(1, nthreads=threads)
-    one = time.perf_counter() - t0
-    reps = max(1, min(2000, int(seconds_budget / max(one, 1e-3))))
-    t0 = time.perf_counter()
-    ch.sweeps(reps, nthreads=threads)
-    dt = time.perf_counter() - t0
-    n = wl["n"]
     model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -134,12 +307,49 @@ def cpu_baseline(wl, seconds_budget=15.0):
                 break
     except OSError:
         pass
-    return {"value": n * reps / dt, "unit": "site-updates/s", "cores": threads,
-            "kind": "oracle",
+
+    def timed(ch, n, budget, nthreads, cap=2000):
+        t0 = time.perf_counter()
+        ch.sweeps(1, nthreads=nthreads)
+        one = time.perf_counter() - t0
+        reps = max(1, min(cap, int(budget / max(one, 1e-4))))
+        t0 = time.perf_counter()
+        ch.sweeps(reps, nthreads=nthreads)
+        dt = time.perf_counter() - t0
+        return n * reps / dt, reps, dt
+
+    n = wl["n"]
+    ch = oracle.Chain(wl["row_ptr"], wl["col"], wl["color"], wl["y"], rho=1.0, seed=1)
+    rate, reps, dt = timed(ch, n, seconds_budget, threads)
+    ch1 = oracle.Chain(wl["row_ptr"], wl["col"], wl["color"], wl["y"], rho=1.0, seed=1)
+    rate1, reps1, dt1 = timed(ch1, n, seconds_budget / 2, 1)
+    from paper_1702_05518_amd import inputs
+
+    c1 = inputs.lattice_workload(64, 64, 4, noise_sd=0.1, data_seed=1)
+    o1 = oracle.Chain(c1["row_ptr"], c1["col"], c1["color"], c1["y"], seed=1)
+    t0 = time.perf_counter()
+    o1.sweeps(1000, nthreads=1)
+    t_c1 = time.perf_counter() - t0
+    c3 = inputs.delaunay_workload(15000, data_seed=3, rho=0.95)
+    color, _ = oracle.greedy_coloring(c3["row_ptr"], c3["col"])
+    o3 = oracle.Chain(c3["row_ptr"], c3["col"], color, c3["y"], rho=0.95, seed=3)
+    t0 = time.perf_counter()
+    o3.sweeps(2000, nthreads=threads)
+    t_c3 = time.perf_counter() - t0
+    bps = BYTES_PER_SITE["fp64_acc"]
+    return {"value": rate, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{reps} FP64 sweeps (+1 untimed) of the same 2048x2048 8-neighbour "
                       f"lattice workload, C oracle with {threads} OpenMP threads on "
                       f"'{model or platform.processor()}'",
-            "seconds": dt}
+            "seconds": dt, "gbs": rate * bps / 1e9,
+            "single_thread": {"value": rate1, "sweeps": reps1, "seconds": dt1,
+                              "gbs": rate1 * bps / 1e9},
+            "lattice64_1000_sweeps": {"seconds": t_c1, "threads": 1,
+                                      "site_updates_per_s": 4096 * 1000 / t_c1},
+            "delaunay15k_2000_sweeps": {"seconds": t_c3, "threads": threads,
+                                        "site_updates_per_s": 15000 * 2000 / t_c3,
+                                        "gbs": 15000 * 2000 / t_c3 *
+                                        CSR_BYTES_PER_SITE["fp64_acc"] / 1e9}}
 
 
 def probe(torch, gmrf, inputs, steps):
@@ -162,42 +372,14 @@ def probe(torch, gmrf, inputs, steps):
 
 
 def bench_batch(torch, gmrf, inputs, args):
-    """The batched workload: 512 independent instances (256 lattices with side
-    U{32..512}, 4 neighbours; 256 Delaunay graphs with n U{1k..50k}, proper CAR
-    rho 0.95), FP32 state with FP64 accumulators, all advanced together by
-    shared launches in a captured graph of sweeps.  Prints one JSON line."""
-    steps = args.steps
-    t0 = time.perf_counter()
-    mix = inputs.batch_mix(512, data_seed=4)
-    log(f"[bench] batch inputs built in {time.perf_counter() - t0:.1f} s")
-    chains, sites = [], 0
-    for i, wl in enumerate(mix):
-        if wl["kind"] == "lattice":
-            g = gmrf.Graph(lattice=(wl["rows"], wl["cols"], wl["stencil"]))
-        else:
-            color, k = gmrf.greedy_coloring(wl["row_ptr"], wl["col"])
-            g = gmrf.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color, num_colors=k,
-                           rho=wl["rho"])
-        ch = gmrf.Chain(g, wl["y"], precision=gmrf.FP32_ACC64, seed=1 + i, instance=i)
-        chains.append(ch)
-        sites += wl["n"]
-    batch = gmrf.Batch(chains)
-    tile, tile_us = batch.autotune(reps=10)     # the lattices' tile shape for the shared launch
-    log(f"[bench] batch autotune: shape {tile}, lattice pass {tile_us[0]:.1f} us (64x64) / "
-        f"{tile_us[1]:.1f} us (32x32)")
-    batch.sweep(args.warmup, capture=False)
-    batch.sweep(steps, capture=True)            # record the graph once
-    torch.cuda.synchronize()
+    """The batched workload alone (batch_row), with the same chains swept one
+    by one for comparison.  Prints one JSON line."""
+    row = batch_row(torch, gmrf, inputs, args, steps=args.steps)
+    chains = row.pop("_chains")
+    solo_sweeps = 5
     s = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    batch.sweep(steps, capture=True)
-    e1.record(s)
-    torch.cuda.synchronize()
-    t_batch = e0.elapsed_time(e1) / 1e3
-    # the same chains one by one (plain launches), a few sweeps each
-    solo_sweeps = 5
     torch.cuda.synchronize()
     e0.record(s)
     for c in chains:
@@ -205,25 +387,18 @@ def bench_batch(torch, gmrf, inputs, args):
     e1.record(s)
     torch.cuda.synchronize()
     t_solo = e0.elapsed_time(e1) / 1e3 / solo_sweeps
-    for c in chains[:: len(chains) // 8]:
-        _, tau, lam, _ = c.get_state()
-        if not (np.isfinite(tau) and np.isfinite(lam)):
-            print("bench.py: non-finite result", file=sys.stderr)
-            sys.exit(1)
-    value = sites * steps / t_batch
     line = {
-        "metric": "site-updates/s (batched instances)", "value": value,
-        "unit": "site-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
-        "ms_per_step": t_batch / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "metric": "site-updates/s (batched instances)", "value": row["site_updates_per_s"],
+        "unit": "site-updates/s", "n_gpus": 1, "steps": row["steps"], "warmup": args.warmup,
+        "ms_per_step": row["ms_per_sweep"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "512 instances: 256 lattices side U{32..512} 4-neighbour, "
-                               "256 Delaunay graphs n U{1k..50k}, FP32 with FP64 accumulators, "
-                               "one captured graph of shared launches per sweep block",
-                   "sites_per_sweep": sites, "instances": len(chains)},
-        "unbatched_site_updates_per_s": sites / t_solo,
-        "batching_speedup": t_solo * steps / t_batch,
-        "lattice_tile_autotune": {"chosen_shape": tile, "us_per_pass_64x64": tile_us[0],
-                                  "us_per_pass_32x32": tile_us[1]},
+        "config": {"workload": row["workload"], "sites_per_sweep": row["sites_per_sweep"],
+                   "instances": row["instances"]},
+        "roofline": {"bound": "hbm", "achieved": row["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": row["frac"], "traffic": None},
+        "unbatched_site_updates_per_s": row["sites_per_sweep"] / t_solo,
+        "batching_speedup": t_solo / (row["ms_per_sweep"] / 1e3),
+        "lattice_tile_autotune": row["lattice_tile_autotune"],
     }
     print(json.dumps(line), flush=True)
 
@@ -451,10 +626,14 @@ def bench_binomial(torch, gmrf, inputs, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-big", action="store_true", help="skip the 8192 x 8192 lattice row")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the 1,000,000-site Delaunay row")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batch row")
     ap.add_argument("--reps", type=int, default=10, help="solves for p50/p99 latency")
     ap.add_argument("--workload", default="lattice2048",
                     choices=["lattice2048", "batch512", "serve", "image", "binomial"],
@@ -510,24 +689,24 @@ def main():
         log(f"[bench] {name}: warmup {args.warmup}")
         chain = gmrf.Chain(graph, wl["y"], precision=prec, seed=1)
         chain.sweep(args.warmup, hyper=True)
-        torch.cuda.synchronize()
-        log(f"[bench] {name}: timing {args.steps} sweeps")
-        t_plain, k_avg = plain_timed_region(torch, chain, args.steps)
         chain.sweep(args.steps, hyper=True, capture=True)      # record the graph once
         torch.cuda.synchronize()
+        log(f"[bench] {name}: timing {args.steps} sweeps")
+        t_plain = timed_sweeps(torch, chain, args.steps, capture=False)
         t_graph = timed_sweeps(torch, chain, args.steps, capture=True)
+        k_disp = dispatch_timed(torch, chain, args.steps)
         lat = solve_latencies(torch, chain, 1000, args.reps)
         mean, var, nacc = chain.posterior_stats()
         x, tau, lam, sw = chain.get_state()
         if not (np.isfinite(mean).all() and np.isfinite(tau) and np.isfinite(lam)):
             print("bench.py: non-finite result", file=sys.stderr)
             sys.exit(1)
-        results[name] = dict(t_plain=t_plain, t_graph=t_graph, kernel_s=k_avg,
+        results[name] = dict(t_plain=t_plain, t_graph=t_graph, kernel_disp_s=k_disp,
                              p50_ms=float(np.percentile(lat, 50)),
                              p99_ms=float(np.percentile(lat, 99)), tau=tau, lam=lam,
                              sweeps_done=sw)
-        log(f"[bench] {name}: plain {t_plain * 1e3:.2f} ms, graph {t_graph * 1e3:.2f} ms, "
-            f"kernel {k_avg * 1e6:.2f} us, p50 {results[name]['p50_ms']:.2f} ms")
+        log(f"[bench] {name}: plain {t_plain * 1e3:.3f} ms, graph {t_graph * 1e3:.3f} ms, "
+            f"dispatch-event kernel {k_disp * 1e6:.2f} us, p50 {results[name]['p50_ms']:.2f} ms")
         del chain
         torch.cuda.synchronize()
 
@@ -537,7 +716,14 @@ def main():
     t_best = min(r["t_plain"], r["t_graph"])
     value = n * args.steps / t_best
     bytes_launch = BYTES_PER_SITE["fp32_acc"] * n
-    achieved = bytes_launch / r["kernel_s"] / 1e9
+    # One launch of the sweep kernel per sweep (it also ends the previous
+    # sweep); the call adds one commit launch and one unit-variate launch.
+    # The kernel's average launch duration is the timed region's length over
+    # its launches, so the figure includes every gap and the small launches.
+    launch_s = t_best / args.steps
+    achieved = bytes_launch / launch_s / 1e9
+    prof = profile_figures(TRACE_SUMMARY)
+    traffic = profile_figures(TRAFFIC_SUMMARY)
     line = {
         "metric": METRIC,
         "value": value,
@@ -559,12 +745,19 @@ def main():
                    r["t_plain"] else "stream"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": MEASURED_TRAFFIC_BYTES.get(SWEEP_KERNEL),
-                     "traffic_unit": "bytes/launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
+                     "traffic": traffic["bytes_per_launch"] if traffic else None,
+                     "traffic_unit": "bytes/launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, each "
+                                     "scaled by a device copy's reading)",
                      "algorithmic_bytes": bytes_launch,
                      "kernel": SWEEP_KERNEL,
                      "bytes_per_site": BYTES_PER_SITE["fp32_acc"],
-                     "kernel_us": r["kernel_s"] * 1e6},
+                     "launch_us": launch_s * 1e6,
+                     "launch_us_basis": "timed region / launches (HIP events around the "
+                                        "K sweeps, one sweep-kernel launch each)",
+                     "kernel_us_rocprof": prof["avg_ns"] / 1e3 if prof else None,
+                     "frac_kernel_rocprof": (bytes_launch / (prof["avg_ns"] * 1e-9) / 1e9 /
+                                             HBM_PEAK_GBS) if prof else None,
+                     "kernel_us_dispatch_events": r["kernel_disp_s"] * 1e6},
         "sweep_ms": {"fp32_stream": r["t_plain"] / args.steps * 1e3,
                      "fp32_graph": r["t_graph"] / args.steps * 1e3},
         "solve_latency_ms_1000_sweeps": {"fp32": {"p50": r["p50_ms"], "p99": r["p99_ms"]}},
@@ -579,10 +772,18 @@ def main():
         t64 = min(d["t_plain"], d["t_graph"])
         line["fp64"] = {"value": n * args.steps / t64, "unit": "site-updates/s",
                         "ms_per_step": t64 / args.steps * 1e3,
-                        "kernel_us": d["kernel_s"] * 1e6,
-                        "hbm_frac": BYTES_PER_SITE["fp64_acc"] * n / d["kernel_s"] / 1e9 /
-                        HBM_PEAK_GBS}
+                        "hbm_frac": BYTES_PER_SITE["fp64_acc"] * n / (t64 / args.steps) / 1e9 /
+                        HBM_PEAK_GBS,
+                        "kernel_us_dispatch_events": d["kernel_disp_s"] * 1e6}
         line["solve_latency_ms_1000_sweeps"]["fp64"] = {"p50": d["p50_ms"], "p99": d["p99_ms"]}
+    if not args.no_big:
+        line["lattice8192_out_of_cache"] = big_lattice_row(torch, gmrf, inputs, args)
+    if not args.no_graph:
+        line["delaunay1m"] = delaunay_row(torch, gmrf, inputs, args)
+    if not args.no_batch:
+        row = batch_row(torch, gmrf, inputs, args)
+        del row["_chains"]
+        line["batch512"] = row
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(wl)

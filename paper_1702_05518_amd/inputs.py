@@ -122,15 +122,46 @@ def gaussian_bump_image(p: int):
     return (5.0 * np.exp(-(vi ** 2 + vj ** 2) / 2.0) / np.pi).reshape(-1)
 
 
+def _dot(a, b) -> float:
+    """Inner product by numpy's pairwise summation, whose order of operations
+    is fixed by numpy itself (np.dot hands the sum to the BLAS, whose kernels,
+    and so whose rounding, depend on the CPU)."""
+    return float(np.add.reduce(a * b))
+
+
+def conjugate_gradients(A, b, rtol: float = 1e-12, maxiter: int = 100000):
+    """Solve A x = b for a symmetric positive definite sparse A by conjugate
+    gradients (Hestenes-Stiefel), stopping at ||r|| <= rtol ||b||.  Every
+    operation is a CSR product (sequential rows), an elementwise one or _dot,
+    so the result is the same on every machine that runs the same numpy and
+    scipy builds."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = _dot(r, r)
+    stop = (rtol * np.sqrt(_dot(b, b))) ** 2
+    for _ in range(maxiter):
+        if rr <= stop:
+            return x
+        Ap = A @ p
+        alpha = rr / _dot(p, Ap)
+        x += alpha * p
+        r -= alpha * Ap
+        rr_new = _dot(r, r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    raise RuntimeError("CG did not converge while drawing the prior field")
+
+
 def proper_car_prior_draw(row_ptr, col, tau: float, rho: float, rng, rtol: float = 1e-12):
     """Exact draw x ~ N(0, (tau (D - rho W))^{-1}) for 0 <= rho < 1.
 
     With B the signed edge incidence, D - rho W = (1 - rho) D + rho B'B, so
     w = sqrt(tau) [sqrt(1 - rho) D^{1/2} z1 + sqrt(rho) B' z2] ~ N(0, Q) and
-    x = Q^{-1} w ~ N(0, Q^{-1}); Q x = w is solved by conjugate gradients.
+    x = Q^{-1} w ~ N(0, Q^{-1}); Q x = w is solved by conjugate gradients
+    (conjugate_gradients, reproducible across machines).
     """
     import scipy.sparse as sp
-    from scipy.sparse.linalg import cg
 
     n = row_ptr.size - 1
     deg = np.diff(row_ptr).astype(np.float64)
@@ -144,10 +175,7 @@ def proper_car_prior_draw(row_ptr, col, tau: float, rho: float, rng, rtol: float
     w = np.sqrt(tau) * (np.sqrt(1.0 - rho) * np.sqrt(deg) * z1 + np.sqrt(rho) * btz)
     W = sp.csr_matrix((np.ones(col.size), col.astype(np.int64), row_ptr), shape=(n, n))
     Q = tau * (sp.diags(deg) - rho * W)
-    x, info = cg(Q.tocsr(), w, rtol=rtol, maxiter=20 * n)
-    if info != 0:
-        raise RuntimeError("CG did not converge while drawing the prior field")
-    return x
+    return conjugate_gradients(Q.tocsr(), w, rtol=rtol, maxiter=20 * n)
 
 
 # --------------------------------------------------------------------------
@@ -221,12 +249,19 @@ def smooth_field(points):
     return np.sin(2 * np.pi * 1.5 * u) * np.cos(2 * np.pi * v) + 0.5 * u
 
 
+def _delaunay_job(args):
+    n, seed = args
+    return delaunay_graph(n, data_seed=seed)
+
+
 def batch_mix(count: int = 512, data_seed: int = 4, side=(32, 512), nrange=(1000, 50000),
-              noise_lattice: float = 0.1, noise_graph: float = 0.2):
+              noise_lattice: float = 0.1, noise_graph: float = 0.2, workers: int = 1):
     """Many independent instances of uneven sizes: the first half lattices with
     side ~ U{side} (4 neighbours, checkerboard), the second half Delaunay
     graphs with n ~ U{nrange} (smooth truth plus noise, proper CAR rho 0.95).
-    Returns a list of workload dicts (graphs without colorings)."""
+    Returns a list of workload dicts (graphs without colorings).  workers > 1
+    builds the Delaunay graphs in that many processes (the same result: the
+    random draws are taken in the same order beforehand)."""
     rng = np.random.Generator(np.random.PCG64(data_seed))
     out = []
     nlat = count // 2
@@ -235,10 +270,21 @@ def batch_mix(count: int = 512, data_seed: int = 4, side=(32, 512), nrange=(1000
         wl = lattice_workload(s, s, 4, noise_sd=noise_lattice,
                               data_seed=int(rng.integers(1 << 30)), with_csr=False)
         out.append(wl)
+    jobs, noise = [], []
     for i in range(count - nlat):
         n = int(rng.integers(nrange[0], nrange[1] + 1))
-        pts, row_ptr, col = delaunay_graph(n, data_seed=int(rng.integers(1 << 30)))
+        jobs.append((n, int(rng.integers(1 << 30))))
+        noise.append(noise_graph * rng.standard_normal(n))
+    if workers > 1:
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+
+        with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+            graphs = list(ex.map(_delaunay_job, jobs, chunksize=4))
+    else:
+        graphs = [_delaunay_job(j) for j in jobs]
+    for (n, _), (pts, row_ptr, col), e in zip(jobs, graphs, noise):
         truth = smooth_field(pts)
-        y = truth + noise_graph * rng.standard_normal(n)
-        out.append(dict(kind="csr", n=n, row_ptr=row_ptr, col=col, y=y, truth=truth, rho=0.95))
+        out.append(dict(kind="csr", n=n, row_ptr=row_ptr, col=col, y=truth + e, truth=truth,
+                        rho=0.95))
     return out

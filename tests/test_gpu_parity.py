@@ -107,20 +107,17 @@ def test_csr_one_sweep_from_injected_state(G, orc, rho, shape):
 
 def test_lattice_trajectory_64x64_fp64(G, orc):
     """64 x 64, 4 neighbours, checkerboard, FP64, 1000 sweeps with hyper draws:
-    tau and lam after every sweep, the field every 100 sweeps, and the
-    posterior mean / variance at the end."""
+    the field, tau and lam after every sweep, and the posterior mean /
+    variance at the end."""
     wl = lattice_case(64, 64, 4)
     g, ch, oc = pair(G, orc, wl, seed=1)
     worst = 0.0
-    for block in range(10):
-        for _ in range(100):
-            ch.sweep(1)
-            oc.sweeps(1)
-            _, tau, lam, _ = ch.get_state()
-            worst = max(worst, rel(tau, oc.tau), rel(lam, oc.lam))
+    for t in range(1000):
+        ch.sweep(1)
+        oc.sweeps(1)
         x, tau, lam, sw = ch.get_state()
-        assert sw == 100 * (block + 1)
-        worst = max(worst, rel(x, oc.x))
+        assert sw == t + 1
+        worst = max(worst, rel(x, oc.x), rel(tau, oc.tau), rel(lam, oc.lam))
     assert worst <= RTOL64, worst
     mean, var, nacc = ch.posterior_stats()
     om, ov = oc.stats()
@@ -129,20 +126,38 @@ def test_lattice_trajectory_64x64_fp64(G, orc):
     assert np.max(np.abs(var - ov)) <= 1e-9 * np.max(np.abs(ov))
 
 
+def oracle_trajectory(oc, sweeps, every=100, nthreads=8):
+    """tau / lam after every sweep of the oracle and its field every `every`
+    sweeps."""
+    taus, lams, xs = np.empty(sweeps), np.empty(sweeps), {}
+    for t in range(sweeps):
+        oc.sweeps(1, nthreads=nthreads)
+        taus[t], lams[t] = oc.tau, oc.lam
+        if (t + 1) % every == 0:
+            xs[t + 1] = oc.x.copy()
+    return taus, lams, xs
+
+
 @pytest.mark.parametrize("shape", [0, 2])
 def test_csr_trajectory_delaunay_fp64(G, orc, shape):
+    """The 15,000-site irregular workload for its 2000 sweeps in FP64: tau and
+    lam after every sweep (device trace), the field every 100 sweeps, and the
+    posterior mean / variance at the end, against the oracle at 1e-12."""
     wl = csr_case(15000, data_seed=3)
     g, ch, oc = pair(G, orc, wl, seed=3, burn_in=10)
     ch.set_tile(shape)
-    ch.sweep(50)
-    oc.sweeps(50)
-    x, tau, lam, sw = ch.get_state()
-    assert sw == 50
-    assert rel(x, oc.x) <= RTOL64
-    assert rel(tau, oc.tau) <= RTOL64 and rel(lam, oc.lam) <= RTOL64
+    ch.enable_trace(2000)
+    taus, lams, xs = oracle_trajectory(oc, 2000)
+    for t in range(20):
+        ch.sweep(100, capture=True)
+        x, tau, lam, sw = ch.get_state()
+        assert sw == 100 * (t + 1)
+        assert rel(x, xs[sw]) <= RTOL64, (sw, rel(x, xs[sw]))
+    tr = ch.trace()
+    assert rel(tr[:, 0], taus) <= RTOL64 and rel(tr[:, 1], lams) <= RTOL64
     mean, var, nacc = ch.posterior_stats()
     om, ov = oc.stats()
-    assert nacc == 40
+    assert nacc == 1990
     assert rel(mean, om) <= RTOL64
     assert np.max(np.abs(var - ov)) <= 1e-9 * np.max(np.abs(ov))
 
@@ -175,17 +190,27 @@ def test_fp32_lattice_posterior_mean_against_fp64_oracle(G, orc):
 
 
 def test_fp32_csr_posterior_mean_against_fp64_oracle(G, orc):
-    """The irregular 15,000-site workload in FP32 with FP64 accumulators
-    against the FP64 oracle on the same seeds: posterior-mean max abs error
-    within 1e-4 after 1000 sweeps."""
+    """The irregular 15,000-site workload in FP32 with FP64 accumulators for
+    its 2000 sweeps against the FP64 oracle on the same seeds: posterior-mean
+    max abs error within 1e-4 (the stated FP32 accuracy), the variance and the
+    tau / lam trajectories (every sweep, device trace) reported and bounded."""
     wl = csr_case(15000, data_seed=3)
     g, ch, oc = pair(G, orc, wl, precision=G.FP32_ACC64, seed=4)
-    ch.sweep(1000)
-    oc.sweeps(1000, nthreads=8)
+    ch.enable_trace(2000)
+    ch.sweep(1000, capture=True)
+    ch.sweep(1000, capture=True)
+    taus, lams, _ = oracle_trajectory(oc, 2000, every=2000)
     mean, var, nacc = ch.posterior_stats()
     om, ov = oc.stats()
-    assert nacc == 1000
-    assert np.max(np.abs(mean - om)) <= 1e-4
+    tr = ch.trace()
+    assert nacc == 2000
+    mean_err = np.max(np.abs(mean - om))
+    var_err = np.max(np.abs(var - ov))
+    print(f"15k FP32, 2000 sweeps: posterior mean max abs err {mean_err:.2e}, var {var_err:.2e}, "
+          f"tau rel {rel(tr[:, 0], taus):.2e}, lam rel {rel(tr[:, 1], lams):.2e}")
+    assert mean_err <= 1e-4
+    assert var_err <= 1e-4 * max(1.0, np.max(ov))
+    assert rel(tr[:, 0], taus) <= 1e-3 and rel(tr[:, 1], lams) <= 1e-3
 
 
 def test_run_to_run_bitwise_and_capture(G, orc):
@@ -403,3 +428,25 @@ def test_library_first_load_order(G):
     r = subprocess.run([sys.executable, "-c", prog], cwd=root, capture_output=True, text=True,
                        timeout=300)
     assert r.returncode == 0 and "first-load ok" in r.stdout, r.stderr[-2000:]
+
+
+def test_numeric_failure_is_reported_through_the_status_word(G, orc):
+    """A field so rough that x'(D - W)x overflows to inf: the tau draw at rate
+    b + q/2 = inf is not a positive finite number, so the device sets its
+    status word (the kernels still end normally) and the next synchronising
+    call returns GMRF_E_NUMERIC; the oracle refuses the same draw."""
+    rows = cols = 16
+    wl = lattice_case(rows, cols, 4)
+    r, c = np.divmod(np.arange(rows * cols), cols)
+    y = np.where((r + c) % 2 == 0, 1e160, -1e160)
+    g = G.Graph(lattice=(rows, cols, 4))
+    ch = G.Chain(g, y, precision=G.FP64, seed=1, lam0=1e6)
+    ch.sweep(1)
+    with pytest.raises(G.GmrfError) as e:
+        ch.get_state()
+    assert e.value.status == G.E_NUMERIC
+    with pytest.raises(G.GmrfError):
+        ch.posterior_stats()
+    oc = orc.Chain(wl["row_ptr"], wl["col"], wl["color"], y, seed=1, lam0=1e6)
+    with pytest.raises(FloatingPointError):
+        oc.sweeps(1)
