@@ -43,6 +43,7 @@
 #include <mutex>
 #include <string>
 #include <unordered_set>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -1260,6 +1261,281 @@ __global__ __launch_bounds__(kThreads) void csr_batch_kernel(const CsrJob<Real> 
 }
 
 // ---------------------------------------------------------------------------
+// general graphs, one launch per sweep: chunks with recomputed closures
+// ---------------------------------------------------------------------------
+// The general-graph counterpart of the fused lattice sweep.  Block b takes
+// chunk b (graph_host.cpp, build_chunks).  It stages in LDS the values from
+// before the sweep of the chunk's staged sites (R_b, then H_b), and y, the
+// original id and the local neighbour list of every R_b site, with every
+// load issued up front.  Then for each color c in order it computes every
+// R_b site of color c from its neighbours in LDS -- lower-colored ones
+// already hold their new values (they are in R_b and were computed in an
+// earlier color), higher-colored ones still the old ones -- exactly the
+// update the color passes make, with the same random numbers (keyed by
+// site) and the same summation order (ascending original neighbour id), so a
+// recomputed site is bitwise its owner's value; the color phases touch only
+// LDS.  Last, the sites the chunk owns (one consecutive run of slab
+// positions per color) add their q / sse terms (each edge once, at its
+// higher-colored endpoint, whose lower-colored neighbours are the staged
+// slots below its color's first slot), update the accumulators and are
+// written back, their loads batched.  The state is ping-ponged between two
+// buffers (sweep t reads buffer t & 1), so no block sees another's new values
+// through memory.
+template <typename Real> struct FusedArgs {
+    const int *ch_loc, *ch_row, *ch_adj, *ch_meta;   // per-chunk bases and metadata
+    const int *loc_site;                             // slab position of each staged site
+    const unsigned short *loc_row, *loc_adj;         // local adjacency of the R sites
+    const int *orig;                                 // slab position -> original id
+    Real *x0, *x1;                                   // ping-pong state, slab order
+    const Real *y;                                   // y (slab order)
+    int k;                                           // colors
+    int max_local, max_r, max_adj;                   // sizes of the LDS image's parts
+};
+
+constexpr int kFusedGather = 8;                      // neighbour indices read per batch
+constexpr int kQtabDeg = 64;                         // degrees with tabulated scales
+constexpr int kFusedCH = 4;                          // owned sites per thread per batch
+
+__host__ __device__ constexpr size_t lds_align16(size_t b) { return (b + 15) / 16 * 16; }
+
+// Neighbour sum of a staged site in row order (local neighbours e0 .. e1 - 1).
+template <typename Real>
+__device__ __forceinline__ Real fused_nbr_sum(const Real *xs, const unsigned short *adj, int e0,
+                                              int e1)
+{
+    Real sum = (Real)0;
+    for (int eb = e0; eb < e1; eb += kFusedGather) {
+        int l[kFusedGather];
+#pragma unroll
+        for (int q = 0; q < kFusedGather; ++q)
+            l[q] = adj[min(eb + q, e1 - 1)];
+#pragma unroll
+        for (int q = 0; q < kFusedGather; ++q)
+            if (eb + q < e1)
+                sum += xs[l[q]];
+    }
+    return sum;
+}
+
+// Chunk b of a chain (rel, fold: as for the lattice sweep kernel).
+template <typename Real, bool B0>
+__device__ __forceinline__ void csr_fused_block(const FusedArgs<Real> &fa, const SweepArgs &a,
+                                                const int b, const int rel, const int fold)
+{
+    extern __shared__ __align__(16) unsigned char fused_lds[];
+    Real *xs = reinterpret_cast<Real *>(fused_lds);
+    size_t off = lds_align16(sizeof(Real) * (size_t)fa.max_local);
+    Real *ys = reinterpret_cast<Real *>(fused_lds + off);
+    off += lds_align16(sizeof(Real) * (size_t)fa.max_r);
+    unsigned *ids = reinterpret_cast<unsigned *>(fused_lds + off);
+    off += lds_align16(sizeof(unsigned) * (size_t)fa.max_r);
+    unsigned short *lrow = reinterpret_cast<unsigned short *>(fused_lds + off);
+    off += lds_align16(sizeof(unsigned short) * (size_t)(fa.max_r + 1));
+    unsigned short *ladj = reinterpret_cast<unsigned short *>(fused_lds + off);
+    __shared__ Real qtab[2 * kQtabDeg];
+
+    const unsigned t = (unsigned)(a.st->sweep + (unsigned long long)rel);
+    const Real *src = (t & 1u) ? fa.x1 : fa.x0;
+    Real *dst = (t & 1u) ? fa.x0 : fa.x1;
+    HyperIn hin;
+    if (fold) {      // end the previous sweep of the call (as the lattice kernel does)
+        SweepArgs ea = a;
+        ea.dry = a.dry || b != 0;
+        hin = end_sweep_block<kThreads>(ea, partials_of(a, rel - 1), t - 1u,
+                                        inputs_of(a, rel - 1), false);
+        if (!ea.dry && threadIdx.x == 0) {
+            double *const h = a.st->hs[rel & 1];
+            h[0] = hin.tau;
+            h[1] = hin.lam;
+            h[2] = hin.beta0;
+        }
+    } else {
+        hin = inputs_of(a, 0);
+    }
+    const Real tau = (Real)hin.tau, lam = (Real)hin.lam, tau_rho = (Real)(hin.tau * a.rho);
+    const double beta0 = B0 ? hin.beta0 : 0.0;
+    const bool acc = (long long)t >= a.burn_in;
+    const int k = fa.k;
+    const int *meta = fa.ch_meta + (size_t)b * (3 * k + 1);
+    const int loc0 = fa.ch_loc[b], nloc = fa.ch_loc[b + 1] - loc0;
+    const int nr = meta[k];
+    const int row0 = fa.ch_row[b], adj0 = fa.ch_adj[b], nadj = fa.ch_adj[b + 1] - adj0;
+    const int *site = fa.loc_site + loc0;
+
+    // the chunk's LDS image, kFusedCH entries per thread in flight at a time:
+    // staged values, y and ids by slab position, then the rows and
+    // neighbours (each chunk's start on a 16-byte boundary, padded to whole
+    // 16-byte vectors) as 16-byte vectors
+    for (int s0 = (int)threadIdx.x; s0 < nloc; s0 += kFusedCH * kThreads) {
+        int p[kFusedCH];
+        Real xv[kFusedCH], yv[kFusedCH];
+        unsigned iv[kFusedCH];
+#pragma unroll
+        for (int j = 0; j < kFusedCH; ++j) {
+            const int s = s0 + j * kThreads;
+            p[j] = site[min(s, nloc - 1)];
+        }
+#pragma unroll
+        for (int j = 0; j < kFusedCH; ++j) {
+            xv[j] = src[p[j]];
+            yv[j] = fa.y[p[j]];
+            iv[j] = (unsigned)fa.orig[p[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < kFusedCH; ++j) {
+            const int s = s0 + j * kThreads;
+            if (s < nloc)
+                xs[s] = xv[j];
+            if (s < nr) {
+                ys[s] = yv[j];
+                ids[s] = iv[j];
+            }
+        }
+    }
+    {
+        const int nrow4 = (nr + 1 + 7) / 8, nadj4 = nadj / 8;
+        const uint4 *grow = reinterpret_cast<const uint4 *>(fa.loc_row + row0);
+        const uint4 *gadj = reinterpret_cast<const uint4 *>(fa.loc_adj + adj0);
+        uint4 *srow = reinterpret_cast<uint4 *>(lrow);
+        uint4 *sadj = reinterpret_cast<uint4 *>(ladj);
+        for (int i0 = (int)threadIdx.x; i0 < nrow4 + nadj4; i0 += kFusedCH * kThreads) {
+            uint4 v[kFusedCH];
+#pragma unroll
+            for (int j = 0; j < kFusedCH; ++j) {
+                const int i = min(i0 + j * kThreads, nrow4 + nadj4 - 1);
+                v[j] = i < nrow4 ? grow[i] : gadj[i - nrow4];
+            }
+#pragma unroll
+            for (int j = 0; j < kFusedCH; ++j) {
+                const int i = i0 + j * kThreads;
+                if (i < nrow4)
+                    srow[i] = v[j];
+                else if (i < nrow4 + nadj4)
+                    sadj[i - nrow4] = v[j];
+            }
+        }
+    }
+    if (threadIdx.x < kQtabDeg)
+        site_scales<Real>(tau, lam, (int)threadIdx.x, qtab[threadIdx.x],
+                          qtab[kQtabDeg + threadIdx.x]);
+    lds_barrier();
+
+    // the color phases, in LDS
+    for (int c = 0; c < k; ++c) {
+        const int lo = meta[c], hi = meta[c + 1];
+        for (int s = lo + (int)threadIdx.x; s < hi; s += kThreads) {
+            const int e0 = lrow[s], e1 = lrow[s + 1], deg = e1 - e0;
+            const Real sum = fused_nbr_sum<Real>(xs, ladj, e0, e1);
+            const Real z = site_normal<Real>(draw_words(a.seed, ids[s], t, a.instance, 0u));
+            Real inv_q, isd;
+            if (deg < kQtabDeg) {
+                inv_q = qtab[deg];
+                isd = qtab[kQtabDeg + deg];
+            } else {
+                site_scales<Real>(tau, lam, deg, inv_q, isd);
+            }
+            const Real yeff = B0 ? ys[s] - (Real)beta0 : ys[s];
+            xs[s] = site_draw<Real>(yeff, sum, z, lam, tau_rho, inv_q, isd);
+        }
+        lds_barrier();
+    }
+
+    // the owned sites: q / sse terms, accumulators, write-back
+    int n_own = 0;
+    for (int c = 0; c < k; ++c)
+        n_own += meta[k + 1 + c];
+    Red rd;
+    for (int o0 = (int)threadIdx.x; o0 < n_own; o0 += kFusedCH * kThreads) {
+        int sl[kFusedCH], pos[kFusedCH], lo[kFusedCH];
+        double s1v[kFusedCH], s2v[kFusedCH];
+#pragma unroll
+        for (int j = 0; j < kFusedCH; ++j) {
+            const int o = o0 + j * kThreads;
+            sl[j] = -1;
+            pos[j] = 0;
+            lo[j] = 0;
+            s1v[j] = s2v[j] = 0.0;
+            if (o < n_own) {
+                int c = 0, before = 0;
+                while (o >= before + meta[k + 1 + c]) {
+                    before += meta[k + 1 + c];
+                    ++c;
+                }
+                lo[j] = meta[c];
+                sl[j] = meta[c] + (o - before);
+                pos[j] = meta[2 * k + 1 + c] + (o - before);
+                if (acc) {
+                    s1v[j] = a.s1[pos[j]];
+                    s2v[j] = a.s2[pos[j]];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kFusedCH; ++j) {
+            if (sl[j] < 0)
+                continue;
+            const int s = sl[j];
+            const Real xn = xs[s];
+            const double xd = (double)xn;
+            const int e0 = lrow[s], e1 = lrow[s + 1];
+            double edge = 0.0;
+            for (int e = e0; e < e1; ++e) {
+                const int l = ladj[e];
+                if (l < lo[j]) {                // lower color: new value, this sweep
+                    const double d = xd - (double)xs[l];
+                    edge += d * d;
+                }
+            }
+            rd.q += (1.0 - a.rho) * (double)(e1 - e0) * xd * xd + a.rho * edge;
+            const double rr = B0 ? (double)ys[s] - beta0 - xd : (double)ys[s] - xd;
+            rd.sse += rr * rr;
+            if (B0)
+                rd.rsum += rr;
+            if (acc) {
+                const double phi = B0 ? xd + beta0 : xd;
+                a.s1[pos[j]] = s1v[j] + phi;
+                a.s2[pos[j]] = s2v[j] + phi * phi;
+            }
+            dst[pos[j]] = xn;
+        }
+    }
+    write_partials<kThreads>(partials_of(a, rel), rd, b);
+}
+
+// Block b takes chunk xcd_tile(b): each XCD sweeps a contiguous run of
+// chunks, which the locality order makes a compact region.
+template <typename Real, bool B0>
+__global__ __launch_bounds__(kThreads) void csr_fused_kernel(FusedArgs<Real> fa, SweepArgs a,
+                                                             int rel, int fold)
+{
+    csr_fused_block<Real, B0>(fa, a, xcd_tile((int)blockIdx.x, (int)gridDim.x), rel, fold);
+}
+
+// Batched form: one entry per block over the chunks of every chunked
+// general-graph chain of a batch (chain by chain, so each XCD takes a run of
+// chains); with_hyper, rel and fold as for lattice_batch_kernel.
+template <typename Real> struct FusedJob {
+    FusedArgs<Real> fa;
+    SweepArgs a;
+};
+struct FusedBlock {
+    int job, chunk;
+};
+
+template <typename Real, bool B0>
+__global__ __launch_bounds__(kThreads) void csr_fused_batch_kernel(const FusedJob<Real> *jobs,
+                                                                   const FusedBlock *blocks,
+                                                                   int with_hyper, int rel,
+                                                                   int fold)
+{
+    const FusedBlock bk = blocks[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
+    const FusedJob<Real> &j = jobs[bk.job];
+    SweepArgs a = j.a;
+    a.with_hyper = with_hyper;
+    csr_fused_block<Real, B0>(j.fa, a, bk.chunk, rel, fold);
+}
+
+// ---------------------------------------------------------------------------
 // general graphs whose field fits in LDS: one block, the field in LDS
 // ---------------------------------------------------------------------------
 // The field of a small general graph (n values within kCsrLdsBytes) stays in
@@ -1385,7 +1661,7 @@ __global__ __launch_bounds__(kCsrPersistThreads) void csr_persistent_kernel(CsrA
     }
     for (int p = (int)threadIdx.x; p < n; p += NT)
         ca.x[p] = xs[p];
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && !a.dry) {
         a.st->n_acc = nacc;
         a.st->sweep = (unsigned long long)v.t;
     }
@@ -1573,6 +1849,10 @@ using namespace gmrf;
 struct gmrf_graph {
     HostGraph h;
     int *d_row_ptr = nullptr, *d_col = nullptr, *d_orig = nullptr;
+    // chunks of the one-launch sweep (shape 1), when h.chunks_ok
+    int *d_ch_loc = nullptr, *d_ch_row = nullptr, *d_ch_adj = nullptr, *d_ch_meta = nullptr;
+    int *d_loc_site = nullptr;
+    unsigned short *d_loc_row = nullptr, *d_loc_adj = nullptr;
 };
 
 struct gmrf_chain {
@@ -1620,6 +1900,10 @@ struct gmrf_batch {
     int lat_tile_count[8] = {};
     void *csr_jobs[2] = {};
     CsrBlock *csr_blocks[2] = {};
+    void *fused_jobs[2] = {};                     // chunked general-graph chains (shape 1)
+    FusedBlock *fused_blocks[2] = {};
+    int fused_count[2] = {};
+    int fused_lds = 0;
     std::vector<int> csr_color_off[2];            // per color index: first block
     SweepArgs *unit_args = nullptr;               // per chain, for the unit-variate launches
     SweepArgs *csr_commit = nullptr;              // general-graph chains: commit every sweep
@@ -1645,6 +1929,7 @@ struct TileShape {
 };
 constexpr TileShape kTiles[GMRF_NUM_TILES] = {{64, 64, 512}, {32, 32, 256}, {64, 64, 512}};
 constexpr int kPersistent = 2;
+constexpr int kFused = 1;          // general graphs: the chunked one-launch sweep
 template <int ST, int K>
 using LatticeCfg = LatCfg<ST, kTiles[K].th, kTiles[K].tw, kTiles[K].nt, 4>;
 static_assert(GMRF_NUM_TILES == 3, "tile dispatch below covers three shapes");
@@ -1722,17 +2007,19 @@ size_t chain_layout(const gmrf_graph *g, gmrf_precision p, char *base, gmrf_chai
             pass_blocks.push_back(nb);
             slots += nb;
         }
-        reserve = slots;
+        reserve = std::max(slots, g->h.chunks_ok ? g->h.nchunks : 0);
+        if (c && c->lat_tile == kFused)
+            slots = g->h.nchunks;
     }
     char *st = take(sizeof(DevState));
     char *x0 = take(rs * n);
-    char *x1 = is_lattice(g) ? take(rs * n) : nullptr;
+    char *x1 = take(rs * n);
     char *y = take(rs * n);
     char *s1 = take(8 * n);
     char *s2 = take(8 * n);
-    // lattice sweeps alternate two partial buffers (a sweep kernel ends the
-    // previous sweep from its buffer while writing its own)
-    char *part = take(8 * kPartials * (size_t)std::max(reserve, 1) * (is_lattice(g) ? 2 : 1));
+    // one-launch sweeps alternate two partial buffers (a sweep kernel ends
+    // the previous sweep from its buffer while writing its own)
+    char *part = take(8 * kPartials * (size_t)std::max(reserve, 1) * 2);
     char *units = take(sizeof(UnitDraws) * 2 * kUnitRows);
     char *stats = take(16 * n);
     char *trials = binomial ? take(4 * n) : nullptr;
@@ -1803,7 +2090,7 @@ SweepArgs make_args(const gmrf_chain *c, unsigned flags)
     a.n_sites = (double)c->g->h.n;
     a.units = c->d_units;
     a.slot_stride = c->slot_stride;
-    a.deferred = is_lattice(c->g) ? 1 : 0;
+    a.deferred = is_lattice(c->g) || c->lat_tile == kFused ? 1 : 0;
     return a;
 }
 
@@ -1938,19 +2225,42 @@ bool csr_persist_fits(const HostGraph &h, gmrf_precision p)
     return slots <= kCsrPersistSlots;
 }
 
+// Can the chunked one-launch sweep take this chain?  (Its graph's chunks fit
+// the LDS and index limits; not the binomial model, whose Polya-Gamma draws
+// run per site before the color passes.)
+bool csr_fused_fits(const HostGraph &h, gmrf_precision p, bool binomial)
+{
+    return h.stencil == 0 && h.chunks_ok && !binomial &&
+           chunk_lds_bytes(h.max_local, h.max_r, h.max_adj, (int64_t)real_size(p)) <=
+               kFusedLaunchLds;
+}
+
 // Default shape of a general-graph chain: the one block while it covers
 // every color's slab in at most two rounds of its threads (measured on
 // MI355X with Delaunay graphs: one block 15.2 against 24.3 us per sweep at
 // 500 sites, 29.4 against 35.4 at 4,000, slower from ~5,000 sites on, where
-// its serial rounds outlast the k + 1 launches), else the color passes.
-int csr_default_shape(const HostGraph &h, gmrf_precision p)
+// its serial rounds outlast the k + 1 launches), else the chunked one-launch
+// sweep where it fits, else the color passes.
+int csr_default_shape(const HostGraph &h, gmrf_precision p, bool binomial)
 {
-    if (!csr_persist_fits(h, p))
-        return 0;
-    for (int32_t col = 0; col < h.k; ++col)
+    bool small = csr_persist_fits(h, p);
+    for (int32_t col = 0; small && col < h.k; ++col)
         if (h.slab_offsets[col + 1] - h.slab_offsets[col] > 2 * kCsrPersistThreads)
-            return 0;
-    return kPersistent;
+            small = false;
+    if (small)
+        return kPersistent;
+    return csr_fused_fits(h, p, binomial) ? kFused : 0;
+}
+
+// Partial slots of one sweep of a general-graph chain in shape k.
+int csr_slots(const gmrf_chain *c, int k)
+{
+    if (k == kFused)
+        return c->g->h.nchunks;
+    int slots = 0;
+    for (int nb : c->pass_blocks)
+        slots += nb;
+    return slots;
 }
 
 // Do all the sweeps of a call run in one launch?  (Shape 2, except for the
@@ -1968,11 +2278,60 @@ int elementwise_blocks(int64_t n)
 }
 
 
+// Arguments of the chunked one-launch sweep; x0 / x1 are the chain's two
+// state buffers (swap: the other way round, for timing runs whose current
+// buffer is not the one the sweep parity reads).
+template <typename Real> FusedArgs<Real> fused_args(const gmrf_chain *c, bool swap = false)
+{
+    const gmrf_graph *g = c->g;
+    FusedArgs<Real> fa;
+    fa.ch_loc = g->d_ch_loc;
+    fa.ch_row = g->d_ch_row;
+    fa.ch_adj = g->d_ch_adj;
+    fa.ch_meta = g->d_ch_meta;
+    fa.loc_site = g->d_loc_site;
+    fa.loc_row = g->d_loc_row;
+    fa.loc_adj = g->d_loc_adj;
+    fa.orig = g->d_orig;
+    fa.x0 = static_cast<Real *>(c->d_x[swap ? 1 : 0]);
+    fa.x1 = static_cast<Real *>(c->d_x[swap ? 0 : 1]);
+    fa.y = static_cast<const Real *>(c->d_y);
+    fa.k = g->h.k;
+    fa.max_local = g->h.max_local;
+    fa.max_r = g->h.max_r;
+    fa.max_adj = g->h.max_adj;
+    return fa;
+}
+
+// LDS of the chunked sweep for a graph's chunks in precision Real.
+template <typename Real> size_t fused_lds_bytes(const HostGraph &h)
+{
+    return (size_t)chunk_lds_bytes(h.max_local, h.max_r, h.max_adj, sizeof(Real));
+}
+
 template <typename Real>
-void launch_csr(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent_t ev0,
-                hipEvent_t ev1)
+void launch_fused(const gmrf_chain *c, const FusedArgs<Real> &fa, const SweepArgs &a,
+                  hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int rel, int fold)
 {
     const HostGraph &h = c->g->h;
+    auto kern = c->model.intercept ? csr_fused_kernel<Real, true> : csr_fused_kernel<Real, false>;
+    const size_t lds = fused_lds_bytes<Real>(h);
+    if (ev0 || ev1)
+        hipExtLaunchKernelGGL(kern, dim3(h.nchunks), dim3(kThreads), lds, s, ev0, ev1, 0, fa, a,
+                              rel, fold);
+    else
+        hipLaunchKernelGGL(kern, dim3(h.nchunks), dim3(kThreads), lds, s, fa, a, rel, fold);
+}
+
+template <typename Real>
+void launch_csr(const gmrf_chain *c, const SweepArgs &a, hipStream_t s, hipEvent_t ev0,
+                hipEvent_t ev1, int rel = 0, int fold = 0)
+{
+    const HostGraph &h = c->g->h;
+    if (c->lat_tile == kFused) {
+        launch_fused<Real>(c, fused_args<Real>(c), a, s, ev0, ev1, rel, fold);
+        return;
+    }
     const CsrArgs<Real> ca = csr_args<Real>(c);
     int slot = 0, last = -1;
     for (int32_t col = 0; col < h.k; ++col)
@@ -2045,8 +2404,8 @@ void launch_sweep_kernels(const gmrf_chain *c, const SweepArgs &a, hipStream_t s
     const bool f64 = c->prec == GMRF_FP64;
     if (a.dry)
         rel = 0;
+    const int fold = rel > 0 ? 1 : 0;
     if (is_lattice(c->g)) {
-        const int fold = rel > 0 ? 1 : 0;
         if (c->g->h.stencil == 4)
             f64 ? launch_lattice<double, 4>(c, a, s, ev0, ev1, rel, fold)
                 : launch_lattice<float, 4>(c, a, s, ev0, ev1, rel, fold);
@@ -2054,7 +2413,8 @@ void launch_sweep_kernels(const gmrf_chain *c, const SweepArgs &a, hipStream_t s
             f64 ? launch_lattice<double, 8>(c, a, s, ev0, ev1, rel, fold)
                 : launch_lattice<float, 8>(c, a, s, ev0, ev1, rel, fold);
     } else {
-        f64 ? launch_csr<double>(c, a, s, ev0, ev1) : launch_csr<float>(c, a, s, ev0, ev1);
+        f64 ? launch_csr<double>(c, a, s, ev0, ev1, rel, fold)
+            : launch_csr<float>(c, a, s, ev0, ev1, rel, fold);
     }
 }
 
@@ -2076,14 +2436,15 @@ void launch_units_ahead(const gmrf_chain *c, const SweepArgs &a, int i, int nswe
 }
 
 // After relative sweep i of a call of nsweeps: its commit where one is due
-// (a general graph after every sweep, a lattice after the call's last; none
-// where the kernels draw themselves, or for timing runs of a lattice).
+// (one-launch sweeps -- lattices and chunked general graphs -- after the
+// call's last sweep; color passes after every sweep; none where the kernels
+// draw themselves, or for timing runs of one-launch sweeps).
 void launch_commit_after(const gmrf_chain *c, const SweepArgs &a, int i, int nsweeps,
                          hipStream_t s)
 {
     if (draws_in_sweep(c))
         return;
-    if (!is_lattice(c->g))
+    if (!a.deferred)
         launch_commit(a, 0, 1, s);
     else if (i == nsweeps - 1 && !a.dry)
         launch_commit(a, i, nsweeps, s);
@@ -2114,10 +2475,12 @@ int check_status(const DevState &st)
     return GMRF_OK;
 }
 
-// Current state buffer: lattice chains ping-pong on the sweep parity.
+// Current state buffer: lattice chains and chunked general-graph chains
+// (shape 1) ping-pong on the sweep parity; the other general-graph shapes
+// update buffer 0 in place.
 void *current_x(const gmrf_chain *c, uint64_t sweep)
 {
-    return is_lattice(c->g) ? c->d_x[sweep & 1u] : c->d_x[0];
+    return is_lattice(c->g) || c->lat_tile == kFused ? c->d_x[sweep & 1u] : c->d_x[0];
 }
 
 // x in layout order (Real) <-> original-order doubles.
@@ -2213,8 +2576,11 @@ struct BatchImage {
     size_t off_lat_jobs[8] = {}, off_lat_tiles[8] = {};
     size_t off_csr_jobs[2] = {}, off_csr_blocks[2] = {}, off_units = 0;
     size_t off_csr_commit = 0, off_lat_commit = 0;
+    size_t off_fused_jobs[2] = {}, off_fused_blocks[2] = {};
     int n_csr = 0, n_lat = 0;
     int lat_tile_count[8] = {};
+    int fused_count[2] = {};
+    int fused_lds = 0;                            // bytes of LDS of the batched chunked launch
     std::vector<int> csr_color_off[2];
 };
 
@@ -2238,7 +2604,9 @@ void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im, int 
     std::vector<LatTile> ltiles[8];
     std::vector<CsrJob<Real>> cjobs[2];
     std::vector<std::vector<CsrBlock>> cblocks[2];   // per color index
-    std::vector<SweepArgs> units, csr_commit, lat_commit;
+    std::vector<SweepArgs> units, csr_commit, lat_commit;   // lat_commit: every one-launch chain
+    std::vector<FusedJob<Real>> fjobs[2];
+    std::vector<FusedBlock> fblocks[2];
     for (const gmrf_chain *c : cs) {
         const SweepArgs a = make_args(c, 0u);
         units.push_back(a);
@@ -2255,6 +2623,13 @@ void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im, int 
             lat_commit.push_back(la_args);
             for (int t = 0; t < tiles; ++t)
                 ltiles[w].push_back(LatTile{job, t});
+        } else if (c->lat_tile == kFused) {
+            const int job = (int)fjobs[g].size();
+            fjobs[g].push_back(FusedJob<Real>{fused_args<Real>(c), a});
+            lat_commit.push_back(a);
+            for (int b = 0; b < h.nchunks; ++b)
+                fblocks[g].push_back(FusedBlock{job, b});
+            im.fused_lds = std::max(im.fused_lds, (int)fused_lds_bytes<Real>(h));
         } else {
             const int job = (int)cjobs[g].size();
             cjobs[g].push_back(CsrJob<Real>{csr_args<Real>(c), a});
@@ -2285,6 +2660,9 @@ void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im, int 
         }
         im.off_csr_jobs[g] = append(im.bytes, cjobs[g]);
         im.off_csr_blocks[g] = append(im.bytes, flat);
+        im.off_fused_jobs[g] = append(im.bytes, fjobs[g]);
+        im.off_fused_blocks[g] = append(im.bytes, fblocks[g]);
+        im.fused_count[g] = (int)fblocks[g].size();
     }
     im.off_units = append(im.bytes, units);
     im.off_csr_commit = append(im.bytes, csr_commit);
@@ -2368,6 +2746,9 @@ int install_image(gmrf_batch *b, const BatchImage &im, hipStream_t stream)
     for (int g = 0; g < 2; ++g) {
         b->csr_jobs[g] = b->ws + im.off_csr_jobs[g];
         b->csr_blocks[g] = reinterpret_cast<CsrBlock *>(b->ws + im.off_csr_blocks[g]);
+        b->fused_jobs[g] = b->ws + im.off_fused_jobs[g];
+        b->fused_blocks[g] = reinterpret_cast<FusedBlock *>(b->ws + im.off_fused_blocks[g]);
+        b->fused_count[g] = im.fused_count[g];
         b->csr_color_off[g] = im.csr_color_off[g];
     }
     b->unit_args = reinterpret_cast<SweepArgs *>(b->ws + im.off_units);
@@ -2375,6 +2756,7 @@ int install_image(gmrf_batch *b, const BatchImage &im, hipStream_t stream)
     b->lat_commit = reinterpret_cast<SweepArgs *>(b->ws + im.off_lat_commit);
     b->n_csr = im.n_csr;
     b->n_lat = im.n_lat;
+    b->fused_lds = im.fused_lds;
     return GMRF_OK;
 }
 
@@ -2419,10 +2801,23 @@ void launch_batch_lattice_kernels(const gmrf_batch *b, int hyper, int rel, int f
     launch_lattice_group<Real, 8, true, 1>(b, hyper, rel, fold, s);
 }
 
+template <typename Real, bool B0>
+void launch_fused_group(const gmrf_batch *b, int hyper, int rel, int fold, hipStream_t s)
+{
+    const int g = B0 ? 1 : 0;
+    if (b->fused_count[g] > 0)
+        hipLaunchKernelGGL((csr_fused_batch_kernel<Real, B0>), dim3(b->fused_count[g]),
+                           dim3(kThreads), (size_t)b->fused_lds, s,
+                           static_cast<const FusedJob<Real> *>(b->fused_jobs[g]),
+                           b->fused_blocks[g], hyper, rel, fold);
+}
+
 template <typename Real>
 void launch_batch_sweep_kernels(const gmrf_batch *b, int hyper, int rel, int fold, hipStream_t s)
 {
     launch_batch_lattice_kernels<Real>(b, hyper, rel, fold, s);
+    launch_fused_group<Real, false>(b, hyper, rel, fold, s);
+    launch_fused_group<Real, true>(b, hyper, rel, fold, s);
     // color c of every general-graph chain before color c + 1 of any
     const size_t ncol = std::max(b->csr_color_off[0].size(), b->csr_color_off[1].size());
     for (size_t col = 0; col + 1 < ncol; ++col) {
@@ -2491,6 +2886,88 @@ void drop_graphs(gmrf_chain *c)
     c->graph_defs.clear();
 }
 
+// The autotuner for a Gaussian chain on a general graph: times `reps`
+// whole sweeps of every shape that fits (0 color passes, 1 chunked one
+// launch, 2 one block) in dry mode, on a copy of the field in the chain's
+// other state buffer where a shape updates the field in place, so the
+// chain's state, accumulators and sweep count are unchanged.
+template <typename Real>
+int csr_autotune(gmrf_chain *c, int32_t reps, hipStream_t stream, double *t, int *win)
+{
+    const HostGraph &h = c->g->h;
+    const int keep = c->lat_tile;
+    const int cur = keep == kFused ? (int)(c->host_sweeps & 1u) : 0;   // buffer holding x
+    const size_t bytes = real_size(c->prec) * (size_t)h.n;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    GMRF_HIP(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    *win = keep;
+    for (int k = 0; k < GMRF_NUM_TILES && he == hipSuccess; ++k) {
+        t[k] = 0.0;
+        const bool fits = k == 0 || (k == kFused && csr_fused_fits(h, c->prec, false)) ||
+                          (k == kPersistent && csr_persist_fits(h, c->prec));
+        if (!fits)
+            continue;
+        c->lat_tile = k;
+        c->total_slots = csr_slots(c, k);
+        const SweepArgs a = dry_args(make_args(c, GMRF_WITH_HYPER), c);
+        CsrArgs<Real> ca = csr_args<Real>(c);
+        ca.x = static_cast<Real *>(c->d_x[1 - cur]);          // the in-place shapes' copy
+        // the chunked sweep reads buffer (sweep & 1): make that the current one
+        const FusedArgs<Real> fa = fused_args<Real>(c, (int)(c->host_sweeps & 1u) != cur);
+        auto one = [&](hipStream_t s) {
+            if (k == kFused) {
+                launch_fused<Real>(c, fa, a, s, nullptr, nullptr, 0, 0);
+            } else if (k == kPersistent) {
+                const SlabTable sl = slab_table(h);
+                auto kern = c->model.intercept ? csr_persistent_kernel<Real, true, false>
+                                               : csr_persistent_kernel<Real, false, false>;
+                hipLaunchKernelGGL(kern, dim3(1), dim3(kCsrPersistThreads), 0, s, ca, a, sl, 1);
+            } else {
+                int slot = 0;
+                for (int32_t col = 0; col < h.k; ++col) {
+                    const int nb = c->pass_blocks[col];
+                    if (nb == 0)
+                        continue;
+                    const int lo = h.slab_offsets[col], cnt = h.slab_offsets[col + 1] - lo;
+                    auto kern = c->model.intercept ? csr_pass_kernel<Real, true>
+                                                   : csr_pass_kernel<Real, false>;
+                    hipLaunchKernelGGL(kern, dim3(nb), dim3(kThreads), 0, s, ca, a, lo, cnt, slot);
+                    slot += nb;
+                }
+            }
+        };
+        if (k != kFused)
+            he = hipMemcpyAsync(ca.x, c->d_x[cur], bytes, hipMemcpyDeviceToDevice, stream);
+        for (int i = 0; i < 2 && he == hipSuccess; ++i)
+            one(stream);
+        if (he == hipSuccess)
+            he = hipEventRecord(e0, stream);
+        for (int i = 0; i < reps && he == hipSuccess; ++i)
+            one(stream);
+        if (he == hipSuccess)
+            he = hipEventRecord(e1, stream);
+        if (he == hipSuccess)
+            he = hipGetLastError();
+        if (he == hipSuccess)
+            he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (he == hipSuccess)
+            he = hipEventElapsedTime(&ms, e0, e1);
+        t[k] = 1e3 * (double)ms / reps;
+        if (he == hipSuccess && (k == 0 || t[k] < t[*win]))
+            *win = k;
+    }
+    (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    c->lat_tile = keep;
+    c->total_slots = csr_slots(c, keep);
+    if (he != hipSuccess)
+        return fail(GMRF_E_DEVICE, std::string("chain_autotune: ") + hipGetErrorString(he));
+    return GMRF_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -2512,7 +2989,11 @@ size_t gmrf_graph_footprint(const gmrf_graph_desc *d)
         set_error("graph_footprint: n >= 1 and row_ptr are required");
         return 0;
     }
-    return graph_device_bytes(d->n, d->row_ptr[d->n], false);
+    // the chunk tables' size depends on the graph: build its host form
+    HostGraph h;
+    if (build_host_graph(d, &h) != GMRF_OK)
+        return 0;
+    return graph_device_bytes(h);
 }
 
 int gmrf_graph_create(const gmrf_graph_desc *d, void *d_ws, size_t ws_bytes, hipStream_t stream,
@@ -2529,7 +3010,7 @@ int gmrf_graph_create(const gmrf_graph_desc *d, void *d_ws, size_t ws_bytes, hip
         return rc;
     }
     if (!is_lattice(g)) {
-        const size_t need = graph_device_bytes(g->h.n, g->h.nnz, false);
+        const size_t need = graph_device_bytes(g->h);
         if (!d_ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0) {
             delete g;
             return fail(GMRF_E_WORKSPACE, "graph_create: workspace NULL, misaligned or smaller "
@@ -2542,6 +3023,24 @@ int gmrf_graph_create(const gmrf_graph_desc *d, void *d_ws, size_t ws_bytes, hip
         g->d_col = reinterpret_cast<int *>(b);
         b += align_up(sizeof(int) * (size_t)std::max<int64_t>(g->h.nnz, 1));
         g->d_orig = reinterpret_cast<int *>(b);
+        b += align_up(sizeof(int) * (size_t)g->h.n);
+        std::vector<std::pair<void *, std::pair<const void *, size_t>>> chunk_up;
+        if (g->h.chunks_ok) {
+            auto place = [&](auto *&dptr, const auto &vec) {
+                using T = typename std::decay_t<decltype(vec)>::value_type;
+                dptr = reinterpret_cast<std::remove_reference_t<decltype(dptr)>>(b);
+                b += align_up(sizeof(T) * std::max<size_t>(vec.size(), 1));
+                if (!vec.empty())
+                    chunk_up.push_back({(void *)dptr, {vec.data(), sizeof(T) * vec.size()}});
+            };
+            place(g->d_ch_loc, g->h.ch_loc);
+            place(g->d_ch_row, g->h.ch_row);
+            place(g->d_ch_adj, g->h.ch_adj);
+            place(g->d_ch_meta, g->h.ch_meta);
+            place(g->d_loc_site, g->h.loc_site);
+            place(g->d_loc_row, g->h.loc_row);
+            place(g->d_loc_adj, g->h.loc_adj);
+        }
         static const int kNoNeighbour = 0;   // the column entry of a graph without edges
         hipError_t e = hipMemcpyAsync(g->d_row_ptr, g->h.row_ptr.data(),
                                       sizeof(int) * (g->h.n + 1), hipMemcpyHostToDevice, stream);
@@ -2553,6 +3052,10 @@ int gmrf_graph_create(const gmrf_graph_desc *d, void *d_ws, size_t ws_bytes, hip
         if (e == hipSuccess)
             e = hipMemcpyAsync(g->d_orig, g->h.orig_of_slab.data(), sizeof(int) * g->h.n,
                                hipMemcpyHostToDevice, stream);
+        for (const auto &u : chunk_up)
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(u.first, u.second.first, u.second.second,
+                                   hipMemcpyHostToDevice, stream);
         if (e == hipSuccess)
             e = hipStreamSynchronize(stream);
         if (e != hipSuccess) {
@@ -2707,7 +3210,7 @@ static int chain_create_impl(const char *who, const gmrf_graph *g, const gmrf_mo
     c->instance = instance;
     c->rank = rank;
     c->binomial = binomial;
-    c->lat_tile = is_lattice(g) ? default_tile(g->h) : csr_default_shape(g->h, p);
+    c->lat_tile = is_lattice(g) ? default_tile(g->h) : csr_default_shape(g->h, p, binomial);
     chain_layout(g, p, static_cast<char *>(d_ws), c, binomial, n_chunks);
 
     auto cleanup = [&](int rc) {
@@ -3159,12 +3662,24 @@ int gmrf_chain_set_tile(gmrf_chain *c, int32_t tile)
         return fail(GMRF_E_INVALID_ARG, "chain_set_tile: NULL chain, or tile not in 0 .. "
                                         "GMRF_NUM_TILES - 1");
     if (!is_lattice(c->g)) {
-        if (tile == 1 || (tile == kPersistent && !csr_persist_fits(c->g->h, c->prec)))
-            return fail(GMRF_E_INVALID_ARG, "chain_set_tile: a general graph takes shape 0, or "
-                                            "shape 2 when its field fits in LDS (at most 122880 "
-                                            "bytes of state) and it has at most 32 colors");
+        if ((tile == kFused && !csr_fused_fits(c->g->h, c->prec, c->binomial)) ||
+            (tile == kPersistent && !csr_persist_fits(c->g->h, c->prec)))
+            return fail(GMRF_E_INVALID_ARG, "chain_set_tile: a general graph takes shape 0; "
+                                            "shape 1 when its chunks fit (not for the binomial "
+                                            "model); shape 2 when its field fits in LDS (at most "
+                                            "122880 bytes of state) and it has at most 32 colors");
         if (tile != c->lat_tile) {
+            // shape 1 keeps x in buffer (sweep & 1), the others in buffer 0:
+            // move it when the chain has run an odd number of sweeps
+            if ((tile == kFused) != (c->lat_tile == kFused) && (c->host_sweeps & 1u)) {
+                const size_t bytes = real_size(c->prec) * (size_t)c->g->h.n;
+                GMRF_HIP(hipDeviceSynchronize());
+                GMRF_HIP(tile == kFused
+                             ? hipMemcpy(c->d_x[1], c->d_x[0], bytes, hipMemcpyDeviceToDevice)
+                             : hipMemcpy(c->d_x[0], c->d_x[1], bytes, hipMemcpyDeviceToDevice));
+            }
             c->lat_tile = tile;
+            c->total_slots = csr_slots(c, tile);
             drop_graphs(c);
         }
         return GMRF_OK;
@@ -3184,9 +3699,23 @@ int gmrf_chain_autotune(gmrf_chain *c, int32_t reps, hipStream_t stream, int32_t
                         double *us_per_sweep)
 {
     clear_error();
-    if (!c || !is_lattice(c->g) || reps < 1 || reps > 100000)
-        return fail(GMRF_E_INVALID_ARG, "chain_autotune: NULL or general-graph chain, or reps "
-                                        "not in 1 .. 100000");
+    if (!c || reps < 1 || reps > 100000 || c->binomial)
+        return fail(GMRF_E_INVALID_ARG, "chain_autotune: NULL or binomial chain, or reps not "
+                                        "in 1 .. 100000");
+    if (!is_lattice(c->g)) {
+        double t[GMRF_NUM_TILES] = {};
+        int win = c->lat_tile;
+        const int rc = c->prec == GMRF_FP64 ? csr_autotune<double>(c, reps, stream, t, &win)
+                                            : csr_autotune<float>(c, reps, stream, t, &win);
+        if (rc != GMRF_OK)
+            return rc;
+        if (us_per_sweep)
+            for (int k = 0; k < GMRF_NUM_TILES; ++k)
+                us_per_sweep[k] = t[k];
+        if (best)
+            *best = win;
+        return gmrf_chain_set_tile(c, win);
+    }
     const int keep = c->lat_tile;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     GMRF_HIP(hipEventCreate(&e0));

@@ -33,7 +33,47 @@ struct HostGraph {
     std::vector<int32_t> slab_of_orig;   // original id -> slab position
     std::vector<int32_t> row_ptr;        // permuted CSR, n + 1
     std::vector<int32_t> col;            // slab positions, each row in ascending ORIGINAL id
+    // Chunks for the one-launch sweep of a general graph (built by
+    // build_chunks): chunk b owns about kChunkSites sites of compact extent
+    // and stages, in LDS slot order, R_b (its owned sites and every site
+    // whose new value they need this sweep, by color, owned first within a
+    // color) and then H_b (the other neighbours of R_b, read-only).
+    int32_t nchunks = 0;
+    int32_t max_local = 0;               // most staged sites of any chunk
+    int32_t max_r = 0;                   // most recomputed (R) sites of any chunk
+    int32_t max_adj = 0;                 // most local neighbour entries of any chunk
+    bool chunks_ok = false;              // every chunk within the LDS and index limits
+    std::vector<int32_t> ch_loc;         // nchunks + 1: first staged site of each chunk
+    std::vector<int32_t> ch_row;         // nchunks + 1: first local row offset of each chunk
+    std::vector<int32_t> ch_adj;         // nchunks + 1: first local neighbour of each chunk
+    std::vector<int32_t> ch_meta;        // per chunk, 3k + 1: R color offsets (k + 1), owned
+                                         // counts (k), first slab position of the owned run of
+                                         // each color (k)
+    std::vector<int32_t> loc_site;       // slab position of every staged site
+    std::vector<uint16_t> loc_row;       // per chunk, |R_b| + 1 offsets into its local neighbours
+    std::vector<uint16_t> loc_adj;       // local slots of the neighbours of each R_b site,
+                                         // ascending original id
 };
+
+// Owned sites per chunk, and the limits of a chunk: its LDS image (staged
+// values, y and ids of the R sites, local rows and neighbours) in FP64, and
+// 16-bit local offsets.  A launch reserves the largest image part by part
+// (chunk_lds_bytes of the per-part maxima), at most kFusedLaunchLds.
+constexpr int32_t kChunkSites = 512;
+constexpr int64_t kFusedLdsBytes = 40960;
+constexpr int64_t kFusedLaunchLds = 65536;
+constexpr int64_t kMaxLocalAdj = 65535;
+
+// Bytes of a chunk's LDS image with real_bytes-byte values (the layout of
+// the chunked sweep kernel: values of the staged sites, then y and the
+// original id of each R site, then the R sites' local row offsets and
+// neighbours, each part 16-byte aligned).
+inline int64_t chunk_lds_bytes(int64_t nloc, int64_t nr, int64_t nadj, int64_t real_bytes)
+{
+    auto al = [](int64_t b) { return (b + 15) / 16 * 16; };
+    return al(real_bytes * nloc) + al(real_bytes * nr) + al(4 * nr) + al(2 * (nr + 1)) +
+           al(2 * nadj);
+}
 
 // Validate a description and build its host form; returns a gmrf_status.
 int build_host_graph(const gmrf_graph_desc *d, HostGraph *out);
@@ -42,8 +82,8 @@ int build_host_graph(const gmrf_graph_desc *d, HostGraph *out);
 int greedy_coloring_host(int64_t n, const int64_t *row_ptr, const int32_t *col, int32_t *color,
                          int32_t *k);
 
-// Bytes of the device form of a graph.
-size_t graph_device_bytes(int64_t n, int64_t nnz, bool lattice);
+// Bytes of the device form of a graph (a built host form).
+size_t graph_device_bytes(const HostGraph &g);
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }

@@ -136,7 +136,15 @@ def test_footprint_arithmetic():
     fp = gmrf.lib().gmrf_graph_footprint(gmrf.C.byref(d.desc))
     al = lambda b: (b + 255) // 256 * 256
     n, nnz = rp.size - 1, cl.size
-    assert fp == al(4 * (n + 1)) + al(4 * max(nnz, 1)) + al(4 * n)
+    csr = al(4 * (n + 1)) + al(4 * max(nnz, 1)) + al(4 * n)
+    # a graph within one chunk: the chunk stages every site (R = all, H
+    # empty), so its tables are 3 x 2 bases, 3k + 1 metadata entries, n
+    # staged sites, n + 1 local row offsets and nnz local neighbours (16 bits,
+    # each padded to a multiple of 8 entries)
+    p8 = lambda m: (m + 7) // 8 * 8
+    chunks = (3 * al(8) + al(4 * (3 * k + 1)) + al(4 * n) + al(2 * p8(n + 1)) +
+              al(2 * max(p8(nnz), 1)))
+    assert fp == csr + chunks
     d = gmrf._Desc(lattice=(64, 64, 4))
     assert gmrf.lib().gmrf_graph_footprint(gmrf.C.byref(d.desc)) == 0
 

@@ -52,7 +52,7 @@ def bipartite(hubs, m):
 GRAPHS = {"wheel1201": lambda: wheel(1201), "k3_700": lambda: bipartite(3, 700)}
 
 
-@pytest.mark.parametrize("shape", [0, 2])
+@pytest.mark.parametrize("shape", [0, 1, 2])
 @pytest.mark.parametrize("rho", [1.0, 0.95])
 @pytest.mark.parametrize("name", sorted(GRAPHS))
 def test_hub_graph_gaussian_sweeps(G, orc, name, rho, shape):
@@ -99,7 +99,7 @@ def test_hub_graph_binomial_sweeps(G, orc, name, shape):
         assert rel(tau, oc.tau) <= RTOL64 and rel(ch.beta0, oc.beta0) <= RTOL64
 
 
-@pytest.mark.parametrize("shape", [0, 2])
+@pytest.mark.parametrize("shape", [0, 1, 2])
 @pytest.mark.parametrize("rho", [1.0, 0.95])
 def test_graph_without_edges(G, orc, rho, shape):
     """Every site isolated (no column entries at all): x_i ~ N(y_i, 1 / lam)

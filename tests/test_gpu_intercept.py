@@ -105,9 +105,11 @@ def test_image_trajectory_fp64(G, orc):
     assert rel(m, om) <= RTOL64 and rel(v, ov) <= 1e-9
 
 
-def test_csr_intercept_trajectory_fp64(G, orc):
+@pytest.mark.parametrize("shape", [0, 1, 2])
+def test_csr_intercept_trajectory_fp64(G, orc, shape):
     wl = csr_intrinsic(3000)
     g, ch, oc = pair(G, orc, wl, seed=11, instance=2)
+    ch.set_tile(shape)
     ch.sweep(60)
     oc.sweeps(60)
     x, tau, lam, sw = ch.get_state()

@@ -86,7 +86,7 @@ def test_lattice_one_sweep_from_injected_state(G, orc, rows, cols, st, shape):
     assert rel(tau, oc.tau) <= RTOL64 and rel(lam, oc.lam) <= RTOL64
 
 
-@pytest.mark.parametrize("shape", [0, 2])
+@pytest.mark.parametrize("shape", [0, 1, 2])
 @pytest.mark.parametrize("rho", [1.0, 0.95])
 def test_csr_one_sweep_from_injected_state(G, orc, rho, shape):
     wl = csr_case(3000, data_seed=5, rho=rho)
@@ -138,7 +138,7 @@ def oracle_trajectory(oc, sweeps, every=100, nthreads=8):
     return taus, lams, xs
 
 
-@pytest.mark.parametrize("shape", [0, 2])
+@pytest.mark.parametrize("shape", [0, 1, 2])
 def test_csr_trajectory_delaunay_fp64(G, orc, shape):
     """The 15,000-site irregular workload for its 2000 sweeps in FP64: tau and
     lam after every sweep (device trace), the field every 100 sweeps, and the
@@ -287,7 +287,7 @@ def test_device_pointer_stats(G, orc):
     assert np.array_equal(m.cpu().numpy(), mean) and np.array_equal(v.cpu().numpy(), var)
 
 
-@pytest.mark.parametrize("shape", [0, 2])
+@pytest.mark.parametrize("shape", [0, 1, 2])
 def test_isolated_sites_and_empty_color(G, orc, shape):
     # 3 components (one isolated site) and a coloring that leaves color 2 empty
     rp, cl = inputs.edges_to_csr(6, [0, 1, 3], [1, 2, 4])
@@ -357,14 +357,14 @@ def test_lattice_checkpoint_resume_and_burn_in(G, orc, prec):
         assert nf == 8 and rel(s1f, oc.s1) <= RTOL64 and rel(s2f, oc.s2) <= RTOL64
 
 
-@pytest.mark.parametrize("kind", ["lattice", "csr", "csr_one_block"])
+@pytest.mark.parametrize("kind", ["lattice", "csr", "csr_one_block", "csr_chunked"])
 def test_sweep_timed_equals_sweep(G, orc, kind):
     wl = lattice_case(100, 120, 8) if kind == "lattice" else csr_case(4000, data_seed=2)
     g = gpu_graph(G, wl)
     a = G.Chain(g, wl["y"], seed=4)
     b = G.Chain(g, wl["y"], seed=4)
     if kind.startswith("csr"):
-        shape = 2 if kind == "csr_one_block" else 0
+        shape = {"csr": 0, "csr_one_block": 2, "csr_chunked": 1}[kind]
         a.set_tile(shape)
         b.set_tile(shape)
     a.sweep(6)
@@ -450,3 +450,62 @@ def test_numeric_failure_is_reported_through_the_status_word(G, orc):
     oc = orc.Chain(wl["row_ptr"], wl["col"], wl["color"], y, seed=1, lam0=1e6)
     with pytest.raises(FloatingPointError):
         oc.sweeps(1)
+
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_csr_chunked_shape_changes_mid_chain(G, orc, prec):
+    """The chunked one-launch sweep (shape 1) keeps the field in the buffer of
+    the sweep parity, the other shapes in one buffer: switching shapes after
+    an odd number of sweeps moves it, so the chain goes on exactly as the
+    oracle's, with plain and captured sweeps."""
+    precision = G.FP64 if prec == "fp64" else G.FP32_ACC64
+    wl = csr_case(9000, data_seed=6, rho=0.95)
+    g, ch, oc = pair(G, orc, wl, precision=precision, seed=12, burn_in=4)
+    ref = G.Chain(g, wl["y"], precision=precision, seed=12, burn_in=4)
+    ref.set_tile(1)
+    steps = [(0, 3, False), (1, 5, True), (2, 1, False), (1, 2, False), (0, 4, True)]
+    for shape, n, cap in steps:
+        ch.set_tile(shape)
+        assert ch.tile[0] == shape
+        ch.sweep(n, capture=cap)
+        ref.sweep(n)
+        oc.sweeps(n, nthreads=8)
+        x, tau, lam, _ = ch.get_state()
+        if prec == "fp64":
+            assert rel(x, oc.x) <= RTOL64 and rel(tau, oc.tau) <= RTOL64, (shape, n)
+        else:
+            assert np.max(np.abs(x - oc.x)) <= 1e-4
+    m, v, nacc = ch.posterior_stats()
+    om, ov = oc.stats()
+    assert nacc == 15 - 4
+    if prec == "fp64":
+        assert rel(m, om) <= RTOL64
+    # the chunked chain swept in one shape ends in the same state as the
+    # oracle's too (the same site values, whatever the shape)
+    xr, _, _, _ = ref.get_state()
+    if prec == "fp64":
+        assert rel(xr, oc.x) <= RTOL64
+
+
+def test_csr_autotune_leaves_state_unchanged(G, orc):
+    wl = csr_case(6000, data_seed=7, rho=0.95)
+    g, ch, oc = pair(G, orc, wl, seed=14)
+    twin = G.Chain(g, wl["y"], seed=14)
+    ch.set_tile(1)
+    ch.sweep(3)                         # odd: the field sits in the second buffer
+    twin.sweep(3)
+    before = ch.get_state(), ch.get_accumulators(), ch.last_reductions()
+    best, us = ch.autotune(reps=4)
+    after = ch.get_state(), ch.get_accumulators(), ch.last_reductions()
+    assert best in (0, 1, 2) and all(u > 0 for u in us), us
+    assert ch.tile[0] == best
+    assert np.array_equal(before[0][0], after[0][0]) and before[0][1:] == after[0][1:]
+    assert np.array_equal(before[1][0], after[1][0]) and np.array_equal(before[1][1], after[1][1])
+    assert before[1][2] == after[1][2] and before[2] == after[2]
+    ch.sweep(5)
+    twin.sweep(5)
+    oc.sweeps(8)
+    for c in (ch, twin):
+        x, tau, lam, _ = c.get_state()
+        assert rel(x, oc.x) <= RTOL64 and rel(tau, oc.tau) <= RTOL64

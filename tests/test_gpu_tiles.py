@@ -46,21 +46,22 @@ def test_default_shapes(G):
     assert csr.tile == (2, 0, 0, 512)          # the field fits in LDS: one block
     csr.set_tile(0)
     assert csr.tile == (0, 0, 0, 256)          # one launch per color
-    with pytest.raises(G.GmrfError):
-        csr.set_tile(1)
+    csr.set_tile(1)
+    assert csr.tile == (1, 0, 0, 256)          # chunks, one launch per sweep
     with pytest.raises(G.GmrfError):
         small.set_tile(2)
-    with pytest.raises(G.GmrfError):
-        csr.autotune()
+    best, us = csr.autotune(reps=2)
+    assert csr.tile[0] == best and all(u > 0 for u in us)
     big_wl = inputs.delaunay_workload(20000, data_seed=3)
     bcolor, bk = G.greedy_coloring(big_wl["row_ptr"], big_wl["col"])
     bg = G.Graph(row_ptr=big_wl["row_ptr"], col_idx=big_wl["col"], color=bcolor, num_colors=bk,
                  rho=0.95)
-    # 20,000 sites: color slabs beyond two rounds of the block, so the color
-    # passes by default; FP64 (160 KB) does not fit in LDS, FP32 (80 KB) does
+    # 20,000 sites: color slabs beyond two rounds of the block, so the chunked
+    # one-launch sweep by default; FP64 (160 KB) does not fit in LDS, FP32
+    # (80 KB) does
     c64 = G.Chain(bg, big_wl["y"])
     c32 = G.Chain(bg, big_wl["y"], precision=G.FP32_ACC64)
-    assert c64.tile[0] == 0 and c32.tile[0] == 0
+    assert c64.tile[0] == 1 and c32.tile[0] == 1
     with pytest.raises(G.GmrfError):
         c64.set_tile(2)
     c32.set_tile(2)
