@@ -359,44 +359,67 @@ __device__ __forceinline__ HyperIn inputs_of(const SweepArgs &a, int rel)
 // i + kFinishThreads, ..., then a fixed tree), and draw beta0 / tau / lam
 // from the ring's unit variates (end_of_sweep_draws, which also stores q /
 // sse and the trace row unless a.dry).  Returns the draws in every thread.
+// The two halves (fold_partials, then a barrier, then fold_draws) may be run
+// apart, with other work between them.
 constexpr int kFinishThreads = 256;
 
-template <int NT>
-__device__ __forceinline__ HyperIn end_sweep_block(const SweepArgs &a, const double *P, unsigned t,
-                                                   const HyperIn &in, bool commit)
+struct FoldLds {
+    double red[kPartials * (kFinishThreads / 64)];
+    double hyp[3];
+};
+
+// Per-wave sums of the partials into L.red (U: slots per thread in flight).
+template <int U>
+__device__ __forceinline__ void fold_partials(const SweepArgs &a, const double *P, FoldLds &L)
 {
-    static_assert(NT >= kFinishThreads && NT % 64 == 0, "the finish needs kFinishThreads threads");
     constexpr int W = kFinishThreads / 64;
-    __shared__ double red[kPartials * W];
-    __shared__ double hyp[3];
     const int lane = (int)threadIdx.x & 63, wid = (int)threadIdx.x >> 6;
     if (wid < W) {
         Red r;
-#pragma unroll 4
-        for (int i = threadIdx.x; i < a.total_slots; i += kFinishThreads) {
-            r.q += P[kPartials * i];
-            r.sse += P[kPartials * i + 1];
-            r.rsum += P[kPartials * i + 2];
+        for (int i0 = threadIdx.x; i0 < a.total_slots; i0 += U * kFinishThreads) {
+            double v[kPartials * U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * kFinishThreads;
+#pragma unroll
+                for (int w = 0; w < kPartials; ++w)
+                    v[kPartials * u + w] = P[kPartials * min(i, a.total_slots - 1) + w];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i0 + u * kFinishThreads < a.total_slots) {
+                    r.q += v[kPartials * u];
+                    r.sse += v[kPartials * u + 1];
+                    r.rsum += v[kPartials * u + 2];
+                }
         }
         r.q = wave_sum(r.q);
         r.sse = wave_sum(r.sse);
         r.rsum = wave_sum(r.rsum);
         if (lane == 0) {
-            red[wid] = r.q;
-            red[W + wid] = r.sse;
-            red[2 * W + wid] = r.rsum;
+            L.red[wid] = r.q;
+            L.red[W + wid] = r.sse;
+            L.red[2 * W + wid] = r.rsum;
         }
     }
-    lds_barrier();
+}
+
+// The wave sums in order, and the draws (after a barrier that follows
+// fold_partials); ends with a barrier.
+__device__ __forceinline__ HyperIn fold_draws(const SweepArgs &a, unsigned t, const HyperIn &in,
+                                              bool commit, FoldLds &L)
+{
+    constexpr int W = kFinishThreads / 64;
+    const int lane = (int)threadIdx.x & 63, wid = (int)threadIdx.x >> 6;
     if (wid == 0) {
         Red r;
-        r.q = red[0];
-        r.sse = red[W];
-        r.rsum = red[2 * W];
+        r.q = L.red[0];
+        r.sse = L.red[W];
+        r.rsum = L.red[2 * W];
         for (int w = 1; w < W; ++w) {
-            r.q += red[w];
-            r.sse += red[W + w];
-            r.rsum += red[2 * W + w];
+            r.q += L.red[w];
+            r.sse += L.red[W + w];
+            r.rsum += L.red[2 * W + w];
         }
         UnitDraws u{0.0, 0.0, false};
         if (a.with_hyper && lane < 2) {
@@ -408,13 +431,24 @@ __device__ __forceinline__ HyperIn end_sweep_block(const SweepArgs &a, const dou
         }
         const HyperIn out = end_of_sweep_draws(a, t, r, in, lane, u, commit);
         if (lane == 0) {
-            hyp[0] = out.tau;
-            hyp[1] = out.lam;
-            hyp[2] = out.beta0;
+            L.hyp[0] = out.tau;
+            L.hyp[1] = out.lam;
+            L.hyp[2] = out.beta0;
         }
     }
     lds_barrier();
-    return HyperIn{hyp[0], hyp[1], hyp[2]};
+    return HyperIn{L.hyp[0], L.hyp[1], L.hyp[2]};
+}
+
+template <int NT>
+__device__ __forceinline__ HyperIn end_sweep_block(const SweepArgs &a, const double *P, unsigned t,
+                                                   const HyperIn &in, bool commit)
+{
+    static_assert(NT >= kFinishThreads && NT % 64 == 0, "the finish needs kFinishThreads threads");
+    __shared__ FoldLds L;
+    fold_partials<4>(a, P, L);
+    lds_barrier();
+    return fold_draws(a, t, in, commit, L);
 }
 
 // Commit the end of a call: end its relative sweep rel (the last of the
@@ -1285,7 +1319,7 @@ template <typename Real> struct FusedArgs {
     const int *ch_loc, *ch_row, *ch_adj, *ch_meta;   // per-chunk bases and metadata
     const int *loc_site;                             // slab position of each staged site
     const unsigned short *loc_row, *loc_adj;         // local adjacency of the R sites
-    const int *orig;                                 // slab position -> original id
+    const unsigned *loc_id;                          // original id of each staged site
     Real *x0, *x1;                                   // ping-pong state, slab order
     const Real *y;                                   // y (slab order)
     int k;                                           // colors
@@ -1294,16 +1328,17 @@ template <typename Real> struct FusedArgs {
 
 constexpr int kFusedGather = 8;                      // neighbour indices read per batch
 constexpr int kQtabDeg = 64;                         // degrees with tabulated scales
-constexpr int kFusedCH = 4;                          // owned sites per thread per batch
+constexpr int kFusedCH = 4;                          // sites per thread per batch
+constexpr int kFoldUnroll = 8;                       // partial slots per thread in flight
 
 __host__ __device__ constexpr size_t lds_align16(size_t b) { return (b + 15) / 16 * 16; }
 
-// Neighbour sum of a staged site in row order (local neighbours e0 .. e1 - 1).
+// Neighbour sum of a staged site in row order (local neighbours e0 .. e1 - 1),
+// continuing the running sum sum.
 template <typename Real>
 __device__ __forceinline__ Real fused_nbr_sum(const Real *xs, const unsigned short *adj, int e0,
-                                              int e1)
+                                              int e1, Real sum)
 {
-    Real sum = (Real)0;
     for (int eb = e0; eb < e1; eb += kFusedGather) {
         int l[kFusedGather];
 #pragma unroll
@@ -1317,7 +1352,15 @@ __device__ __forceinline__ Real fused_nbr_sum(const Real *xs, const unsigned sho
     return sum;
 }
 
-// Chunk b of a chain (rel, fold: as for the lattice sweep kernel).
+// Chunk b of a chain (rel, fold: as for the lattice sweep kernel).  Order of
+// work, so that independent loads are in flight together: the chunk's local
+// rows and neighbours go to LDS by direct global-to-LDS copies; the slab
+// positions of the first kFusedCH * kThreads staged sites load beside the
+// previous sweep's partials (first half of the fold); their values and y
+// (gathers) go to LDS; the normal variates of the R sites (keyed by
+// original id and sweep only) go to LDS; the fold's draws; the color phases
+// run in LDS, each owned site's q / sse terms, accumulators and write-back
+// taken as it is drawn.
 template <typename Real, bool B0>
 __device__ __forceinline__ void csr_fused_block(const FusedArgs<Real> &fa, const SweepArgs &a,
                                                 const int b, const int rel, const int fold)
@@ -1327,22 +1370,83 @@ __device__ __forceinline__ void csr_fused_block(const FusedArgs<Real> &fa, const
     size_t off = lds_align16(sizeof(Real) * (size_t)fa.max_local);
     Real *ys = reinterpret_cast<Real *>(fused_lds + off);
     off += lds_align16(sizeof(Real) * (size_t)fa.max_r);
-    unsigned *ids = reinterpret_cast<unsigned *>(fused_lds + off);
-    off += lds_align16(sizeof(unsigned) * (size_t)fa.max_r);
+    Real *zs = reinterpret_cast<Real *>(fused_lds + off);
+    off += lds_align16(sizeof(Real) * (size_t)fa.max_r);
     unsigned short *lrow = reinterpret_cast<unsigned short *>(fused_lds + off);
     off += lds_align16(sizeof(unsigned short) * (size_t)(fa.max_r + 1));
     unsigned short *ladj = reinterpret_cast<unsigned short *>(fused_lds + off);
     __shared__ Real qtab[2 * kQtabDeg];
+    __shared__ int sm[3 * kFusedMaxColors + 1];
+    __shared__ FoldLds fl;
 
     const unsigned t = (unsigned)(a.st->sweep + (unsigned long long)rel);
     const Real *src = (t & 1u) ? fa.x1 : fa.x0;
     Real *dst = (t & 1u) ? fa.x0 : fa.x1;
+    const int k = fa.k;
+    const int *meta = fa.ch_meta + (size_t)b * (3 * k + 1);
+    const int loc0 = fa.ch_loc[b], nloc = fa.ch_loc[b + 1] - loc0;
+    const int nr = meta[k];
+    const int row0 = fa.ch_row[b], adj0 = fa.ch_adj[b], nadj = fa.ch_adj[b + 1] - adj0;
+    const int *site = fa.loc_site + loc0;
+    const unsigned *sid = fa.loc_id + loc0;
+    for (int i = (int)threadIdx.x; i < 3 * k + 1; i += kThreads)
+        sm[i] = meta[i];
+
+    // rows and neighbours: each chunk's start is on a 16-byte boundary and
+    // both are padded to whole 16-byte vectors; lane L of a wave copies
+    // vector i to the wave's LDS base + 16 L
+    {
+        const int nrow4 = (nr + 1 + 7) / 8, nadj4 = nadj / 8;
+        const uint4 *grow = reinterpret_cast<const uint4 *>(fa.loc_row + row0);
+        const uint4 *gadj = reinterpret_cast<const uint4 *>(fa.loc_adj + adj0);
+        uint4 *srow = reinterpret_cast<uint4 *>(lrow);
+        uint4 *sadj = reinterpret_cast<uint4 *>(ladj);
+        const int lane = (int)threadIdx.x & 63;
+        for (int i = (int)threadIdx.x; i - lane < nrow4; i += kThreads)
+            if (i < nrow4)
+                __builtin_amdgcn_global_load_lds(grow + i, srow + (i - lane), 16, 0, 0);
+        for (int i = (int)threadIdx.x; i - lane < nadj4; i += kThreads)
+            if (i < nadj4)
+                __builtin_amdgcn_global_load_lds(gadj + i, sadj + (i - lane), 16, 0, 0);
+    }
+
+    // staging, kFusedCH sites per thread at a time; the first batch's slab
+    // positions load beside the fold's partials
+    auto stage = [&](const int base, const bool first) {
+        int p[kFusedCH];
+#pragma unroll
+        for (int j = 0; j < kFusedCH; ++j)
+            p[j] = site[min(base + (int)threadIdx.x + j * kThreads, nloc - 1)];
+        if (first && fold)
+            fold_partials<kFoldUnroll>(a, partials_of(a, rel - 1), fl);
+        Real xv[kFusedCH], yv[kFusedCH];
+#pragma unroll
+        for (int j = 0; j < kFusedCH; ++j) {
+            xv[j] = src[p[j]];
+            yv[j] = fa.y[p[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < kFusedCH; ++j) {
+            const int s = base + (int)threadIdx.x + j * kThreads;
+            if (s < nloc)
+                xs[s] = xv[j];
+            if (s < nr)
+                ys[s] = yv[j];
+        }
+    };
+    stage(0, true);
+    for (int base = kFusedCH * kThreads; base < nloc; base += kFusedCH * kThreads)
+        stage(base, false);
+    // the variates of the R sites
+    for (int s = (int)threadIdx.x; s < nr; s += kThreads)
+        zs[s] = site_normal<Real>(draw_words(a.seed, sid[s], t, a.instance, 0u));
+    // every wave's direct copies have landed (a full barrier waits for them)
+    __syncthreads();
     HyperIn hin;
     if (fold) {      // end the previous sweep of the call (as the lattice kernel does)
         SweepArgs ea = a;
         ea.dry = a.dry || b != 0;
-        hin = end_sweep_block<kThreads>(ea, partials_of(a, rel - 1), t - 1u,
-                                        inputs_of(a, rel - 1), false);
+        hin = fold_draws(ea, t - 1u, inputs_of(a, rel - 1), false, fl);
         if (!ea.dry && threadIdx.x == 0) {
             double *const h = a.st->hs[rel & 1];
             h[0] = hin.tau;
@@ -1355,78 +1459,41 @@ __device__ __forceinline__ void csr_fused_block(const FusedArgs<Real> &fa, const
     const Real tau = (Real)hin.tau, lam = (Real)hin.lam, tau_rho = (Real)(hin.tau * a.rho);
     const double beta0 = B0 ? hin.beta0 : 0.0;
     const bool acc = (long long)t >= a.burn_in;
-    const int k = fa.k;
-    const int *meta = fa.ch_meta + (size_t)b * (3 * k + 1);
-    const int loc0 = fa.ch_loc[b], nloc = fa.ch_loc[b + 1] - loc0;
-    const int nr = meta[k];
-    const int row0 = fa.ch_row[b], adj0 = fa.ch_adj[b], nadj = fa.ch_adj[b + 1] - adj0;
-    const int *site = fa.loc_site + loc0;
-
-    // the chunk's LDS image, kFusedCH entries per thread in flight at a time:
-    // staged values, y and ids by slab position, then the rows and
-    // neighbours (each chunk's start on a 16-byte boundary, padded to whole
-    // 16-byte vectors) as 16-byte vectors
-    for (int s0 = (int)threadIdx.x; s0 < nloc; s0 += kFusedCH * kThreads) {
-        int p[kFusedCH];
-        Real xv[kFusedCH], yv[kFusedCH];
-        unsigned iv[kFusedCH];
-#pragma unroll
-        for (int j = 0; j < kFusedCH; ++j) {
-            const int s = s0 + j * kThreads;
-            p[j] = site[min(s, nloc - 1)];
-        }
-#pragma unroll
-        for (int j = 0; j < kFusedCH; ++j) {
-            xv[j] = src[p[j]];
-            yv[j] = fa.y[p[j]];
-            iv[j] = (unsigned)fa.orig[p[j]];
-        }
-#pragma unroll
-        for (int j = 0; j < kFusedCH; ++j) {
-            const int s = s0 + j * kThreads;
-            if (s < nloc)
-                xs[s] = xv[j];
-            if (s < nr) {
-                ys[s] = yv[j];
-                ids[s] = iv[j];
-            }
-        }
-    }
-    {
-        const int nrow4 = (nr + 1 + 7) / 8, nadj4 = nadj / 8;
-        const uint4 *grow = reinterpret_cast<const uint4 *>(fa.loc_row + row0);
-        const uint4 *gadj = reinterpret_cast<const uint4 *>(fa.loc_adj + adj0);
-        uint4 *srow = reinterpret_cast<uint4 *>(lrow);
-        uint4 *sadj = reinterpret_cast<uint4 *>(ladj);
-        for (int i0 = (int)threadIdx.x; i0 < nrow4 + nadj4; i0 += kFusedCH * kThreads) {
-            uint4 v[kFusedCH];
-#pragma unroll
-            for (int j = 0; j < kFusedCH; ++j) {
-                const int i = min(i0 + j * kThreads, nrow4 + nadj4 - 1);
-                v[j] = i < nrow4 ? grow[i] : gadj[i - nrow4];
-            }
-#pragma unroll
-            for (int j = 0; j < kFusedCH; ++j) {
-                const int i = i0 + j * kThreads;
-                if (i < nrow4)
-                    srow[i] = v[j];
-                else if (i < nrow4 + nadj4)
-                    sadj[i - nrow4] = v[j];
-            }
-        }
-    }
     if (threadIdx.x < kQtabDeg)
         site_scales<Real>(tau, lam, (int)threadIdx.x, qtab[threadIdx.x],
                           qtab[kQtabDeg + threadIdx.x]);
     lds_barrier();
 
-    // the color phases, in LDS
+    // the color phases, in LDS.  The owned sites of color c are the first
+    // owned[c] R sites of its run, at consecutive slab positions from
+    // ostart[c]: a thread that draws one also adds its q / sse terms (its
+    // lower-color neighbours hold this sweep's values), adds it to its
+    // accumulators and writes it back.  The accumulators take atomic adds
+    // whose results are not read back, so no phase waits on global memory;
+    // each accumulator takes one add per sweep, so each sum is the plain
+    // sum, bit for bit.
+    Red rd;
     for (int c = 0; c < k; ++c) {
-        const int lo = meta[c], hi = meta[c + 1];
+        const int lo = sm[c], hi = sm[c + 1], own = sm[k + 1 + c], ost = sm[2 * k + 1 + c];
         for (int s = lo + (int)threadIdx.x; s < hi; s += kThreads) {
             const int e0 = lrow[s], e1 = lrow[s + 1], deg = e1 - e0;
-            const Real sum = fused_nbr_sum<Real>(xs, ladj, e0, e1);
-            const Real z = site_normal<Real>(draw_words(a.seed, ids[s], t, a.instance, 0u));
+            // the first kFusedGather neighbours stay in registers for the
+            // q term; the rest (rare) are read again
+            int l[kFusedGather];
+            Real v[kFusedGather];
+#pragma unroll
+            for (int q = 0; q < kFusedGather; ++q)
+                l[q] = ladj[min(e0 + q, e1 - 1)];
+#pragma unroll
+            for (int q = 0; q < kFusedGather; ++q)
+                v[q] = xs[l[q]];
+            Real sum = (Real)0;
+#pragma unroll
+            for (int q = 0; q < kFusedGather; ++q)
+                if (q < deg)
+                    sum += v[q];
+            if (deg > kFusedGather)
+                sum = fused_nbr_sum<Real>(xs, ladj, e0 + kFusedGather, e1, sum);
             Real inv_q, isd;
             if (deg < kQtabDeg) {
                 inv_q = qtab[deg];
@@ -1434,70 +1501,42 @@ __device__ __forceinline__ void csr_fused_block(const FusedArgs<Real> &fa, const
             } else {
                 site_scales<Real>(tau, lam, deg, inv_q, isd);
             }
-            const Real yeff = B0 ? ys[s] - (Real)beta0 : ys[s];
-            xs[s] = site_draw<Real>(yeff, sum, z, lam, tau_rho, inv_q, isd);
+            const Real yv = ys[s];
+            const Real yeff = B0 ? yv - (Real)beta0 : yv;
+            const Real xn = site_draw<Real>(yeff, sum, zs[s], lam, tau_rho, inv_q, isd);
+            xs[s] = xn;
+            const int o = s - lo;
+            if (o < own) {
+                const int pos = ost + o;
+                const double xd = (double)xn;
+                double edge = 0.0;              // lower colors: this sweep's values
+#pragma unroll
+                for (int q = 0; q < kFusedGather; ++q)
+                    if (q < deg && l[q] < lo) {
+                        const double d = xd - (double)v[q];
+                        edge += d * d;
+                    }
+                for (int e = e0 + kFusedGather; e < e1; ++e) {
+                    const int le = ladj[e];
+                    if (le < lo) {
+                        const double d = xd - (double)xs[le];
+                        edge += d * d;
+                    }
+                }
+                rd.q += (1.0 - a.rho) * (double)deg * xd * xd + a.rho * edge;
+                const double rr = B0 ? (double)yv - beta0 - xd : (double)yv - xd;
+                rd.sse += rr * rr;
+                if (B0)
+                    rd.rsum += rr;
+                if (acc) {
+                    const double phi = B0 ? xd + beta0 : xd;
+                    unsafeAtomicAdd(a.s1 + pos, phi);
+                    unsafeAtomicAdd(a.s2 + pos, phi * phi);
+                }
+                dst[pos] = xn;
+            }
         }
         lds_barrier();
-    }
-
-    // the owned sites: q / sse terms, accumulators, write-back
-    int n_own = 0;
-    for (int c = 0; c < k; ++c)
-        n_own += meta[k + 1 + c];
-    Red rd;
-    for (int o0 = (int)threadIdx.x; o0 < n_own; o0 += kFusedCH * kThreads) {
-        int sl[kFusedCH], pos[kFusedCH], lo[kFusedCH];
-        double s1v[kFusedCH], s2v[kFusedCH];
-#pragma unroll
-        for (int j = 0; j < kFusedCH; ++j) {
-            const int o = o0 + j * kThreads;
-            sl[j] = -1;
-            pos[j] = 0;
-            lo[j] = 0;
-            s1v[j] = s2v[j] = 0.0;
-            if (o < n_own) {
-                int c = 0, before = 0;
-                while (o >= before + meta[k + 1 + c]) {
-                    before += meta[k + 1 + c];
-                    ++c;
-                }
-                lo[j] = meta[c];
-                sl[j] = meta[c] + (o - before);
-                pos[j] = meta[2 * k + 1 + c] + (o - before);
-                if (acc) {
-                    s1v[j] = a.s1[pos[j]];
-                    s2v[j] = a.s2[pos[j]];
-                }
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < kFusedCH; ++j) {
-            if (sl[j] < 0)
-                continue;
-            const int s = sl[j];
-            const Real xn = xs[s];
-            const double xd = (double)xn;
-            const int e0 = lrow[s], e1 = lrow[s + 1];
-            double edge = 0.0;
-            for (int e = e0; e < e1; ++e) {
-                const int l = ladj[e];
-                if (l < lo[j]) {                // lower color: new value, this sweep
-                    const double d = xd - (double)xs[l];
-                    edge += d * d;
-                }
-            }
-            rd.q += (1.0 - a.rho) * (double)(e1 - e0) * xd * xd + a.rho * edge;
-            const double rr = B0 ? (double)ys[s] - beta0 - xd : (double)ys[s] - xd;
-            rd.sse += rr * rr;
-            if (B0)
-                rd.rsum += rr;
-            if (acc) {
-                const double phi = B0 ? xd + beta0 : xd;
-                a.s1[pos[j]] = s1v[j] + phi;
-                a.s2[pos[j]] = s2v[j] + phi * phi;
-            }
-            dst[pos[j]] = xn;
-        }
     }
     write_partials<kThreads>(partials_of(a, rel), rd, b);
 }
@@ -1852,6 +1891,7 @@ struct gmrf_graph {
     // chunks of the one-launch sweep (shape 1), when h.chunks_ok
     int *d_ch_loc = nullptr, *d_ch_row = nullptr, *d_ch_adj = nullptr, *d_ch_meta = nullptr;
     int *d_loc_site = nullptr;
+    unsigned *d_loc_id = nullptr;
     unsigned short *d_loc_row = nullptr, *d_loc_adj = nullptr;
 };
 
@@ -2292,7 +2332,7 @@ template <typename Real> FusedArgs<Real> fused_args(const gmrf_chain *c, bool sw
     fa.loc_site = g->d_loc_site;
     fa.loc_row = g->d_loc_row;
     fa.loc_adj = g->d_loc_adj;
-    fa.orig = g->d_orig;
+    fa.loc_id = g->d_loc_id;
     fa.x0 = static_cast<Real *>(c->d_x[swap ? 1 : 0]);
     fa.x1 = static_cast<Real *>(c->d_x[swap ? 0 : 1]);
     fa.y = static_cast<const Real *>(c->d_y);
@@ -3038,6 +3078,7 @@ int gmrf_graph_create(const gmrf_graph_desc *d, void *d_ws, size_t ws_bytes, hip
             place(g->d_ch_adj, g->h.ch_adj);
             place(g->d_ch_meta, g->h.ch_meta);
             place(g->d_loc_site, g->h.loc_site);
+            place(g->d_loc_id, g->h.loc_id);
             place(g->d_loc_row, g->h.loc_row);
             place(g->d_loc_adj, g->h.loc_adj);
         }

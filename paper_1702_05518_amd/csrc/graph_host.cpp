@@ -409,6 +409,8 @@ void build_chunks(HostGraph *g, const std::vector<int32_t> &cell)
     const int64_t n = g->n;
     const int32_t k = g->k;
     g->chunks_ok = false;
+    if (k > kFusedMaxColors)
+        return;
     g->nchunks = 1 + *std::max_element(cell.begin(), cell.end());
     std::vector<int32_t> colpos(n), chunk(n);
     for (int32_t c = 0; c < k; ++c)
@@ -434,6 +436,7 @@ void build_chunks(HostGraph *g, const std::vector<int32_t> &cell)
     g->ch_adj.assign(1, 0);
     g->ch_meta.clear();
     g->loc_site.clear();
+    g->loc_id.clear();
     g->loc_row.clear();
     g->loc_adj.clear();
     g->max_local = g->max_r = g->max_adj = 0;
@@ -507,6 +510,10 @@ void build_chunks(HostGraph *g, const std::vector<int32_t> &cell)
         g->ch_meta.insert(g->ch_meta.end(), ostart.begin(), ostart.end());
         g->loc_site.insert(g->loc_site.end(), R.begin(), R.end());
         g->loc_site.insert(g->loc_site.end(), H.begin(), H.end());
+        for (int32_t u : R)
+            g->loc_id.push_back((uint32_t)g->orig_of_slab[u]);
+        for (int32_t v : H)
+            g->loc_id.push_back((uint32_t)g->orig_of_slab[v]);
         uint16_t off = 0;
         for (int32_t u : R) {
             g->loc_row.push_back(off);
@@ -592,6 +599,7 @@ size_t graph_device_bytes(const HostGraph &g)
                  align_up(sizeof(int32_t) * g.ch_adj.size()) +
                  align_up(sizeof(int32_t) * g.ch_meta.size()) +
                  align_up(sizeof(int32_t) * g.loc_site.size()) +
+                 align_up(sizeof(uint32_t) * g.loc_id.size()) +
                  align_up(sizeof(uint16_t) * g.loc_row.size()) +
                  align_up(sizeof(uint16_t) * std::max<size_t>(g.loc_adj.size(), 1));
     return bytes;

@@ -50,29 +50,30 @@ struct HostGraph {
                                          // counts (k), first slab position of the owned run of
                                          // each color (k)
     std::vector<int32_t> loc_site;       // slab position of every staged site
+    std::vector<uint32_t> loc_id;        // original id of every staged site
     std::vector<uint16_t> loc_row;       // per chunk, |R_b| + 1 offsets into its local neighbours
     std::vector<uint16_t> loc_adj;       // local slots of the neighbours of each R_b site,
                                          // ascending original id
 };
 
 // Owned sites per chunk, and the limits of a chunk: its LDS image (staged
-// values, y and ids of the R sites, local rows and neighbours) in FP64, and
+// values, y and normal variates of the R sites, local rows and neighbours) in FP64, and
 // 16-bit local offsets.  A launch reserves the largest image part by part
 // (chunk_lds_bytes of the per-part maxima), at most kFusedLaunchLds.
 constexpr int32_t kChunkSites = 512;
 constexpr int64_t kFusedLdsBytes = 40960;
 constexpr int64_t kFusedLaunchLds = 65536;
 constexpr int64_t kMaxLocalAdj = 65535;
+constexpr int32_t kFusedMaxColors = 32;  // colorings with more colors sweep by color passes
 
 // Bytes of a chunk's LDS image with real_bytes-byte values (the layout of
 // the chunked sweep kernel: values of the staged sites, then y and the
-// original id of each R site, then the R sites' local row offsets and
-// neighbours, each part 16-byte aligned).
+// sweep's normal variate of each R site, then the R sites' local row offsets
+// and neighbours, each part 16-byte aligned).
 inline int64_t chunk_lds_bytes(int64_t nloc, int64_t nr, int64_t nadj, int64_t real_bytes)
 {
     auto al = [](int64_t b) { return (b + 15) / 16 * 16; };
-    return al(real_bytes * nloc) + al(real_bytes * nr) + al(4 * nr) + al(2 * (nr + 1)) +
-           al(2 * nadj);
+    return al(real_bytes * nloc) + 2 * al(real_bytes * nr) + al(2 * (nr + 1)) + al(2 * nadj);
 }
 
 // Validate a description and build its host form; returns a gmrf_status.

@@ -139,10 +139,10 @@ def test_footprint_arithmetic():
     csr = al(4 * (n + 1)) + al(4 * max(nnz, 1)) + al(4 * n)
     # a graph within one chunk: the chunk stages every site (R = all, H
     # empty), so its tables are 3 x 2 bases, 3k + 1 metadata entries, n
-    # staged sites, n + 1 local row offsets and nnz local neighbours (16 bits,
-    # each padded to a multiple of 8 entries)
+    # staged sites and their n original ids, n + 1 local row offsets and nnz
+    # local neighbours (16 bits, each padded to a multiple of 8 entries)
     p8 = lambda m: (m + 7) // 8 * 8
-    chunks = (3 * al(8) + al(4 * (3 * k + 1)) + al(4 * n) + al(2 * p8(n + 1)) +
+    chunks = (3 * al(8) + al(4 * (3 * k + 1)) + 2 * al(4 * n) + al(2 * p8(n + 1)) +
               al(2 * max(p8(nnz), 1)))
     assert fp == csr + chunks
     d = gmrf._Desc(lattice=(64, 64, 4))
