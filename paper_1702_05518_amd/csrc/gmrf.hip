@@ -1414,9 +1414,14 @@ __device__ __forceinline__ void csr_fused_block(const FusedArgs<Real> &fa, const
     // positions load beside the fold's partials
     auto stage = [&](const int base, const bool first) {
         int p[kFusedCH];
+        unsigned id[kFusedCH];
 #pragma unroll
-        for (int j = 0; j < kFusedCH; ++j)
-            p[j] = site[min(base + (int)threadIdx.x + j * kThreads, nloc - 1)];
+        for (int j = 0; j < kFusedCH; ++j) {
+            const int s = min(base + (int)threadIdx.x + j * kThreads, nloc - 1);
+            p[j] = site[s];
+            if constexpr (sizeof(Real) == 4)
+                id[j] = sid[s];
+        }
         if (first && fold)
             fold_partials<kFoldUnroll>(a, partials_of(a, rel - 1), fl);
         Real xv[kFusedCH], yv[kFusedCH];
@@ -1424,6 +1429,16 @@ __device__ __forceinline__ void csr_fused_block(const FusedArgs<Real> &fa, const
         for (int j = 0; j < kFusedCH; ++j) {
             xv[j] = src[p[j]];
             yv[j] = fa.y[p[j]];
+        }
+        if constexpr (sizeof(Real) == 4) {
+            // FP32: the batch's variates while its gathers are in flight (the
+            // FP64 draw needs more registers than this point has spare)
+#pragma unroll
+            for (int j = 0; j < kFusedCH; ++j) {
+                const int s = base + (int)threadIdx.x + j * kThreads;
+                if (s < nr)
+                    zs[s] = site_normal<Real>(draw_words(a.seed, id[j], t, a.instance, 0u));
+            }
         }
 #pragma unroll
         for (int j = 0; j < kFusedCH; ++j) {
@@ -1437,9 +1452,10 @@ __device__ __forceinline__ void csr_fused_block(const FusedArgs<Real> &fa, const
     stage(0, true);
     for (int base = kFusedCH * kThreads; base < nloc; base += kFusedCH * kThreads)
         stage(base, false);
-    // the variates of the R sites
-    for (int s = (int)threadIdx.x; s < nr; s += kThreads)
-        zs[s] = site_normal<Real>(draw_words(a.seed, sid[s], t, a.instance, 0u));
+    // the variates of the R sites (FP64)
+    if constexpr (sizeof(Real) == 8)
+        for (int s = (int)threadIdx.x; s < nr; s += kThreads)
+            zs[s] = site_normal<Real>(draw_words(a.seed, sid[s], t, a.instance, 0u));
     // every wave's direct copies have landed (a full barrier waits for them)
     __syncthreads();
     HyperIn hin;
