@@ -152,16 +152,28 @@ int gmrf_version(void);
 
 /* ---- graphs (Sec. 2.3: coloring and the per-color site lists) ------------- */
 
-/* Device workspace bytes that gmrf_graph_create needs for d (host arithmetic
- * only; 0 for a lattice, which needs no structure on the device).  Returns 0
- * and sets the error message if d is invalid in a way visible from sizes. */
+/* Device workspace bytes that gmrf_graph_create needs for d (0 for a
+ * lattice, which needs no structure on the device).  For a general graph the
+ * call validates d and builds the host form of the graph (coloring slabs and
+ * chunk tables, see gmrf_graph_create), so it costs about as much host time
+ * as the create itself.  Returns 0 and sets the error message if d is
+ * invalid. */
 size_t gmrf_graph_footprint(const gmrf_graph_desc *d);
 
 /* Validate d and build the device form of the graph: for a general graph the
- * sites are permuted so that each color is a contiguous slab (color, then a
- * breadth-first locality order), with a permuted CSR (int32) whose neighbour
- * lists stay in ascending ORIGINAL-id order, plus the slab-to-original map.
- * The permutation is internal: results are keyed by original ids.  The
+ * sites are permuted so that each color is a contiguous slab (color, then the
+ * chunk order below), with a permuted CSR (int32) whose neighbour lists stay
+ * in ascending ORIGINAL-id order, plus the slab-to-original map.  The sites
+ * are also split into chunks of at most about 640 sites (graph-Voronoi
+ * cells: a capacity-bounded multi-source breadth-first growth from seeds
+ * placed by recursive bisection of hop-distance coordinates), and for each
+ * chunk the graph stores its closure R under lower-color neighbours, R's
+ * other neighbours, and R's adjacency in chunk-local 16-bit slots: the
+ * tables of the chunked sweep (launch shape 1; Sec. 2.3, a sweep as color
+ * phases inside each chunk).  A graph whose chunks do not fit the kernel's
+ * LDS image or 16-bit slots, or with more than 32 colors, gets no chunk
+ * tables.  The permutation is internal: results are keyed by original ids.
+ * The
  * arrays are uploaded to d_ws (ws_bytes >= gmrf_graph_footprint(d)) on stream
  * and the call synchronises the stream before returning.  Checks: CSR shape,
  * ranges, symmetry, no self loops / duplicates, proper coloring (Sec. 2.3: no
@@ -189,7 +201,11 @@ int gmrf_greedy_coloring(int64_t n, const int64_t *row_ptr, const int32_t *col_i
 /* Device workspace bytes of one chain of precision p on g. */
 size_t gmrf_chain_footprint(const gmrf_graph *g, gmrf_precision p);
 
-/* Create a chain: upload y (host, n values in original order, FP64; stored as
+/* Create a chain of the Gibbs sampler of Sec. 2.3 (Algorithm 1) for the
+ * hierarchical model of Sec. 3.1 / 3.2: y | x ~ N(beta0 1 + x, I / lam), x a
+ * CAR field with precision tau (D - rho W) (Sec. 2.1; rho = 1 the intrinsic
+ * prior of Sec. 3.1, rho < 1 the proper prior of Sec. 3.2), Gamma priors on
+ * tau and lam.  Upload y (host, n values in original order, FP64; stored as
  * FP32 for GMRF_FP32_ACC64) and x0 (host, original order, or NULL for zeros),
  * set tau = m->tau0, lam = m->lam0, sweep = 0, clear the accumulators.  seed
  * and instance key the chain's random numbers.  Synchronises the stream.
@@ -225,11 +241,13 @@ int gmrf_chain_create_binomial(const gmrf_graph *g, const gmrf_model *m, const d
  * every sweep on the device; without it they stay fixed.  GMRF_CAPTURE
  * records the nsweeps sweeps as a HIP graph the first time a (nsweeps, flags)
  * pair is seen on this chain and replays it afterwards.  No host
- * synchronisation.  Launches: a lattice sweep is one kernel, which first
- * ends the previous sweep of the call (sums its reductions and draws the
- * hyperparameters, in every block); a one-block commit kernel ends the
- * call's last sweep.  A general graph runs one kernel per color and the
- * commit kernel after every sweep.  With GMRF_WITH_HYPER a small kernel
+ * synchronisation.  Launches: a lattice sweep, and a general-graph sweep in
+ * launch shape 1 (chunked), is one kernel, which first ends the previous
+ * sweep of the call (sums its reductions and draws the hyperparameters, in
+ * every block); a one-block commit kernel ends the call's last sweep.  A
+ * general graph in shape 0 runs one kernel per color and the commit kernel
+ * after every sweep; shape 2 runs the whole call in one launch.  With
+ * GMRF_WITH_HYPER a small kernel
  * draws the rate-free parts of the hyperparameter draws (which depend only
  * on the sweep index) before every 128 sweeps.  Sec. 2.3, Algorithm 1; the
  * draws: Sec. 3.1 conjugate conditionals. */
@@ -252,7 +270,7 @@ int gmrf_sweep(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t strea
  * binomial chain, whose Polya-Gamma scratch lives in its workspace, or a
  * chain whose sweep needs more than 8192 partial slots: lattices up to
  * 8192 tiles of the chain's shape, general graphs up to 8192 blocks of 256
- * sites over all colors), GMRF_E_DEVICE. */
+ * sites over all colors in shape 0 and up to 8192 chunks in shape 1), GMRF_E_DEVICE. */
 int gmrf_sweep_static(gmrf_chain *c, int32_t nsweeps, uint32_t flags, hipStream_t stream);
 
 /* Profiling form of gmrf_sweep (plain launches, no capture): the same sweeps,
@@ -281,25 +299,32 @@ int gmrf_hyper_update(gmrf_chain *c, hipStream_t stream);
 int gmrf_set_hyper(gmrf_chain *c, double tau, double lam, hipStream_t stream);
 
 /* Posterior mean S1/N and variance (S2 - S1^2/N)/(N - 1) of phi = beta0 + x
- * over the N accumulated sweeps, in original site order, FP64 (the variance
- * needs N >= 2 and the mean N >= 1 to be finite; they are computed as
- * written whatever N is).  With GMRF_PTR_HOST the
- * call synchronises and mean / var / n_acc are host pointers (n_acc may be
- * NULL); with GMRF_PTR_DEVICE mean / var are device buffers of n doubles and
- * n_acc must be NULL.  Returns GMRF_E_NUMERIC if a device draw failed. */
+ * over the N sweeps accumulated after burn-in (Sec. 3.1: posterior summaries
+ * from the draws of the chain), in original site order, FP64.  With
+ * GMRF_PTR_HOST the call synchronises, mean / var / n_acc are host pointers
+ * (n_acc may be NULL) and N < 2 is refused with GMRF_E_INVALID_ARG (nothing
+ * written).  With GMRF_PTR_DEVICE mean / var are device buffers of n
+ * doubles, n_acc must be NULL, the call is asynchronous and N is not
+ * checked: the values are computed as written, so N = 1 gives an infinite
+ * or NaN variance and N = 0 NaN means.  Returns GMRF_E_NUMERIC if a device
+ * draw failed. */
 int gmrf_posterior_stats(gmrf_chain *c, double *mean, double *var, int64_t *n_acc,
                          uint32_t flags, hipStream_t stream);
 
-/* Read the chain state: x (host, n doubles, original order), tau, lam and the
- * number of completed sweeps; any output pointer may be NULL.  Synchronises.
- * Returns GMRF_E_NUMERIC if a device draw failed. */
+/* Read the chain state, the current draw of Algorithm 1 (Sec. 2.3) and of
+ * the Sec. 3.1 hyperparameter conditionals: x (host, n doubles, original
+ * order), tau, lam and the number of completed sweeps; any output pointer
+ * may be NULL.  Synchronises.  Returns GMRF_E_NUMERIC if a device draw
+ * failed. */
 int gmrf_get_state(gmrf_chain *c, double *x, double *tau, double *lam, uint64_t *sweep,
                    hipStream_t stream);
 
-/* Overwrite the chain state (checkpoint resume, tests).  x: host, original
- * order, or NULL to keep x.  The random streams are keyed by (seed, instance,
- * sweep, site), so resuming from a saved state continues the same chain
- * bitwise.  Synchronises. */
+/* Overwrite the chain state (checkpoint resume, tests): the state of the
+ * Markov chain of Algorithm 1 (Sec. 2.3) is x, tau, lam (and beta0, see
+ * gmrf_set_intercept) after a completed sweep.  x: host, original order, or
+ * NULL to keep x.  The random streams are keyed by (seed, instance, sweep,
+ * site), so resuming from a saved state continues the same chain bitwise.
+ * Synchronises. */
 int gmrf_set_state(gmrf_chain *c, const double *x, double tau, double lam, uint64_t sweep,
                    hipStream_t stream);
 
@@ -338,16 +363,28 @@ int gmrf_set_trace(gmrf_chain *c, double *d_trace, int64_t capacity, hipStream_t
  * FP64 reductions differently (results agree to rounding, not bit for bit);
  * the draws of x are keyed by site and do not depend on the shape.
  * General graphs: shape 0 launches one kernel per color (256-thread blocks)
- * and the commit kernel; shape 2 (a field of at most 122880 bytes, at most 32
- * colors) runs the color passes and the draws in one 512-thread block with
- * the field in LDS -- all the sweeps of a call in one launch, or, for the
- * binomial model, one sweep per launch after the Polya-Gamma launches --
- * bitwise the results of shape 0.  A new general-graph chain starts with
- * shape 2 if it fits and no color has more than 1024 sites, else shape 0.
+ * and the commit kernel; shape 1 (Gaussian chains on a graph with chunk
+ * tables whose largest chunk image fits 64 KB of LDS) sweeps with one
+ * 256-thread block per chunk that stages the chunk's closure R and its
+ * other neighbours in LDS, runs every color phase of R there and writes the
+ * chunk's own sites back (sites of R outside the chunk are recomputed,
+ * bitwise as their owner computes them), one launch per sweep, the field
+ * alternating between two buffers; shape 2 (a field of at most 122880
+ * bytes, at most 32 colors) runs the color passes and the draws in one
+ * 512-thread block with the field in LDS -- all the sweeps of a call in one
+ * launch, or, for the binomial model, one sweep per launch after the
+ * Polya-Gamma launches.  Shape 2 gives bitwise the results of shape 0;
+ * shape 1 computes each site's draw the same way but groups the FP64
+ * reductions by chunk, so its chains agree with the others to rounding.  A
+ * new
+ * general-graph chain starts with shape 2 if it fits and no color has more
+ * than 1024 sites, else shape 1 if it fits, else shape 0.
  * gmrf_chain_get_tile reports the shape, the tile size (0 x 0 for a general
  * graph) and the threads per block; any output pointer may be NULL.
- * gmrf_chain_set_tile drops the chain's captured sweeps; a batch keeps the
- * shapes its chains had when it was created (shape 2 is batched as shape 0).
+ * gmrf_chain_set_tile drops the chain's captured sweeps and, when the chain
+ * moves to or from shape 1 with the field in the other buffer, copies the
+ * field over (synchronising the device); a batch keeps the shapes its chains
+ * had when it was created (shape 2 is batched as shape 0).
  * For a shape-2 chain gmrf_sweep_timed reports the duration of the single
  * launch (draws included) as both kernel and span time (binomial: the
  * Polya-Gamma launches and the one-block launch of each sweep).  Host-only
@@ -356,9 +393,10 @@ int gmrf_chain_get_tile(const gmrf_chain *c, int32_t *tile, int32_t *tile_rows, 
                         int32_t *threads);
 int gmrf_chain_set_tile(gmrf_chain *c, int32_t tile);
 
-/* Autotune the tile shape of a lattice chain: time `reps` (1 .. 100000)
- * whole sweeps (draws included) of each shape that fits the lattice on the
- * chain itself and keep the fastest.  The timed sweeps run in a dry mode:
+/* Autotune the launch shape of a chain (a lattice, or a Gaussian chain on a
+ * general graph; not binomial chains): time `reps` (1 .. 100000) whole
+ * sweeps (draws included) of each shape that fits on the chain itself and
+ * keep the fastest.  The timed sweeps run in a dry mode:
  * the draws are computed but not stored, and an accumulating chain's
  * accumulator updates go to its statistics scratch (the same memory traffic),
  * so only scratch (the other state buffer, the partial slots, the statistics
@@ -388,13 +426,14 @@ size_t gmrf_batch_footprint(gmrf_chain *const *chains, int32_t count);
 
 /* Group `count` distinct chains of one precision, each on its own graph or
  * sharing graphs, so that gmrf_batch_sweep advances all of them with shared
- * launches: one lattice launch per stencil covering the tiles of every
- * lattice chain (each lattice chain's sweep kernel ends its previous sweep),
- * one launch per color index covering that color's slab of every
- * general-graph chain followed by one commit launch with a block per
- * general-graph chain, and at the end of the call one commit launch with a
- * block per lattice chain (Sec. 2.3, Algorithm 1, for every chain; the
- * independent chains need no
+ * launches per sweep: one lattice launch per stencil covering the tiles of
+ * every lattice chain, one chunked launch (per intercept setting) covering
+ * the chunks of every shape-1 general-graph chain (these chains' sweep
+ * kernels end their previous sweep), one launch per color index covering
+ * that color's slab of every other general-graph chain followed by one
+ * commit launch with a block per such chain, and at the end of the call one
+ * commit launch with a block per one-launch (lattice or shape-1) chain
+ * (Sec. 2.3, Algorithm 1, for every chain; the independent chains need no
  * communication).  Each chain keeps its own workspace, state, reductions and
  * random streams, so its results equal those of gmrf_sweep on that chain bit
  * for bit.  The tables are uploaded to d_ws (ws_bytes >=

@@ -230,7 +230,11 @@ class Chain:
         self.k = int(self.color.max()) + 1 if n else 0
         self.y = np.ascontiguousarray(y, dtype=np.float64).copy()
         if rank is None:
-            rank = n - components(self.row_ptr, self.col) if rho == 1.0 else n
+            # rank of D - rho W (Sec. 2.1, Sec. 3.2): n minus the number of
+            # connected components for the intrinsic prior (rho = 1); for the
+            # proper prior (rho < 1) only the rows of isolated sites vanish
+            isolated = int(np.count_nonzero(np.diff(self.row_ptr) == 0))
+            rank = (n - components(self.row_ptr, self.col) if rho == 1.0 else n - isolated)
         self.rank = int(rank)
         self.x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
         self.s1 = np.zeros(n)

@@ -1963,7 +1963,8 @@ struct gmrf_batch {
     std::vector<int> csr_color_off[2];            // per color index: first block
     SweepArgs *unit_args = nullptr;               // per chain, for the unit-variate launches
     SweepArgs *csr_commit = nullptr;              // general-graph chains: commit every sweep
-    SweepArgs *lat_commit = nullptr;              // lattice chains: commit at the end of a call
+    SweepArgs *lat_commit = nullptr;              // one-launch chains (lattices, chunked
+                                                  // general graphs): commit at a call's end
     int n_csr = 0, n_lat = 0;
     char *ws = nullptr;                           // the caller's workspace (job tables)
     hipStream_t capture_stream = nullptr;
@@ -2902,7 +2903,7 @@ void launch_batch_sweeps(const gmrf_batch *b, int nsweeps, unsigned flags, hipSt
             hipLaunchKernelGGL(commit_batch_kernel, dim3((unsigned)b->n_csr),
                                dim3(kFinishThreads), 0, s, b->csr_commit, 0, 1, hyper);
     }
-    if (b->n_lat > 0 && nsweeps > 0)   // lattices: the call's last sweep
+    if (b->n_lat > 0 && nsweeps > 0)   // one-launch chains: the call's last sweep
         hipLaunchKernelGGL(commit_batch_kernel, dim3((unsigned)b->n_lat), dim3(kFinishThreads), 0,
                            s, b->lat_commit, nsweeps - 1, nsweeps, hyper);
 }
@@ -3205,7 +3206,10 @@ static int chain_create_impl(const char *who, const gmrf_graph *g, const gmrf_mo
     if (binomial && is_lattice(g))
         return fail(GMRF_E_INVALID_ARG, w + ": the binomial model needs a general (CSR) graph");
     const int64_t n = g->h.n;
-    const int64_t rank = g->h.rho == 1.0 ? n - g->h.components : n;
+    // rank of D - rho W (Sec. 2.1, Sec. 3.2): one null direction per connected
+    // component for rho = 1; for rho < 1 the rows of isolated sites are zero
+    // and every other row block is nonsingular
+    const int64_t rank = g->h.rho == 1.0 ? n - g->h.components : n - g->h.isolated;
     const double shape_tau = m->a_tau + 0.5 * (double)rank, shape_lam = m->a_lam + 0.5 * (double)n;
     if (!(m->b_tau > 0.0) || !(shape_tau >= 1.0) || !std::isfinite(m->a_tau) ||
         !std::isfinite(m->b_tau) ||
@@ -3534,6 +3538,17 @@ int gmrf_posterior_stats(gmrf_chain *c, double *mean, double *var, int64_t *n_ac
     double *dv = flags == GMRF_PTR_DEVICE ? var : c->d_stats + n;
     const int blocks = elementwise_blocks(n);
     const int *orig = is_lattice(c->g) ? nullptr : c->g->d_orig;
+    DevState st;
+    if (flags == GMRF_PTR_HOST) {      // the host form checks N first
+        int rc = read_state(c, &st, stream);
+        if (rc == GMRF_OK)
+            rc = check_status(st);
+        if (rc != GMRF_OK)
+            return rc;
+        if (st.n_acc < 2)
+            return fail(GMRF_E_INVALID_ARG, "posterior_stats: " + std::to_string(st.n_acc) +
+                                                " accumulated sweeps; the variance needs 2");
+    }
     hipLaunchKernelGGL(stats_kernel, dim3(blocks), dim3(kThreads), 0, stream, c->d_s1, c->d_s2,
                        orig, (long long)n, c->d_state, dm, dv);
     GMRF_HIP(hipGetLastError());
@@ -3541,10 +3556,7 @@ int gmrf_posterior_stats(gmrf_chain *c, double *mean, double *var, int64_t *n_ac
         return GMRF_OK;
     GMRF_HIP(hipMemcpyAsync(mean, dm, 8 * n, hipMemcpyDeviceToHost, stream));
     GMRF_HIP(hipMemcpyAsync(var, dv, 8 * n, hipMemcpyDeviceToHost, stream));
-    DevState st;
-    int rc = read_state(c, &st, stream);
-    if (rc != GMRF_OK)
-        return rc;
+    GMRF_HIP(hipStreamSynchronize(stream));
     if (n_acc)
         *n_acc = st.n_acc;
     return check_status(st);

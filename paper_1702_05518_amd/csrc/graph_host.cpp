@@ -567,6 +567,7 @@ int build_lattice(const gmrf_graph_desc *d, HostGraph *g)
     g->cols = (int32_t)cols;
     g->stencil = d->lat_stencil;
     g->components = 1;   // both stencils connect every lattice
+    g->isolated = d->n == 1 ? 1 : 0;
     const int64_t horiz = rows * (cols - 1), vert = (rows - 1) * cols;
     const int64_t diag = d->lat_stencil == 8 ? 2 * (rows - 1) * (cols - 1) : 0;
     g->nnz = 2 * (horiz + vert + diag);
@@ -672,6 +673,9 @@ int build_host_graph(const gmrf_graph_desc *d, HostGraph *g)
     g->stencil = 0;
     std::vector<int64_t> rpv(rp, rp + n + 1);
     g->components = count_components(n, rpv, col);
+    g->isolated = 0;
+    for (int64_t i = 0; i < n; ++i)
+        g->isolated += rp[i + 1] == rp[i];
 
     // Color slabs.  Inside a slab the sites follow the locality order of the
     // chunks (chunk_cells), so the threads of one wavefront touch nearby

@@ -21,12 +21,13 @@ struct HostGraph {
     int64_t n = 0;
     int32_t k = 0;
     int64_t components = 0;
+    int64_t isolated = 0;         // sites without neighbours
     int64_t nnz = 0;              // directed adjacency entries (2 |E|)
     double rho = 1.0;
     int32_t rows = 0, cols = 0;   // lattice shape
     int32_t stencil = 0;          // 0 = general graph, 4 or 8 = lattice
-    // General graphs: sites permuted into color slabs (color, then a
-    // breadth-first locality order).  slab_offsets[c] .. slab_offsets[c+1] is
+    // General graphs: sites permuted into color slabs (color, then the
+    // chunk order).  slab_offsets[c] .. slab_offsets[c+1] is
     // color c.
     std::vector<int32_t> slab_offsets;   // k + 1
     std::vector<int32_t> orig_of_slab;   // slab position -> original id

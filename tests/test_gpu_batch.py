@@ -150,16 +150,16 @@ def test_batch_autotune_keeps_state_and_equality(G, prec):
     batch.sweep(3, capture=True)
     for t in twins:
         t.sweep(3)
-    before = [(c.get_state(), c.posterior_stats()) for c in chains]
+    before = [(c.get_state(), c.get_accumulators()) for c in chains]
     best, us = batch.autotune(reps=3)
     assert best in (0, 1) and us[0] > 0.0 and us[1] > 0.0
     assert best == (1 if us[1] < us[0] else 0)
     for c, (st, ps) in zip(chains, before):
-        st2, ps2 = c.get_state(), c.posterior_stats()
+        st2, ps2 = c.get_state(), c.get_accumulators()
         assert np.array_equal(st[0], st2[0]) and st[1:] == st2[1:]
-        # one accumulated sweep so far: the variance is NaN (N - 1 = 0) on both sides
-        assert np.array_equal(ps[0], ps2[0]) and ps[2] == ps2[2] == 1
-        assert np.array_equal(ps[1], ps2[1], equal_nan=True)
+        # one accumulated sweep so far (too few for posterior_stats' variance)
+        assert np.array_equal(ps[0], ps2[0]) and np.array_equal(ps[1], ps2[1])
+        assert ps[2] == ps2[2] == 1
     for c, t, (g, _) in zip(chains, twins, wls):
         if g.lattice is not None:
             assert c.tile[0] == best

@@ -287,17 +287,20 @@ def test_device_pointer_stats(G, orc):
     assert np.array_equal(m.cpu().numpy(), mean) and np.array_equal(v.cpu().numpy(), var)
 
 
+@pytest.mark.parametrize("rho", [1.0, 0.9])
 @pytest.mark.parametrize("shape", [0, 1, 2])
-def test_isolated_sites_and_empty_color(G, orc, shape):
-    # 3 components (one isolated site) and a coloring that leaves color 2 empty
+def test_isolated_sites_and_empty_color(G, orc, shape, rho):
+    # 3 components (one isolated site) and a coloring that leaves color 2
+    # empty; with rho < 1 the tau shape's rank is n minus the isolated sites
     rp, cl = inputs.edges_to_csr(6, [0, 1, 3], [1, 2, 4])
     color = np.array([0, 1, 0, 0, 1, 3], dtype=np.int32)
     y = np.array([0.1, 0.5, -0.2, 1.0, 0.3, -0.7])
-    g = G.Graph(row_ptr=rp, col_idx=cl, color=color, num_colors=4)
+    g = G.Graph(row_ptr=rp, col_idx=cl, color=color, num_colors=4, rho=rho)
     assert g.components == 3
     ch = G.Chain(g, y, seed=4)
     ch.set_tile(shape)
-    oc = orc.Chain(rp, cl, color, y, seed=4)
+    oc = orc.Chain(rp, cl, color, y, seed=4, rho=rho)
+    assert oc.rank == (3 if rho == 1.0 else 5)
     ch.sweep(25)
     oc.sweeps(25)
     x, tau, lam, _ = ch.get_state()
@@ -323,8 +326,8 @@ def test_chain_argument_errors(G):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_lattice_checkpoint_resume_and_burn_in(G, orc, prec):
-    """Lattice chains add a sweep's x to the sums one sweep late; reading or
-    replacing the state or the sums must give exactly the immediate sums."""
+    """Reading the state and the sums part way, and resuming a new chain from
+    them, continues the same chain exactly, across the burn-in boundary."""
     wl = lattice_case(70, 90, 8)
     p = G.FP64 if prec == "fp64" else G.FP32_ACC64
     g = gpu_graph(G, wl)
@@ -509,3 +512,32 @@ def test_csr_autotune_leaves_state_unchanged(G, orc):
     for c in (ch, twin):
         x, tau, lam, _ = c.get_state()
         assert rel(x, oc.x) <= RTOL64 and rel(tau, oc.tau) <= RTOL64
+
+
+@pytest.mark.gpu
+def test_posterior_stats_needs_two_accumulated_sweeps(G):
+    """The host form of gmrf_posterior_stats refuses N < 2 accumulated sweeps
+    (burn-in not yet passed, or one sweep); the device form computes the
+    values as written (N = 1: the variance divides by zero)."""
+    import torch
+    wl = lattice_case(16, 16, 4)
+    g = G.Graph(lattice=(16, 16, 4))
+    ch = G.Chain(g, wl["y"], precision=G.FP64, seed=2, burn_in=5)
+    ch.sweep(5)                                    # all burn-in: N = 0
+    with pytest.raises(G.GmrfError) as e:
+        ch.posterior_stats()
+    assert e.value.status == G.E_INVALID_ARG and "accumulated" in G.last_error()
+    ch.sweep(1)                                    # N = 1
+    with pytest.raises(G.GmrfError):
+        ch.posterior_stats()
+    mean = torch.empty(ch.n, dtype=torch.float64, device="cuda")
+    var = torch.empty_like(mean)
+    ch.posterior_stats_device(mean, var)
+    torch.cuda.synchronize()
+    s1, _, nacc = ch.get_accumulators()
+    assert nacc == 1
+    assert np.array_equal(mean.cpu().numpy(), s1)       # a lattice: no permutation
+    assert not np.isfinite(var.cpu().numpy()).any()
+    ch.sweep(1)                                    # N = 2
+    m, v, n = ch.posterior_stats()
+    assert n == 2 and np.isfinite(m).all() and np.isfinite(v).all()

@@ -253,6 +253,22 @@ def test_rank_of_intrinsic_prior(orc):
     assert orc.Chain(rp2, cl2, np.array([0, 1, 0, 0, 1, 0]), np.zeros(6)).rank == 3
 
 
+@pytest.mark.parametrize("rho", [1.0, 0.9, 0.5])
+def test_rank_matches_the_dense_precision(orc, rho):
+    """The tau shape's r is the rank of D - rho W (Sec. 2.1; proper prior of
+    Sec. 3.2): numpy's SVD rank of the dense matrix, on graphs with isolated
+    sites and several components."""
+    cases = [inputs.edges_to_csr(6, [0, 1, 3], [1, 2, 4]),        # site 5 isolated
+             inputs.edges_to_csr(9, [0, 2, 2, 6], [1, 3, 4, 7]),  # sites 5, 8 isolated
+             inputs.lattice_csr(4, 5, 8)]
+    for rp, cl in cases:
+        color, _ = orc.greedy_coloring(rp, cl)
+        W = dense_W(rp, cl)
+        R = np.diag(W.sum(1)) - rho * W
+        ch = orc.Chain(rp, cl, color, np.zeros(rp.size - 1), rho=rho)
+        assert ch.rank == np.linalg.matrix_rank(R)
+
+
 # --------------------------------------------------------------------------
 # distributional pins (fixed tau, lam)
 # --------------------------------------------------------------------------
