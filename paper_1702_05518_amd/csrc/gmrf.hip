@@ -2009,6 +2009,13 @@ bool tile_fits(const HostGraph &h, int k)
 
 bool is_lattice(const gmrf_graph *g) { return g->h.stencil != 0; }
 
+// One-launch sweeps: lattices and chunked general graphs sweep in one kernel
+// whose blocks can end the previous sweep of the call themselves.  Each block
+// then sums every partial slot, so that is done only up to kDeferredMaxSlots
+// slots; beyond, each sweep ends in its own one-block commit launch.
+constexpr int kDeferredMaxSlots = 2048;
+bool one_launch(const gmrf_chain *c) { return is_lattice(c->g) || c->lat_tile == kFused; }
+
 size_t real_size(gmrf_precision p) { return p == GMRF_FP64 ? 8 : 4; }
 
 int lattice_blocks(const HostGraph &h, int k)
@@ -2147,7 +2154,7 @@ SweepArgs make_args(const gmrf_chain *c, unsigned flags)
     a.n_sites = (double)c->g->h.n;
     a.units = c->d_units;
     a.slot_stride = c->slot_stride;
-    a.deferred = is_lattice(c->g) || c->lat_tile == kFused ? 1 : 0;
+    a.deferred = one_launch(c) && c->total_slots <= kDeferredMaxSlots ? 1 : 0;
     return a;
 }
 
@@ -2459,7 +2466,7 @@ void launch_sweep_kernels(const gmrf_chain *c, const SweepArgs &a, hipStream_t s
                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
     const bool f64 = c->prec == GMRF_FP64;
-    if (a.dry)
+    if (a.dry || !a.deferred)   // every sweep committed on its own: relative sweep 0
         rel = 0;
     const int fold = rel > 0 ? 1 : 0;
     if (is_lattice(c->g)) {
@@ -2665,7 +2672,9 @@ void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im, int 
     std::vector<FusedJob<Real>> fjobs[2];
     std::vector<FusedBlock> fblocks[2];
     for (const gmrf_chain *c : cs) {
-        const SweepArgs a = make_args(c, 0u);
+        SweepArgs a = make_args(c, 0u);
+        if (one_launch(c))
+            a.deferred = 1;     // shared launches end every one-launch chain's sweep in the next
         units.push_back(a);
         const HostGraph &h = c->g->h;
         const int g = c->model.intercept ? 1 : 0;

@@ -9,6 +9,9 @@
 * 4096 x 4096, 8 neighbours (4096 tiles, more than the blocks the chip
   holds at once, and a working set beyond the 256 MB Infinity Cache): one
   FP64 sweep from an injected state against one oracle sweep over every site.
+* 1500 x 1500, 8 neighbours, in 32 x 32 tiles (2209 tiles: every sweep ends
+  in its own commit launch) and in 64 x 64 tiles: six sweeps against the
+  oracle, FP64 and FP32.
 * Delaunay graph with 1,000,000 sites: one FP64 sweep from an injected
   state against one oracle sweep over every site; the configured 2000-sweep
   run in FP32 and FP64 against the stored FP64 oracle reference
@@ -127,6 +130,39 @@ def test_lattice4096_one_sweep_fp64_all_sites(G, orc):
     assert rel(x, oc.x) <= 1e-12
     assert rel(q, oc.q) <= 1e-12 and rel(sse, oc.sse) <= 1e-12
     assert rel(tau, oc.tau) <= 1e-12 and rel(lam, oc.lam) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_lattice_many_tiles_sweeps_commit_each(G, orc, prec):
+    """A lattice with more tiles (2209 of 32 x 32) than a block sums when it
+    ends the previous sweep itself: every sweep ends in its own commit
+    launch.  Six sweeps with the hyperparameter draws, every site and tau /
+    lam against the oracle (FP64 1e-12; FP32 state: field 1e-4, tau / lam
+    1e-4 relative), and the same chain in 64 x 64 tiles (576 tiles, the
+    previous sweep ended inside the next sweep's kernel) agreeing to
+    rounding."""
+    wl = inputs.lattice_workload(1500, 1500, 8, noise_sd=0.1, data_seed=5)
+    n = wl["n"]
+    p = G.FP64 if prec == "fp64" else G.FP32_ACC64
+    g = G.Graph(lattice=(1500, 1500, 8))
+    out = {}
+    for shape in (1, 0):
+        ch = G.Chain(g, wl["y"], precision=p, seed=6, burn_in=2)
+        ch.set_tile(shape)
+        ch.sweep(4)
+        ch.sweep(2, capture=True)
+        x, tau, lam, sw = ch.get_state()
+        s1, _, nacc = ch.get_accumulators()
+        assert sw == 6 and nacc == 4
+        out[shape] = (x, tau, lam, s1)
+    oc = orc.Chain(wl["row_ptr"], wl["col"], wl["color"], wl["y"], seed=6, burn_in=2)
+    oc.sweeps(6, nthreads=THREADS)
+    tol = 1e-12 if prec == "fp64" else 1e-4
+    for shape in (1, 0):
+        x, tau, lam, s1 = out[shape]
+        assert np.max(np.abs(x - oc.x)) <= tol * max(1.0, float(np.max(np.abs(oc.x))))
+        assert rel(tau, oc.tau) <= tol and rel(lam, oc.lam) <= tol
+        assert np.max(np.abs(s1 - oc.s1)) <= 4 * tol * max(1.0, float(np.max(np.abs(oc.s1))))
 
 
 def test_delaunay_1m_one_sweep_fp64_all_sites(G, orc):
