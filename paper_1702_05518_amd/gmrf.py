@@ -369,8 +369,9 @@ class Chain:
     @property
     def tile(self):
         """(shape index, tile rows, tile cols, threads).  Lattices: shapes 0, 1
-        (64x64 / 32x32 tiles) and 2 (one persistent block).  General graphs:
-        0 (one launch per color; tile 0 x 0) or 2 (one block, field in LDS)."""
+        (64x64 / 32x32 tiles) and 2 (one persistent block).  General graphs
+        (tile 0 x 0): 0 (one launch per color), 1 (chunks staged in LDS, one
+        launch per sweep) or 2 (one block, field in LDS)."""
         k, r, c, t = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         _check(lib().gmrf_chain_get_tile(self.handle, C.byref(k), C.byref(r), C.byref(c),
                                          C.byref(t)))

@@ -43,11 +43,11 @@ def test_default_shapes(G):
     color, k = G.greedy_coloring(wl["row_ptr"], wl["col"])
     csr = G.Chain(G.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color, num_colors=k,
                           rho=0.95), wl["y"])
-    assert csr.tile == (2, 0, 0, 512)          # the field fits in LDS: one block
+    assert csr.tile == (1, 0, 0, 256)          # chunks, one launch per sweep (the default)
     csr.set_tile(0)
     assert csr.tile == (0, 0, 0, 256)          # one launch per color
-    csr.set_tile(1)
-    assert csr.tile == (1, 0, 0, 256)          # chunks, one launch per sweep
+    csr.set_tile(2)
+    assert csr.tile == (2, 0, 0, 512)          # the field fits in LDS: one block
     with pytest.raises(G.GmrfError):
         small.set_tile(2)
     best, us = csr.autotune(reps=2)
@@ -56,9 +56,8 @@ def test_default_shapes(G):
     bcolor, bk = G.greedy_coloring(big_wl["row_ptr"], big_wl["col"])
     bg = G.Graph(row_ptr=big_wl["row_ptr"], col_idx=big_wl["col"], color=bcolor, num_colors=bk,
                  rho=0.95)
-    # 20,000 sites: color slabs beyond two rounds of the block, so the chunked
-    # one-launch sweep by default; FP64 (160 KB) does not fit in LDS, FP32
-    # (80 KB) does
+    # 20,000 sites: the chunked one-launch sweep by default; for the one-block
+    # shape FP64 (160 KB) does not fit in LDS, FP32 (80 KB) does
     c64 = G.Chain(bg, big_wl["y"])
     c32 = G.Chain(bg, big_wl["y"], precision=G.FP32_ACC64)
     assert c64.tile[0] == 1 and c32.tile[0] == 1
