@@ -51,6 +51,7 @@ SWEEP_KERNEL = "lattice_sweep_kernel<float, LatCfg<8, 64, 64, 512, 4>, false>"
 PROFILES = os.path.join(ROOT, "profiles")
 TRACE_SUMMARY = os.path.join(PROFILES, "lattice_sweep_2048x2048_s8_kernel_trace.md")
 TRAFFIC_SUMMARY = os.path.join(PROFILES, "lattice_sweep_2048x2048_s8_fp32_traffic.md")
+TRAFFIC_SUMMARY_BIG = os.path.join(PROFILES, "lattice_sweep_8192x8192_s8_fp32_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1702_05518_amd", "csrc", f)
                   for f in ("gmrf.hip", "rng.hpp")]
 
@@ -81,6 +82,135 @@ def profile_figures(path):
     except OSError:
         pass
     return None
+
+
+def _csv_rows(path):
+    import csv
+
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _short(name, width=110):
+    name = name.replace("gmrf::", "")
+    return name if len(name) <= width else name[:width - 3] + "..."
+
+
+def trace_summary(trace_csv, commands):
+    """Markdown summary of a rocprofv3 kernel trace (kernel_trace.csv): one
+    row per kernel and launch size (workgroups), durations in ns, and a
+    "json:" line with the sweep kernel's figures at the benchmark's size."""
+    groups = {}
+    total = 0
+    for r in _csv_rows(trace_csv):
+        if r["Kind"] != "KERNEL_DISPATCH":
+            continue
+        wg = int(r["Workgroup_Size_X"]) * int(r["Workgroup_Size_Y"]) * int(r["Workgroup_Size_Z"])
+        blocks = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]) // wg
+        d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        total += d
+        groups.setdefault((r["Kernel_Name"], blocks, wg), []).append(d)
+    rows = sorted(groups.items(), key=lambda kv: -sum(kv[1]))
+    out = ["# Kernel trace: " + commands[0].split(" -- ", 1)[-1], "",
+           "Commands (from the repository root on the GPU box):", "", "```", *commands, "```", "",
+           "Per kernel and launch size (workgroups x threads), durations in ns:", "",
+           "| Kernel | Workgroups x threads | Calls | Average | Min | Max | % of GPU time |",
+           "|---|---|---|---|---|---|---|"]
+    for (name, blocks, wg), ds in rows[:16]:
+        out.append(f"| `{_short(name)}` | {blocks} x {wg} | {len(ds)} | {np.mean(ds):.0f} | "
+                   f"{min(ds)} | {max(ds)} | {100.0 * sum(ds) / total:.2f} |")
+    key = [k for k in groups if SWEEP_KERNEL.replace(" ", "") in
+           k[0].replace("gmrf::", "").replace(" ", "") and k[1] == (ROWS // 64) * (COLS // 64)]
+    fig = None
+    if key:
+        ds = groups[key[0]]
+        fig = {"kernel": SWEEP_KERNEL, "workgroups": key[0][1], "calls": len(ds),
+               "avg_ns": float(np.mean(ds)), "kernel_sources_sha256": kernel_sources_sha256()}
+    return "\n".join(out), fig
+
+
+def traffic_summary(fetch_csv, write_csv, dram_csv, side, commands):
+    """Markdown summary of the counter probes (bench.py --probe): FETCH_SIZE
+    and WRITE_SIZE of the sweep kernel at side x side, each scaled by the
+    counter's reading for the probe's 512 MiB device copy, and, from a third
+    run, the share of the L2's read and write requests that went to DRAM."""
+    def per_kernel(path, counter):
+        copy, sweep = [], []
+        for r in _csv_rows(path):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"])
+            if r["Kernel_Name"] == "__amd_rocclr_copyBuffer":
+                copy.append(v)
+            elif "lattice_sweep_kernel<float" in r["Kernel_Name"]:
+                sweep.append(v)
+        return max(copy), sweep
+
+    copy_kib = 512 * 1024
+    f_copy, f_sweep = per_kernel(fetch_csv, "FETCH_SIZE")
+    w_copy, w_sweep = per_kernel(write_csv, "WRITE_SIZE")
+    f_scale, w_scale = copy_kib / f_copy, copy_kib / w_copy
+    fetch_b = float(np.mean(f_sweep)) * f_scale * 1024
+    write_b = float(np.mean(w_sweep)) * w_scale * 1024
+    n = side * side
+    alg = BYTES_PER_SITE["fp32_acc"] * n
+    out = [f"# HBM traffic counters: FP32 lattice sweep kernel, {side}x{side}, 8 neighbours", "",
+           "Commands (from the repository root on the GPU box):", "", "```", *commands, "```", "",
+           "`bench.py --probe` first copies 512 MiB device-to-device (one dispatch of the "
+           "runtime's `__amd_rocclr_copyBuffer`), which must read and write exactly 524288 "
+           "KiB: its readings give each counter's scale.", "",
+           "| Quantity | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) |", "|---|---|---|",
+           f"| 512 MiB copy, counter | {f_copy:.1f} | {w_copy:.1f} |",
+           f"| scale factor = 524288 / counter | {f_scale:.3f} | {w_scale:.3f} |",
+           f"| sweep kernel, counter, mean of {len(f_sweep)} launches | "
+           f"{np.mean(f_sweep):.1f} | {np.mean(w_sweep):.1f} |",
+           f"| sweep kernel, scaled, MB per launch | {fetch_b / 1e6:.1f} | {write_b / 1e6:.1f} |",
+           "", f"Scaled traffic per launch: {(fetch_b + write_b) / 1e6:.1f} MB, against "
+           f"{alg / 1e6:.1f} MB of algorithmic bytes (44 B per site).", ""]
+    fig = {"kernel": SWEEP_KERNEL, "side": side, "bytes_per_launch": fetch_b + write_b,
+           "fetch_bytes": fetch_b, "write_bytes": write_b, "fetch_scale": f_scale,
+           "write_scale": w_scale, "kernel_sources_sha256": kernel_sources_sha256()}
+    if dram_csv:
+        tot = {}
+        for r in _csv_rows(dram_csv):
+            if "lattice_sweep_kernel<float" in r["Kernel_Name"]:
+                tot.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        rd = np.mean(tot["TCC_EA0_RDREQ_DRAM_sum"]) / np.mean(tot["TCC_EA0_RDREQ_sum"])
+        wr = np.mean(tot["TCC_EA0_WRREQ_DRAM_sum"]) / np.mean(tot["TCC_EA0_WRREQ_sum"])
+        out += ["Requests from the L2 to the fabric that went to DRAM (TCC_EA0_RDREQ_DRAM_sum / "
+                "TCC_EA0_RDREQ_sum, TCC_EA0_WRREQ_DRAM_sum / TCC_EA0_WRREQ_sum, means over the "
+                "sweep launches):", "",
+                "| | L2 requests | to DRAM | share | DRAM bytes (share x scaled bytes) |",
+                "|---|---|---|---|---|",
+                f"| reads | {np.mean(tot['TCC_EA0_RDREQ_sum']):.0f} | "
+                f"{np.mean(tot['TCC_EA0_RDREQ_DRAM_sum']):.0f} | {rd:.3f} | "
+                f"{rd * fetch_b / 1e6:.1f} MB |",
+                f"| writes | {np.mean(tot['TCC_EA0_WRREQ_sum']):.0f} | "
+                f"{np.mean(tot['TCC_EA0_WRREQ_DRAM_sum']):.0f} | {wr:.3f} | "
+                f"{wr * write_b / 1e6:.1f} MB |", ""]
+        fig.update(dram_read_share=float(rd), dram_write_share=float(wr),
+                   dram_bytes=float(rd * fetch_b + wr * write_b))
+    return "\n".join(out), fig
+
+
+def counter_summary(csvs, commands):
+    """Markdown summary of counter probes (bench.py --probe): the mean of
+    every counter over the FP32 sweep kernel's launches, per launch and per
+    wave (SQ_WAVES)."""
+    vals = {}
+    for path in csvs:
+        for r in _csv_rows(path):
+            if "lattice_sweep_kernel<float" in r["Kernel_Name"]:
+                vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    waves = np.mean(vals["SQ_WAVES"]) if "SQ_WAVES" in vals else None
+    out = [f"# Counters: FP32 lattice sweep kernel, {ROWS}x{COLS}, 8 neighbours", "",
+           "Commands (from the repository root on the GPU box):", "", "```", *commands, "```", "",
+           f"Mean over the {len(next(iter(vals.values())))} launches of the probe:", "",
+           "| Counter | Per launch | Per wave |", "|---|---|---|"]
+    for k in sorted(vals):
+        m = float(np.mean(vals[k]))
+        out.append(f"| {k} | {m:.0f} | {m / waves:.1f} |" if waves else f"| {k} | {m:.0f} | |")
+    return "\n".join(out), None
 
 
 def timed_sweeps(torch, chain, steps, capture):
@@ -215,6 +345,10 @@ def big_lattice_row(torch, gmrf, inputs, args):
            "ms_per_step": launch_s * 1e3, "achieved_gbs": gbs,
            "frac": gbs / HBM_PEAK_GBS, "copy_gbs": copy, "frac_of_copy": gbs / copy,
            "bytes_per_site": BYTES_PER_SITE["fp32_acc"]}
+    traffic = profile_figures(TRAFFIC_SUMMARY_BIG)
+    row["traffic"] = traffic["bytes_per_launch"] if traffic else None
+    row["traffic_unit"] = ("bytes/launch (rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a device "
+                           "copy's reading; every such request goes to the memory side)")
     log(f"[bench] {BIG}x{BIG}: {launch_s * 1e6:.1f} us per sweep, {gbs:.0f} GB/s "
         f"({gbs / HBM_PEAK_GBS:.3f} of peak, {gbs / copy:.3f} of a {copy:.0f} GB/s copy)")
     return row
@@ -352,23 +486,24 @@ def cpu_baseline(wl, seconds_budget=10.0):
                                         CSR_BYTES_PER_SITE["fp64_acc"] / 1e9}}
 
 
-def probe(torch, gmrf, inputs, steps):
+def probe(torch, gmrf, inputs, steps, side=ROWS):
     """A plain device copy of 512 MiB (its counters give the scale factor of
     FETCH_SIZE / WRITE_SIZE), then warm-up and `steps` FP32 sweeps, one launch
-    each, of the benchmark workload."""
+    each, of the benchmark workload (side x side, 8 neighbours)."""
     src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
-    wl = inputs.lattice_workload(ROWS, COLS, STENCIL, noise_sd=0.1, data_seed=1, with_csr=False)
-    graph = gmrf.Graph(lattice=(ROWS, COLS, STENCIL))
+    wl = inputs.lattice_workload(side, side, STENCIL, noise_sd=0.1, data_seed=1, with_csr=False)
+    graph = gmrf.Graph(lattice=(side, side, STENCIL))
     chain = gmrf.Chain(graph, wl["y"], precision=gmrf.FP32_ACC64, seed=1)
     chain.sweep(5, hyper=True)
     for _ in range(steps):
         chain.sweep(1, hyper=True)
     torch.cuda.synchronize()
-    print(json.dumps({"probe": "copy 512 MiB + sweeps", "sweeps": steps + 5}), flush=True)
+    print(json.dumps({"probe": "copy 512 MiB + sweeps", "side": side, "sweeps": steps + 5}),
+          flush=True)
 
 
 def bench_batch(torch, gmrf, inputs, args):
@@ -647,10 +782,31 @@ def main():
     ap.add_argument("--iterations", type=int, default=10_000,
                     help="image / binomial: iterations of the paper's example (default 10,000, "
                          "with the paper's burn-in fractions 4/5 and 1/2)")
+    ap.add_argument("--summarize", nargs="+", metavar="ARG",
+                    help="print a profiles/ summary: 'trace KERNEL_TRACE_CSV', 'traffic SIDE "
+                         "FETCH_CSV WRITE_CSV [DRAM_CSV]' or 'counters CSV...' (rocprofv3 "
+                         "outputs; no GPU needed)")
+    ap.add_argument("--command", action="append", default=[],
+                    help="with --summarize: a command line to record in the summary")
+    ap.add_argument("--probe-side", type=int, default=ROWS,
+                    help="lattice side of --probe (8 neighbours, FP32)")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe for rocprofv3 --pmc: a 512 MiB device copy (the "
                          "scale reference for FETCH_SIZE / WRITE_SIZE), then --steps sweeps")
     args = ap.parse_args()
+    if args.summarize:
+        kind, rest = args.summarize[0], args.summarize[1:]
+        if kind == "trace":
+            text, fig = trace_summary(rest[0], args.command)
+        elif kind == "counters":
+            text, fig = counter_summary(rest, args.command)
+        else:
+            text, fig = traffic_summary(rest[1], rest[2], rest[3] if len(rest) > 3 else None,
+                                        int(rest[0]), args.command)
+        print(text)
+        if fig:
+            print("\njson: " + json.dumps(fig))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: the benchmark runs on exactly one GPU (independent chains shard across "
               "GPUs without communication); --gpus must be 1", file=sys.stderr)
@@ -666,7 +822,7 @@ def main():
     gmrf.lib()
     n = ROWS * COLS
     if args.probe:
-        probe(torch, gmrf, inputs, args.steps)
+        probe(torch, gmrf, inputs, args.steps, args.probe_side)
         return
     if args.workload == "batch512":
         bench_batch(torch, gmrf, inputs, args)
