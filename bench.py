@@ -354,11 +354,10 @@ def big_lattice_row(torch, gmrf, inputs, args):
     return row
 
 
-def delaunay_row(torch, gmrf, inputs, args):
+def delaunay_row(torch, gmrf, inputs, args, wl):
     """The irregular workload at 1,000,000 sites (Delaunay, proper CAR rho
     0.95, greedy coloring), FP32 with FP64 accumulators and FP64."""
     log("[bench] Delaunay 1M")
-    wl = inputs.delaunay_workload(1_000_000, data_seed=3, rho=0.95)
     color, k = gmrf.greedy_coloring(wl["row_ptr"], wl["col"])
     g = gmrf.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color, num_colors=k, rho=0.95)
     n = wl["n"]
@@ -425,10 +424,11 @@ def batch_row(torch, gmrf, inputs, args, steps=None):
                                       "us_per_pass_32x32": tile_us[1]}, "_chains": chains}
 
 
-def cpu_baseline(wl, seconds_budget=10.0):
+def cpu_baseline(wl, seconds_budget=10.0, wl1m=None):
     """The oracle (C, FP64) on bounded samples: the 2048 x 2048 workload with
     every host thread (up to 16) and with one, the 64 x 64 workload in full,
-    and the irregular 15,000-site workload in full (2000 sweeps)."""
+    the irregular 15,000-site workload in full (2000 sweeps) and, given the
+    1,000,000-site workload, a bounded number of its sweeps."""
     import oracle
 
     oracle.build(force=False)
@@ -471,6 +471,13 @@ def cpu_baseline(wl, seconds_budget=10.0):
     o3.sweeps(2000, nthreads=threads)
     t_c3 = time.perf_counter() - t0
     bps = BYTES_PER_SITE["fp64_acc"]
+    big = None
+    if wl1m is not None:
+        color1m, _ = oracle.greedy_coloring(wl1m["row_ptr"], wl1m["col"])
+        o4 = oracle.Chain(wl1m["row_ptr"], wl1m["col"], color1m, wl1m["y"], rho=0.95, seed=3)
+        r4, reps4, dt4 = timed(o4, wl1m["n"], seconds_budget / 2, threads)
+        big = {"site_updates_per_s": r4, "sweeps": reps4, "seconds": dt4, "threads": threads,
+               "gbs": r4 * CSR_BYTES_PER_SITE["fp64_acc"] / 1e9}
     return {"value": rate, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{reps} FP64 sweeps (+1 untimed) of the same 2048x2048 8-neighbour "
                       f"lattice workload, C oracle with {threads} OpenMP threads on "
@@ -483,7 +490,8 @@ def cpu_baseline(wl, seconds_budget=10.0):
             "delaunay15k_2000_sweeps": {"seconds": t_c3, "threads": threads,
                                         "site_updates_per_s": 15000 * 2000 / t_c3,
                                         "gbs": 15000 * 2000 / t_c3 *
-                                        CSR_BYTES_PER_SITE["fp64_acc"] / 1e9}}
+                                        CSR_BYTES_PER_SITE["fp64_acc"] / 1e9},
+            "delaunay1m_sample": big}
 
 
 def probe(torch, gmrf, inputs, steps, side=ROWS):
@@ -936,15 +944,18 @@ def main():
         line["solve_latency_ms_1000_sweeps"]["fp64"] = {"p50": d["p50_ms"], "p99": d["p99_ms"]}
     if not args.no_big:
         line["lattice8192_out_of_cache"] = big_lattice_row(torch, gmrf, inputs, args)
+    wl1m = None
+    if not (args.no_graph and args.no_cpu):
+        wl1m = inputs.delaunay_workload(1_000_000, data_seed=3, rho=0.95)
     if not args.no_graph:
-        line["delaunay1m"] = delaunay_row(torch, gmrf, inputs, args)
+        line["delaunay1m"] = delaunay_row(torch, gmrf, inputs, args, wl1m)
     if not args.no_batch:
         row = batch_row(torch, gmrf, inputs, args)
         del row["_chains"]
         line["batch512"] = row
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(wl)
+        line["cpu_baseline"] = cpu_baseline(wl, wl1m=wl1m)
     print(json.dumps(line), flush=True)
 
 
