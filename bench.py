@@ -38,6 +38,7 @@ HBM_PEAK_GBS = 8000.0
 # write + y read + S1 / S2 read-modify-write; a general graph adds its CSR
 # row (row offset + column indices at mean degree ~6) and the slab-to-id map
 BYTES_PER_SITE = {"fp32_acc": 44, "fp64_acc": 56}
+BURN_IN_BYTES_PER_SITE = 12          # FP32 burn-in sweep: x read + x write + y read
 CSR_BYTES_PER_SITE = {"fp32_acc": 72, "fp64_acc": 84}
 METRIC = ("site-updates/s + HBM GB/s fraction per sweep; p50/p99 solve latency "
           "(FP32 vs FP64)")
@@ -876,6 +877,14 @@ def main():
         del chain
         torch.cuda.synchronize()
 
+    # burn-in sweeps (no accumulator update): x read and written, y read
+    burn = gmrf.Chain(graph, wl["y"], precision=gmrf.FP32_ACC64, seed=1, burn_in=1 << 40)
+    burn.sweep(args.warmup, hyper=True)
+    t_burn = graph_seconds(torch, lambda cap: burn.sweep(args.steps, hyper=True, capture=cap),
+                           args.steps) / args.steps
+    del burn
+    burn_gbs = BURN_IN_BYTES_PER_SITE * n / t_burn / 1e9
+    log(f"[bench] burn-in sweep: {t_burn * 1e6:.1f} us ({burn_gbs / HBM_PEAK_GBS:.3f} of peak)")
     log("[bench] host-to-host solve (FP32, 1000 sweeps)")
     host_solve_s = min(host_to_host_solve(torch, gmrf, graph, wl["y"], 1000) for _ in range(3))
     r = results["fp32_acc"]
@@ -924,6 +933,10 @@ def main():
                      "frac_kernel_rocprof": (bytes_launch / (prof["avg_ns"] * 1e-9) / 1e9 /
                                              HBM_PEAK_GBS) if prof else None,
                      "kernel_us_dispatch_events": r["kernel_disp_s"] * 1e6},
+        "burn_in_sweep": {"us": t_burn * 1e6, "bytes_per_site": BURN_IN_BYTES_PER_SITE,
+                          "achieved_gbs": burn_gbs, "frac": burn_gbs / HBM_PEAK_GBS,
+                          "covers": "FP32 sweeps before burn-in ends (no S1/S2 update), "
+                                    "graph replay"},
         "sweep_ms": {"fp32_stream": r["t_plain"] / args.steps * 1e3,
                      "fp32_graph": r["t_graph"] / args.steps * 1e3},
         "solve_latency_ms_1000_sweeps": {"fp32": {"p50": r["p50_ms"], "p99": r["p99_ms"]}},

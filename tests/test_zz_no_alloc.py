@@ -65,12 +65,16 @@ def test_static_equals_workspace_sweeps_on_consecutive_calls(G):
     assert_same(ref, st)
 
 
-def test_static_general_graph_and_fixed_hyperparameters(G):
+@pytest.mark.parametrize("shape", [0, 1, 2])
+def test_static_general_graph_and_fixed_hyperparameters(G, shape):
+    # every general-graph launch shape: color passes, chunks, one block
     wl = inputs.delaunay_workload(3000, data_seed=8, rho=0.95)
     color, k = G.greedy_coloring(wl["row_ptr"], wl["col"])
     g = G.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color, num_colors=k, rho=0.95)
     for prec in (G.FP32_ACC64, G.FP64):
         ref, st = twins(G, g, wl["y"], prec, 21)
+        ref.set_tile(shape)
+        st.set_tile(shape)
         ref.sweep(5)
         st.sweep_static(5)
         ref.sweep(3, hyper=False)
