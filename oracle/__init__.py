@@ -60,6 +60,9 @@ class _Problem(C.Structure):
         ("likelihood", C.c_int32),
         ("trials", C.POINTER(C.c_int32)),
         ("beta0_var", C.c_double),
+        ("rng_version", C.c_int32),
+        ("pair_key", C.POINTER(C.c_int32)),
+        ("pair_branch", C.POINTER(C.c_uint8)),
     ]
 
 
@@ -97,6 +100,11 @@ def lib():
         L.orc_uniform52.restype = dbl
         L.orc_normal.argtypes = [u64, u32, u32, u32, u32]
         L.orc_normal.restype = dbl
+        L.orc_normal_pair.argtypes = [u64, u32, u32, u32, u32, u32]
+        L.orc_normal_pair.restype = dbl
+        L.orc_rng_pairs.argtypes = [i64, C.POINTER(i32), i32, C.POINTER(i32),
+                                    C.POINTER(C.c_uint8)]
+        L.orc_rng_pairs.restype = i32
         L.orc_gamma.argtypes = [dbl, dbl, u64, u32, u32, u32, C.c_int, C.POINTER(dbl)]
         L.orc_gamma.restype = C.c_int
         L.orc_pg1.argtypes = [dbl, u64, u32, u32, u32, u32, C.POINTER(dbl)]
@@ -144,6 +152,27 @@ def uniform52(hi: int, lo: int) -> float:
 def normal(seed: int, c0: int, c1: int, c2: int, c3: int) -> float:
     """Box-Muller normal of the Philox block at counter (c0, c1, c2, c3)."""
     return lib().orc_normal(seed, c0, c1, c2, c3)
+
+
+def normal_pair(seed: int, key: int, branch: int, c1: int, c2: int, c3: int) -> float:
+    """Cosine (branch 0) or sine (branch 1) Box-Muller normal of the Philox
+    block at counter (key, c1, c2, c3): the version-2 site normal."""
+    return lib().orc_normal_pair(seed, key, branch, c1, c2, c3)
+
+
+def rng_pairs(color):
+    """Version-2 pairing of a coloring: (key, branch) per site, key the id
+    of the lower-ranked site of its pair within its color, branch 1 for the
+    higher-ranked site."""
+    color = np.ascontiguousarray(color, dtype=np.int32)
+    n = color.size
+    k = int(color.max()) + 1 if n else 0
+    key = np.zeros(max(n, 1), dtype=np.int32)
+    branch = np.zeros(max(n, 1), dtype=np.uint8)
+    if lib().orc_rng_pairs(n, _ptr(color, C.c_int32), k, _ptr(key, C.c_int32),
+                           _ptr(branch, C.c_uint8)) != 0:
+        raise ValueError("color outside 0 .. k-1")
+    return key[:n], branch[:n]
 
 
 def site_normals(seed: int, sweep: int, instance: int, n: int) -> np.ndarray:
@@ -217,11 +246,13 @@ class Chain:
 
     def __init__(self, row_ptr, col, color, y, rho=1.0, a_tau=1.0, b_tau=1.0, a_lam=1.0,
                  b_lam=1.0, tau0=1.0, lam0=1.0, burn_in=0, seed=1, instance=0, x0=None,
-                 rank=None, intercept=False, beta0=0.0, trials=None, beta0_var=0.0):
+                 rank=None, intercept=False, beta0=0.0, trials=None, beta0_var=0.0,
+                 rng_version=1):
         """With ``trials`` (m_i, integers >= 0) the chain samples the binomial
         logit model: y holds the successes Y_i, the Polya-Gamma psi_i of the
         last sweep are in ``psi``, and beta0_var is the prior variance of b0
-        (0 = flat)."""
+        (0 = flat).  rng_version 2 draws the site normals by the paired
+        contract (``rng_pairs``), 1 one Philox block per site."""
         self.row_ptr, self.col = _csr(row_ptr, col)
         self.n = n = self.row_ptr.size - 1
         self.color = np.ascontiguousarray(color, dtype=np.int32)
@@ -245,12 +276,23 @@ class Chain:
                        else np.zeros(1, dtype=np.int32))
         if binom and self.trials.size != n:
             raise ValueError("trials must have n entries")
+        if rng_version not in (1, 2):
+            raise ValueError("rng_version must be 1 or 2")
+        self.rng_version = int(rng_version)
+        if self.rng_version == 2:
+            self.pair_key, self.pair_branch = rng_pairs(self.color)
+        else:
+            self.pair_key = np.zeros(1, dtype=np.int32)
+            self.pair_branch = np.zeros(1, dtype=np.uint8)
+        self.pair_key = np.ascontiguousarray(self.pair_key)
+        self.pair_branch = np.ascontiguousarray(self.pair_branch)
         self._p = _Problem(n, _ptr(self.row_ptr, C.c_int64), _ptr(self.col, C.c_int32),
                            _ptr(self.color, C.c_int32), self.k, float(rho),
                            _ptr(self.y, C.c_double), a_tau, b_tau, a_lam, b_lam, self.rank,
                            int(burn_in), int(seed), int(instance), 1 if intercept else 0,
                            BINOMIAL if binom else GAUSSIAN, _ptr(self.trials, C.c_int32),
-                           float(beta0_var))
+                           float(beta0_var), self.rng_version,
+                           _ptr(self.pair_key, C.c_int32), _ptr(self.pair_branch, C.c_uint8))
         self._s = _Chain(_ptr(self.x, C.c_double), _ptr(self.s1, C.c_double),
                          _ptr(self.s2, C.c_double), float(tau0), float(lam0), 0, 0, 0.0, 0.0, 0,
                          float(beta0), _ptr(self.psi, C.c_double), 0.0)

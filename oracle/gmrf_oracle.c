@@ -59,6 +59,17 @@
  * the 64-bit seed, counter (c0, c1, c2, c3) = (site or attempt, sweep,
  * instance, tag); Box & Muller (1958) cosine branch for normals; Marsaglia &
  * Tsang (2000) for Gamma variates.
+ *
+ * Random-number contract version 2 (selectable per chain; version 1 above is
+ * the default): the sites of each color, taken in ascending original id, are
+ * paired by their rank in the color, ranks (2m, 2m + 1).  Both sites of a
+ * pair take their site normal from the one Philox block keyed by the id of
+ * the lower-ranked site: that site the cosine branch (so its value is the
+ * version-1 normal of its own id), its partner the sine branch of the same
+ * two uniforms.  A color's last site, when its count is odd, is unpaired and
+ * takes the cosine branch of its own block.  Box-Muller's two branches are
+ * independent standard normals, so the sweep's noise keeps its law; only
+ * which counter feeds which site changes.
  */
 #include <math.h>
 #include <stdint.h>
@@ -127,6 +138,52 @@ double orc_normal(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t
     u1 = orc_uniform52(w[0], w[1]);
     u2 = orc_uniform52(w[2], w[3]);
     return sqrt(-2.0 * log(u1)) * cos(ORC_TWO_PI * u2);
+}
+
+/* Version-2 site normal: the Box-Muller pair of the Philox block at counter
+ * (key, c1, c2, c3), its cosine branch (branch 0) or sine branch (branch 1). */
+double orc_normal_pair(uint64_t seed, uint32_t key, uint32_t branch, uint32_t c1, uint32_t c2,
+                       uint32_t c3)
+{
+    uint32_t w[4];
+    double u1, u2, r;
+    orc_words(seed, key, c1, c2, c3, w);
+    u1 = orc_uniform52(w[0], w[1]);
+    u2 = orc_uniform52(w[2], w[3]);
+    r = sqrt(-2.0 * log(u1));
+    return branch ? r * sin(ORC_TWO_PI * u2) : r * cos(ORC_TWO_PI * u2);
+}
+
+/* The version-2 pairing of a colored graph: key[i] is the id of the
+ * lower-ranked site of i's pair within its color (i itself when i is
+ * unpaired or ranked first), branch[i] 1 for the higher-ranked site, else 0.
+ * One pass in ascending id keeps, per color, the site still waiting for a
+ * partner.  Returns 0, or 1 on a color outside 0 .. k-1. */
+int32_t orc_rng_pairs(int64_t n, const int32_t *color, int32_t k, int32_t *key, uint8_t *branch)
+{
+    int64_t i;
+    int64_t *waiting = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k > 0 ? k : 1));
+    int32_t c;
+    for (c = 0; c < k; ++c)
+        waiting[c] = -1;
+    for (i = 0; i < n; ++i) {
+        c = color[i];
+        if (c < 0 || c >= k) {
+            free(waiting);
+            return 1;
+        }
+        if (waiting[c] < 0) {
+            key[i] = (int32_t)i;
+            branch[i] = 0;
+            waiting[c] = i;
+        } else {
+            key[i] = (int32_t)waiting[c];
+            branch[i] = 1;
+            waiting[c] = -1;
+        }
+    }
+    free(waiting);
+    return 0;
 }
 
 /* Gamma(shape, rate) by Marsaglia & Tsang (2000), shape >= 1, no squeeze.
@@ -411,6 +468,9 @@ typedef struct {
     int32_t likelihood;       /* 0 Gaussian (y = b0 + x + e), 1 binomial logit */
     const int32_t *trials;    /* binomial: m_i (y holds the successes Y_i) */
     double beta0_var;         /* binomial: prior variance v0 of b0 (0 = flat) */
+    int32_t rng_version;      /* 1 (or 0): one block per site; 2: paired sites */
+    const int32_t *pair_key;  /* version 2: orc_rng_pairs of the coloring */
+    const uint8_t *pair_branch;
 } orc_problem;
 
 #define ORC_BINOMIAL 1
@@ -555,7 +615,13 @@ static void orc_update_site(const orc_problem *p, orc_chain *s, int64_t i, uint3
         Qii = s->tau * deg + s->lam;
         m = (s->lam * (p->y[i] - s->beta0) + s->tau * p->rho * sum) / Qii;
     }
-    z = (flags & ORC_ZERO_NOISE) ? 0.0 : orc_normal(p->seed, (uint32_t)i, t, p->instance, 0u);
+    if (flags & ORC_ZERO_NOISE)
+        z = 0.0;
+    else if (p->rng_version == 2)
+        z = orc_normal_pair(p->seed, (uint32_t)p->pair_key[i], p->pair_branch[i], t, p->instance,
+                            0u);
+    else
+        z = orc_normal(p->seed, (uint32_t)i, t, p->instance, 0u);
     s->x[i] = m + z / sqrt(Qii);
 }
 
@@ -567,6 +633,8 @@ int orc_sweeps(const orc_problem *p, orc_chain *s, int64_t nsweeps, uint32_t fla
                const int64_t *visit, int32_t nthreads)
 {
     int64_t it, n = p->n;
+    if (p->rng_version == 2 && n > 0 && (!p->pair_key || !p->pair_branch))
+        return 1;
 #ifdef _OPENMP
     if (nthreads < 1)
         nthreads = 1;
