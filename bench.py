@@ -42,7 +42,7 @@ BURN_IN_BYTES_PER_SITE = 12          # FP32 burn-in sweep: x read + x write + y 
 CSR_BYTES_PER_SITE = {"fp32_acc": 72, "fp64_acc": 84}
 METRIC = ("site-updates/s + HBM GB/s fraction per sweep; p50/p99 solve latency "
           "(FP32 vs FP64)")
-SWEEP_KERNEL = "lattice_sweep_kernel<float, LatCfg<8, 64, 64, 512, 4>, false>"
+SWEEP_KERNEL = "lattice_sweep_kernel<float, LatCfg<8, 64, 64, 512, 4>, false, false>"
 # rocprofv3 summaries of the dominant kernel (committed under profiles/):
 # its average duration in the kernel trace of this benchmark's command, and
 # its HBM traffic per launch from FETCH_SIZE / WRITE_SIZE scaled by a device
@@ -143,7 +143,7 @@ def traffic_summary(fetch_csv, write_csv, dram_csv, side, commands):
             v = float(r["Counter_Value"])
             if r["Kernel_Name"] == "__amd_rocclr_copyBuffer":
                 copy.append(v)
-            elif "lattice_sweep_kernel<float" in r["Kernel_Name"]:
+            elif _sweep_variant(r["Kernel_Name"]) == "fp32 v1":
                 sweep.append(v)
         return max(copy), sweep
 
@@ -174,7 +174,7 @@ def traffic_summary(fetch_csv, write_csv, dram_csv, side, commands):
     if dram_csv:
         tot = {}
         for r in _csv_rows(dram_csv):
-            if "lattice_sweep_kernel<float" in r["Kernel_Name"]:
+            if _sweep_variant(r["Kernel_Name"]) == "fp32 v1":
                 tot.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
         rd = np.mean(tot["TCC_EA0_RDREQ_DRAM_sum"]) / np.mean(tot["TCC_EA0_RDREQ_sum"])
         wr = np.mean(tot["TCC_EA0_WRREQ_DRAM_sum"]) / np.mean(tot["TCC_EA0_WRREQ_sum"])
@@ -194,23 +194,46 @@ def traffic_summary(fetch_csv, write_csv, dram_csv, side, commands):
     return "\n".join(out), fig
 
 
+def _sweep_variant(name):
+    """'fp32 v1' etc. for a 64 x 64 8-neighbour lattice sweep kernel without
+    an intercept, else None."""
+    n = name.replace("gmrf::", "").replace(" ", "")
+    for real, tag in (("float", "fp32"), ("double", "fp64")):
+        for v2, ver in (("false", "v1"), ("true", "v2")):
+            if f"lattice_sweep_kernel<{real},LatCfg<8,64,64,512,4>,false,{v2}>" in n:
+                return f"{tag} {ver}"
+    return None
+
+
 def counter_summary(csvs, commands):
     """Markdown summary of counter probes (bench.py --probe): the mean of
-    every counter over the FP32 sweep kernel's launches, per launch and per
-    wave (SQ_WAVES)."""
+    every counter over each sweep kernel's launches (FP32 / FP64, random-number
+    contract 1 / 2), per launch and per wave (SQ_WAVES)."""
     vals = {}
     for path in csvs:
         for r in _csv_rows(path):
-            if "lattice_sweep_kernel<float" in r["Kernel_Name"]:
-                vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
-    waves = np.mean(vals["SQ_WAVES"]) if "SQ_WAVES" in vals else None
-    out = [f"# Counters: FP32 lattice sweep kernel, {ROWS}x{COLS}, 8 neighbours", "",
+            k = _sweep_variant(r["Kernel_Name"])
+            if k:
+                vals.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(
+                    float(r["Counter_Value"]))
+    kinds = sorted(vals)
+    out = [f"# Counters: lattice sweep kernels, {ROWS}x{COLS}, 8 neighbours", "",
            "Commands (from the repository root on the GPU box):", "", "```", *commands, "```", "",
-           f"Mean over the {len(next(iter(vals.values())))} launches of the probe:", "",
-           "| Counter | Per launch | Per wave |", "|---|---|---|"]
-    for k in sorted(vals):
-        m = float(np.mean(vals[k]))
-        out.append(f"| {k} | {m:.0f} | {m / waves:.1f} |" if waves else f"| {k} | {m:.0f} | |")
+           "Mean over each kernel's launches in the probe (" +
+           ", ".join(f"{k}: {len(next(iter(vals[k].values())))}" for k in kinds) +
+           "), per wave (SQ_WAVES per launch in the last row):", "",
+           "| Counter | " + " | ".join(kinds) + " |", "|---|" + "---|" * len(kinds)]
+    names = sorted({c for k in kinds for c in vals[k]} - {"SQ_WAVES"})
+    for c in names:
+        cells = []
+        for k in kinds:
+            w = np.mean(vals[k]["SQ_WAVES"]) if "SQ_WAVES" in vals[k] else None
+            m = float(np.mean(vals[k][c])) if c in vals[k] else None
+            cells.append("" if m is None else (f"{m / w:.1f}" if w else f"{m:.0f} (launch)"))
+        out.append(f"| {c} | " + " | ".join(cells) + " |")
+    out.append("| SQ_WAVES | " + " | ".join(
+        f"{np.mean(vals[k]['SQ_WAVES']):.0f}" if "SQ_WAVES" in vals[k] else "" for k in kinds) +
+        " |")
     return "\n".join(out), None
 
 
@@ -316,6 +339,39 @@ def copy_gbs(torch, nbytes=1 << 30, reps=5):
     del src, dst
     torch.cuda.empty_cache()
     return 2.0 * nbytes / best / 1e9
+
+
+def rng_v2_row(torch, gmrf, graph, y, args):
+    """The same workload under the paired random-number contract (version 2:
+    one Philox block and one Box-Muller radius per rank pair of a color), FP32
+    and FP64, timed like the headline."""
+    n = ROWS * COLS
+    out = {"covers": "lattice 2048x2048 8-neighbour, rng_version 2 (pairs (r, c), (r, c + 2) "
+                     "of a color share one Philox block: cosine and sine branches)"}
+    for name, prec in (("fp32_acc", gmrf.FP32_ACC64), ("fp64_acc", gmrf.FP64)):
+        if name == "fp64_acc" and args.no_fp64:
+            continue
+        chain = gmrf.Chain(graph, y, precision=prec, seed=1, rng_version=2)
+        chain.sweep(args.warmup, hyper=True)
+        chain.sweep(args.steps, hyper=True, capture=True)
+        torch.cuda.synchronize()
+        t = min(timed_sweeps(torch, chain, args.steps, capture=False),
+                timed_sweeps(torch, chain, args.steps, capture=True))
+        k_disp = dispatch_timed(torch, chain, args.steps)
+        x, tau, lam, _ = chain.get_state()
+        if not (np.isfinite(tau) and np.isfinite(lam)):
+            print("bench.py: non-finite result (rng_version 2)", file=sys.stderr)
+            sys.exit(1)
+        bps = BYTES_PER_SITE[name]
+        out[name] = {"value": n * args.steps / t, "unit": "site-updates/s",
+                     "ms_per_step": t / args.steps * 1e3,
+                     "hbm_frac": bps * n / (t / args.steps) / 1e9 / HBM_PEAK_GBS,
+                     "kernel_us_dispatch_events": k_disp * 1e6}
+        log(f"[bench] rng v2 {name}: {t / args.steps * 1e6:.1f} us/sweep "
+            f"({out[name]['hbm_frac']:.3f} of peak)")
+        del chain
+        torch.cuda.synchronize()
+    return out
 
 
 def big_lattice_row(torch, gmrf, inputs, args):
@@ -495,10 +551,11 @@ def cpu_baseline(wl, seconds_budget=10.0, wl1m=None):
             "delaunay1m_sample": big}
 
 
-def probe(torch, gmrf, inputs, steps, side=ROWS):
+def probe(torch, gmrf, inputs, steps, side=ROWS, variants=False):
     """A plain device copy of 512 MiB (its counters give the scale factor of
     FETCH_SIZE / WRITE_SIZE), then warm-up and `steps` FP32 sweeps, one launch
-    each, of the benchmark workload (side x side, 8 neighbours)."""
+    each, of the benchmark workload (side x side, 8 neighbours).  variants:
+    then the same for FP32 under rng_version 2 and FP64 under both."""
     src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
@@ -506,13 +563,18 @@ def probe(torch, gmrf, inputs, steps, side=ROWS):
     del src, dst
     wl = inputs.lattice_workload(side, side, STENCIL, noise_sd=0.1, data_seed=1, with_csr=False)
     graph = gmrf.Graph(lattice=(side, side, STENCIL))
-    chain = gmrf.Chain(graph, wl["y"], precision=gmrf.FP32_ACC64, seed=1)
-    chain.sweep(5, hyper=True)
-    for _ in range(steps):
-        chain.sweep(1, hyper=True)
-    torch.cuda.synchronize()
-    print(json.dumps({"probe": "copy 512 MiB + sweeps", "side": side, "sweeps": steps + 5}),
-          flush=True)
+    runs = [(gmrf.FP32_ACC64, 1)]
+    if variants:
+        runs += [(gmrf.FP32_ACC64, 2), (gmrf.FP64, 1), (gmrf.FP64, 2)]
+    for prec, v in runs:
+        chain = gmrf.Chain(graph, wl["y"], precision=prec, seed=1, rng_version=v)
+        chain.sweep(5, hyper=True)
+        for _ in range(steps):
+            chain.sweep(1, hyper=True)
+        torch.cuda.synchronize()
+        del chain
+    print(json.dumps({"probe": "copy 512 MiB + sweeps", "side": side, "sweeps": steps + 5,
+                      "chains": len(runs)}), flush=True)
 
 
 def bench_batch(torch, gmrf, inputs, args):
@@ -780,6 +842,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the 1,000,000-site Delaunay row")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batch row")
+    ap.add_argument("--no-v2", action="store_true",
+                    help="skip the paired random-number contract (rng_version 2) row")
     ap.add_argument("--reps", type=int, default=10, help="solves for p50/p99 latency")
     ap.add_argument("--workload", default="lattice2048",
                     choices=["lattice2048", "batch512", "serve", "image", "binomial"],
@@ -799,6 +863,8 @@ def main():
                     help="with --summarize: a command line to record in the summary")
     ap.add_argument("--probe-side", type=int, default=ROWS,
                     help="lattice side of --probe (8 neighbours, FP32)")
+    ap.add_argument("--probe-variants", action="store_true",
+                    help="with --probe: also FP32 under rng_version 2 and FP64 under both")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe for rocprofv3 --pmc: a 512 MiB device copy (the "
                          "scale reference for FETCH_SIZE / WRITE_SIZE), then --steps sweeps")
@@ -831,7 +897,7 @@ def main():
     gmrf.lib()
     n = ROWS * COLS
     if args.probe:
-        probe(torch, gmrf, inputs, args.steps, args.probe_side)
+        probe(torch, gmrf, inputs, args.steps, args.probe_side, args.probe_variants)
         return
     if args.workload == "batch512":
         bench_batch(torch, gmrf, inputs, args)
@@ -955,6 +1021,8 @@ def main():
                         HBM_PEAK_GBS,
                         "kernel_us_dispatch_events": d["kernel_disp_s"] * 1e6}
         line["solve_latency_ms_1000_sweeps"]["fp64"] = {"p50": d["p50_ms"], "p99": d["p99_ms"]}
+    if not args.no_v2:
+        line["rng_v2"] = rng_v2_row(torch, gmrf, graph, wl["y"], args)
     if not args.no_big:
         line["lattice8192_out_of_cache"] = big_lattice_row(torch, gmrf, inputs, args)
     wl1m = None

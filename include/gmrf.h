@@ -136,6 +136,14 @@ typedef struct {
                                (gmrf_chain_create_binomial) */
     double beta0;           /* initial beta0 (finite; must be 0 when intercept = 0) */
     double beta0_var;       /* binomial: prior variance of beta0, 0 = flat; Gaussian: 0 */
+    int32_t rng_version;    /* random-number contract of the site normals (0 means 1):
+                               1: one Philox block per site, cosine branch;
+                               2: the sites of each color, ranked by original id, share
+                               one block per rank pair (2m, 2m + 1): cosine branch for
+                               the first, sine branch for the second (Box-Muller's two
+                               independent normals; half the generator work).  Version
+                               2 is taken by Gaussian lattice chains whose width is a
+                               multiple of 4, swept on their own (not in a batch). */
 } gmrf_model;
 
 #define GMRF_GAUSSIAN 0
@@ -208,8 +216,10 @@ size_t gmrf_chain_footprint(const gmrf_graph *g, gmrf_precision p);
  * tau and lam.  Upload y (host, n values in original order, FP64; stored as
  * FP32 for GMRF_FP32_ACC64) and x0 (host, original order, or NULL for zeros),
  * set tau = m->tau0, lam = m->lam0, sweep = 0, clear the accumulators.  seed
- * and instance key the chain's random numbers.  Synchronises the stream.
- * Errors: GMRF_E_INVALID_ARG (bad model or precision, non-finite y or x0),
+ * and instance key the chain's random numbers (by m->rng_version).
+ * Synchronises the stream.  Errors: GMRF_E_INVALID_ARG (bad model or
+ * precision, non-finite y or x0, rng_version other than 0, 1, 2, or 2 on a
+ * general graph or a lattice whose width is not a multiple of 4),
  * GMRF_E_WORKSPACE, GMRF_E_DEVICE. */
 int gmrf_chain_create(const gmrf_graph *g, const gmrf_model *m, const double *y, const double *x0,
                       gmrf_precision p, uint64_t seed, uint32_t instance, void *d_ws,
@@ -440,7 +450,8 @@ size_t gmrf_batch_footprint(gmrf_chain *const *chains, int32_t count);
  * gmrf_batch_footprint) and the call synchronises the stream.  The chains
  * must outlive the batch and must not be swept on their own while the batch
  * is in use on another stream.  Errors: GMRF_E_INVALID_ARG (count < 1, NULL
- * or repeated chain, mixed precisions), GMRF_E_WORKSPACE, GMRF_E_DEVICE. */
+ * or repeated chain, mixed precisions, a binomial or rng_version 2 chain),
+ * GMRF_E_WORKSPACE, GMRF_E_DEVICE. */
 int gmrf_batch_create(gmrf_chain *const *chains, int32_t count, void *d_ws, size_t ws_bytes,
                       hipStream_t stream, gmrf_batch **out);
 int gmrf_batch_destroy(gmrf_batch *b);

@@ -583,15 +583,16 @@ __device__ __forceinline__ void qtab_fill(Real *qtab, Real tau, Real lam)
 }
 
 // One site of Algorithm 1 on the LDS tile: neighbour sum in ascending
-// original-id order, conditional mean and precision, the draw; for interior
-// sites also the q / sse terms.  Cells of the tile outside the lattice hold
+// original-id order, conditional mean and precision, the draw with the
+// site's standard normal z; for interior sites also the q / sse terms.  Cells of the tile outside the lattice hold
 // 0 (lattice_stage), so the neighbour sum adds every stencil cell: a missing
 // neighbour adds 0, which leaves each partial sum of the in-lattice
 // neighbours unchanged.  INTERIOR: the tile and its halo lie inside the
 // lattice, so every site has all its neighbours (compile-time flags).
 template <typename Real, typename Cfg, int J, bool INTERIOR, bool B0>
-__device__ __forceinline__ void lattice_site(Real *xs, Real yv, int r, int c, int r0, int c0,
-                                             int rows, int cols, const SiteCtx<Real> &sc, Red &rd)
+__device__ __forceinline__ void lattice_site(Real *xs, Real yv, Real z, int r, int c, int r0,
+                                             int c0, int rows, int cols, const SiteCtx<Real> &sc,
+                                             Red &rd)
 {
     constexpr int ST = Cfg::ST, H = Cfg::H, LW = Cfg::LW;
     Real *p = xs + (r - r0 + H) * LW + (c - c0 + H);
@@ -607,9 +608,6 @@ __device__ __forceinline__ void lattice_site(Real *xs, Real yv, int r, int c, in
     s += p[LW];
     if (ST == 8) s += p[LW + 1];
 
-    const unsigned site = (unsigned)r * (unsigned)cols + (unsigned)c;
-    const Words4 w = draw_words(sc.seed, site, sc.t, sc.instance, 0u);
-    const Real z = site_normal<Real>(w);
     Real inv_q, isd;
     if constexpr (INTERIOR) {
         inv_q = sc.inv_q_full;
@@ -669,80 +667,212 @@ __device__ __forceinline__ int div_small(int idx, int d, float rcp, int &rem)
     return qt;
 }
 
-// Phase J: every color-J site of the tile grown by E = k-1-J rings.  The
-// iteration count per thread has a compile-time bound, so the y loads of all
-// of a thread's sites are issued before the first site is computed.
-template <typename Real, typename Cfg, int J, bool INTERIOR, bool B0>
-__device__ __forceinline__ void lattice_phase(Real *xs, const Real *__restrict__ y, int r0,
-                                              int c0, int rows, int cols, const SiteCtx<Real> &sc,
-                                              Red &rd)
+// The color-J sites of the tile grown by E = k-1-J rings: rows ra .. rb - 1
+// and columns ca .. cb - 1 (8 neighbours: ra and ca moved to the parities of
+// J), nR rows of at most nC sites each.  Unit idx = R nC + C of a phase is
+// the site (ra + R, ca + ((r + ca + J) & 1) + 2 C) for 4 neighbours and
+// (ra + 2 R, ca + 2 C) for 8.
+struct PhaseGeom {
+    int ra, rb, ca, cb, nR, nC;
+};
+
+template <typename Cfg, int J>
+__device__ __forceinline__ PhaseGeom phase_geom(int r0, int c0, int rows, int cols)
 {
     constexpr int E = Cfg::K - 1 - J;
-    constexpr int NT = Cfg::NT;
-    constexpr int MAXS = Cfg::ST == 8 ? (Cfg::TH / 2 + E) * (Cfg::TW / 2 + E)
-                                      : (Cfg::TH + 2 * E) * ((Cfg::TW + 2 * E + 1) / 2);
-    constexpr int NI = (MAXS + NT - 1) / NT;
-    int ra = max(r0 - E, 0);
-    const int rb = min(r0 + Cfg::TH + E, rows);
-    int ca = max(c0 - E, 0);
-    const int cb = min(c0 + Cfg::TW + E, cols);
-    int nR, nC;
+    PhaseGeom g;
+    g.ra = max(r0 - E, 0);
+    g.rb = min(r0 + Cfg::TH + E, rows);
+    g.ca = max(c0 - E, 0);
+    g.cb = min(c0 + Cfg::TW + E, cols);
     if constexpr (Cfg::ST == 8) {
-        ra += ((ra & 1) != (J >> 1));
-        ca += ((ca & 1) != (J & 1));
-        nR = rb > ra ? (rb - ra + 1) >> 1 : 0;
-        nC = cb > ca ? (cb - ca + 1) >> 1 : 0;
+        g.ra += ((g.ra & 1) != (J >> 1));
+        g.ca += ((g.ca & 1) != (J & 1));
+        g.nR = g.rb > g.ra ? (g.rb - g.ra + 1) >> 1 : 0;
     } else {
-        nR = rb > ra ? rb - ra : 0;
-        nC = cb > ca ? (cb - ca + 1) >> 1 : 0;
+        g.nR = g.rb > g.ra ? g.rb - g.ra : 0;
     }
-    const int total = nR * nC;
-    const float rcp = 1.0f / (float)max(nC, 1);
+    g.nC = g.cb > g.ca ? (g.cb - g.ca + 1) >> 1 : 0;
+    return g;
+}
+
+// Most units of a phase of the grown tile (phase 0 grows the most).
+template <typename Cfg> constexpr int phase_units(int J)
+{
+    return Cfg::ST == 8 ? (Cfg::TH / 2 + Cfg::K - 1 - J) * (Cfg::TW / 2 + Cfg::K - 1 - J)
+                        : (Cfg::TH + 2 * (Cfg::K - 1 - J)) *
+                              ((Cfg::TW + 2 * (Cfg::K - 1 - J) + 1) / 2);
+}
+
+// Phase J: every color-J site of the grown tile.  The iteration count per
+// thread has a compile-time bound, so the y loads of all of a thread's sites
+// are issued before the first site is computed; mid() runs between the
+// loads and the sites (work that hides their latency).  zin: the sites'
+// normals, drawn ahead by lattice_normals at the units' indices (paired
+// random-number contract), or NULL to draw each site's own block here.
+template <typename Real, typename Cfg, int J, bool INTERIOR, bool B0, typename Mid>
+__device__ __forceinline__ void lattice_phase(Real *xs, const Real *__restrict__ y, int r0,
+                                              int c0, int rows, int cols, const SiteCtx<Real> &sc,
+                                              Red &rd, const Real *zin, Mid &&mid)
+{
+    constexpr int NT = Cfg::NT;
+    constexpr int NI = (phase_units<Cfg>(J) + NT - 1) / NT;
+    const PhaseGeom g = phase_geom<Cfg, J>(r0, c0, rows, cols);
+    const int total = g.nR * g.nC;
+    const float rcp = 1.0f / (float)max(g.nC, 1);
     int rr[NI], cc[NI];
     Real yv[NI];
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
         const int idx = (int)threadIdx.x + k * NT;
         int C;
-        const int R = div_small(idx, max(nC, 1), rcp, C);
+        const int R = div_small(idx, max(g.nC, 1), rcp, C);
         int r, c;
         if constexpr (Cfg::ST == 8) {
-            r = ra + 2 * R;
-            c = ca + 2 * C;
+            r = g.ra + 2 * R;
+            c = g.ca + 2 * C;
         } else {
-            r = ra + R;
-            c = ca + ((r + ca + J) & 1) + 2 * C;
+            r = g.ra + R;
+            c = g.ca + ((r + g.ca + J) & 1) + 2 * C;
         }
-        const bool ok = idx < total && c < cb;
+        const bool ok = idx < total && c < g.cb;
         rr[k] = ok ? r : -1;
         cc[k] = c;
         // clamped address: always inside the lattice, used only when ok
         const int rc = min(max(r, 0), rows - 1), ccl = min(max(c, 0), cols - 1);
         yv[k] = y[(size_t)rc * cols + ccl];
     }
+    mid();
 #pragma unroll
     for (int k = 0; k < NI; ++k)
-        if (rr[k] >= 0)
-            lattice_site<Real, Cfg, J, INTERIOR, B0>(xs, yv[k], rr[k], cc[k], r0, c0, rows, cols,
-                                                     sc, rd);
+        if (rr[k] >= 0) {
+            Real z;
+            if (zin) {
+                z = zin[(int)threadIdx.x + k * NT];
+            } else {
+                const unsigned site = (unsigned)rr[k] * (unsigned)cols + (unsigned)cc[k];
+                z = site_normal<Real>(draw_words(sc.seed, site, sc.t, sc.instance, 0u));
+            }
+            lattice_site<Real, Cfg, J, INTERIOR, B0>(xs, yv[k], z, rr[k], cc[k], r0, c0, rows,
+                                                     cols, sc, rd);
+        }
 }
 
-// The k color phases of one tile, separated by LDS barriers.
-template <typename Real, typename Cfg, bool INTERIOR, bool B0>
+// The normals of phase J's sites under the paired random-number contract,
+// into zb at the phase's unit indices.  The sites of a color, ranked by
+// original id, share one Philox block per rank pair (2m, 2m + 1): the
+// cosine branch for the first, the sine branch for the second.  With the
+// lattice width a multiple of 4 every row holds an even number of sites of
+// each of its colors, so the pairs are (r, c) and (r, c + 2) with bit 1 of c
+// clear, keyed by the id of (r, c).  A thread takes pair slots here (one
+// block and one Box-Muller radius for two sites) and the site updates take
+// one site per thread, so the update reads the tile with the stride of the
+// unpaired phase; a slot cut by the edge of the grown tile stores the one
+// normal inside.
+template <typename Real, typename Cfg, int J>
+__device__ __forceinline__ void lattice_normals(Real *zb, int r0, int c0, int rows, int cols,
+                                                const SiteCtx<Real> &sc)
+{
+    constexpr int E = Cfg::K - 1 - J;
+    constexpr int NT = Cfg::NT;
+    static_assert(Cfg::TW % 4 == 0, "pair slots need tile columns at multiples of 4");
+    // rows of the grown tile that hold color-J sites, and pair slots per row
+    // (c0 is a multiple of 4, so columns c0 - E .. c0 + TW + E - 1 meet at
+    // most TW / 4 + 2 slots)
+    constexpr int MR = Cfg::ST == 8 ? Cfg::TH / 2 + E : Cfg::TH + 2 * E;
+    constexpr int MP = Cfg::TW / 4 + 2;
+    constexpr int NI = (MR * MP + NT - 1) / NT;
+    const PhaseGeom g = phase_geom<Cfg, J>(r0, c0, rows, cols);
+    const int pa = g.ca >> 2;
+    int nP;
+    if constexpr (Cfg::ST == 8) {
+        const int cl = g.cb - 1 - (((g.cb - 1) & 1) != (J & 1));   // last column of parity J & 1
+        nP = cl >= g.ca ? (cl >> 2) - pa + 1 : 0;
+    } else {
+        nP = g.cb > g.ca ? ((g.cb - 1) >> 2) - pa + 1 : 0;
+    }
+    const int total = g.nR * nP;
+    const float rcp = 1.0f / (float)max(nP, 1);
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int idx = (int)threadIdx.x + k * NT;
+        if (idx < total) {
+            int P;
+            const int R = div_small(idx, max(nP, 1), rcp, P);
+            const int r = Cfg::ST == 8 ? g.ra + 2 * R : g.ra + R;
+            const int off = Cfg::ST == 8 ? (J & 1) : ((r + J) & 1);
+            const int c = 4 * (pa + P) + off;
+            const bool in1 = c >= g.ca && c < g.cb, in2 = c + 2 >= g.ca && c + 2 < g.cb;
+            if (in1 || in2) {
+                const unsigned key = (unsigned)r * (unsigned)cols + (unsigned)c;
+                Real zc, zs;
+                site_normal_pair<Real>(draw_words(sc.seed, key, sc.t, sc.instance, 0u), zc, zs);
+                Real *const zrow = zb + R * g.nC;
+                if (in1)
+                    zrow[(c - g.ca) >> 1] = zc;
+                if (in2)
+                    zrow[(c + 2 - g.ca) >> 1] = zs;
+            }
+        }
+    }
+}
+
+// The k color phases of one tile, separated by LDS barriers.  V2: the chain
+// draws by the paired contract; zb then holds two buffers of
+// phase_units<Cfg>(0) normals, and the caller has drawn phase 0's into the
+// first and synchronised.  Each phase draws the next phase's normals into
+// the other buffer between its y loads and its site updates; the barrier
+// that ends the phase publishes them.
+template <typename Real, typename Cfg, bool INTERIOR, bool B0, bool V2>
 __device__ __forceinline__ void lattice_phases(Real *xs, const Real *__restrict__ y, int r0,
                                                int c0, int rows, int cols, const SiteCtx<Real> &sc,
-                                               Red &rd)
+                                               Red &rd, Real *zb)
 {
-    lattice_phase<Real, Cfg, 0, INTERIOR, B0>(xs, y, r0, c0, rows, cols, sc, rd);
-    lds_barrier();
-    lattice_phase<Real, Cfg, 1, INTERIOR, B0>(xs, y, r0, c0, rows, cols, sc, rd);
-    lds_barrier();
-    if constexpr (Cfg::K == 4) {
-        lattice_phase<Real, Cfg, 2, INTERIOR, B0>(xs, y, r0, c0, rows, cols, sc, rd);
+    constexpr int ZN = phase_units<Cfg>(0);
+    auto none = [] {};
+    if constexpr (V2) {
+        lattice_phase<Real, Cfg, 0, INTERIOR, B0>(
+            xs, y, r0, c0, rows, cols, sc, rd, zb,
+            [&] { lattice_normals<Real, Cfg, 1>(zb + ZN, r0, c0, rows, cols, sc); });
         lds_barrier();
-        lattice_phase<Real, Cfg, 3, INTERIOR, B0>(xs, y, r0, c0, rows, cols, sc, rd);
+        if constexpr (Cfg::K == 4) {
+            lattice_phase<Real, Cfg, 1, INTERIOR, B0>(
+                xs, y, r0, c0, rows, cols, sc, rd, zb + ZN,
+                [&] { lattice_normals<Real, Cfg, 2>(zb, r0, c0, rows, cols, sc); });
+            lds_barrier();
+            lattice_phase<Real, Cfg, 2, INTERIOR, B0>(
+                xs, y, r0, c0, rows, cols, sc, rd, zb,
+                [&] { lattice_normals<Real, Cfg, 3>(zb + ZN, r0, c0, rows, cols, sc); });
+            lds_barrier();
+            lattice_phase<Real, Cfg, 3, INTERIOR, B0>(xs, y, r0, c0, rows, cols, sc, rd,
+                                                      zb + ZN, none);
+            lds_barrier();
+        } else {
+            lattice_phase<Real, Cfg, 1, INTERIOR, B0>(xs, y, r0, c0, rows, cols, sc, rd,
+                                                      zb + ZN, none);
+            lds_barrier();
+        }
+    } else {
+        const Real *const nz = nullptr;
+        lattice_phase<Real, Cfg, 0, INTERIOR, B0>(xs, y, r0, c0, rows, cols, sc, rd, nz, none);
         lds_barrier();
+        lattice_phase<Real, Cfg, 1, INTERIOR, B0>(xs, y, r0, c0, rows, cols, sc, rd, nz, none);
+        lds_barrier();
+        if constexpr (Cfg::K == 4) {
+            lattice_phase<Real, Cfg, 2, INTERIOR, B0>(xs, y, r0, c0, rows, cols, sc, rd, nz,
+                                                      none);
+            lds_barrier();
+            lattice_phase<Real, Cfg, 3, INTERIOR, B0>(xs, y, r0, c0, rows, cols, sc, rd, nz,
+                                                      none);
+            lds_barrier();
+        }
     }
+}
+
+// LDS normals of a V2 tile: two phase buffers (one element otherwise).
+template <typename Cfg, bool V2> constexpr int zbuf_len()
+{
+    return V2 ? 2 * phase_units<Cfg>(0) : 1;
 }
 
 // XCD-aware tile order: the hardware hands block b to XCD b mod 8, so give
@@ -811,8 +941,9 @@ __device__ __forceinline__ void lattice_store(Real *xs, const Real (&v)[tile_loa
 // holding them across the draws would cost the kernel its occupancy), and
 // the block of tile 0 records the draws for the next sweep kernel and the
 // commit.  Without fold the sweep runs with the committed
-// state (the first sweep of a call, and timing runs).
-template <typename Real, typename Cfg, bool B0>
+// state (the first sweep of a call, and timing runs).  V2: the chain draws
+// its site normals by the paired contract (lattice_normals).
+template <typename Real, typename Cfg, bool B0, bool V2>
 __device__ __forceinline__ void lattice_sweep_block(const LatArgs<Real> &la, const SweepArgs &a,
                                                     const int tile, const int rel, const int fold)
 {
@@ -822,6 +953,7 @@ __device__ __forceinline__ void lattice_sweep_block(const LatArgs<Real> &la, con
     constexpr int CH = Cfg::CH < NPT ? Cfg::CH : NPT;  // accumulator batch
     __shared__ Real xs[LH * LW];
     __shared__ Real qtab[2 * (Cfg::ST + 1)];
+    __shared__ Real zb[zbuf_len<Cfg, V2>()];
 
     const unsigned t = (unsigned)(a.st->sweep + (unsigned long long)rel);
     const Real *src = (t & 1u) ? la.x1 : la.x0;
@@ -862,6 +994,9 @@ __device__ __forceinline__ void lattice_sweep_block(const LatArgs<Real> &la, con
     sc.seed = a.seed;
     sc.instance = a.instance;
     sc.qtab = qtab;
+    // phase 0's paired normals while the tile loads are in flight
+    if constexpr (V2)
+        lattice_normals<Real, Cfg, 0>(zb, r0, c0, rows, cols, sc);
 
     lattice_store<Real, Cfg>(xs, v);
     qtab_fill<Real, Cfg::ST>(qtab, sc.tau, sc.lam);
@@ -872,10 +1007,10 @@ __device__ __forceinline__ void lattice_sweep_block(const LatArgs<Real> &la, con
     const bool interior = r0 >= H && c0 >= H && r0 + TH + Cfg::HH <= rows &&
                           c0 + TW + Cfg::HH <= cols;
     if (interior)
-        lattice_phases<Real, Cfg, true, B0>(xs, la.y, r0, c0, rows, cols, sc, rd);
+        lattice_phases<Real, Cfg, true, B0, V2>(xs, la.y, r0, c0, rows, cols, sc, rd, zb);
     else
 #endif
-        lattice_phases<Real, Cfg, false, B0>(xs, la.y, r0, c0, rows, cols, sc, rd);
+        lattice_phases<Real, Cfg, false, B0, V2>(xs, la.y, r0, c0, rows, cols, sc, rd, zb);
 
     // Write the interior back and update the accumulators, CH sites per
     // thread per batch so their loads are in flight together.
@@ -915,12 +1050,12 @@ __device__ __forceinline__ void lattice_sweep_block(const LatArgs<Real> &la, con
     write_partials<NT>(partials_of(a, rel), rd, tile);
 }
 
-template <typename Real, typename Cfg, bool B0>
+template <typename Real, typename Cfg, bool B0, bool V2>
 __global__ __launch_bounds__(Cfg::NT) void lattice_sweep_kernel(LatArgs<Real> la, SweepArgs a,
                                                                 int rel, int fold)
 {
-    lattice_sweep_block<Real, Cfg, B0>(la, a, xcd_tile((int)blockIdx.x, (int)gridDim.x), rel,
-                                       fold);
+    lattice_sweep_block<Real, Cfg, B0, V2>(la, a, xcd_tile((int)blockIdx.x, (int)gridDim.x), rel,
+                                           fold);
 }
 
 // A lattice that fits one tile, many sweeps in one launch (one block): the
@@ -931,7 +1066,7 @@ __global__ __launch_bounds__(Cfg::NT) void lattice_sweep_kernel(LatArgs<Real> la
 // single-tile lattice, in the same order, so the results are bitwise those of
 // tile shape 0.  With a.dry set (timing) it writes only the state buffer that
 // the sweep after the last one would overwrite.
-template <typename Real, typename Cfg, bool B0>
+template <typename Real, typename Cfg, bool B0, bool V2>
 __global__ __launch_bounds__(Cfg::NT) void lattice_persistent_kernel(LatArgs<Real> la, SweepArgs a,
                                                                      int nsweeps)
 {
@@ -943,6 +1078,7 @@ __global__ __launch_bounds__(Cfg::NT) void lattice_persistent_kernel(LatArgs<Rea
     __shared__ double red[kPartials * (NT / 64)];
     __shared__ double hyp[3];
     __shared__ UnitDraws ub[kUnitBatch][2];
+    __shared__ Real zb[zbuf_len<Cfg, V2>()];
     const int rows = la.rows, cols = la.cols;
     const int lane = (int)threadIdx.x & 63;
     unsigned t = (unsigned)a.st->sweep;
@@ -986,9 +1122,11 @@ __global__ __launch_bounds__(Cfg::NT) void lattice_persistent_kernel(LatArgs<Rea
         sc.instance = a.instance;
         sc.qtab = qtab;
         qtab_fill<Real, Cfg::ST>(qtab, sc.tau, sc.lam);
+        if constexpr (V2)
+            lattice_normals<Real, Cfg, 0>(zb, 0, 0, rows, cols, sc);
         lds_barrier();
         Red rd;
-        lattice_phases<Real, Cfg, false, B0>(xs, la.y, 0, 0, rows, cols, sc, rd);
+        lattice_phases<Real, Cfg, false, B0, V2>(xs, la.y, 0, 0, rows, cols, sc, rd, zb);
         if ((long long)t >= a.burn_in) {
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
@@ -1065,7 +1203,7 @@ __global__ __launch_bounds__(Cfg::NT) void lattice_batch_kernel(const LatJob<Rea
     const LatJob<Real> &j = jobs[tl.job];
     SweepArgs a = j.a;
     a.with_hyper = with_hyper;
-    lattice_sweep_block<Real, Cfg, B0>(j.la, a, tl.tile, rel, fold);
+    lattice_sweep_block<Real, Cfg, B0, false>(j.la, a, tl.tile, rel, fold);
 }
 
 // ---------------------------------------------------------------------------
@@ -2198,8 +2336,12 @@ void launch_lattice_shape(const gmrf_chain *c, const SweepArgs &a, hipStream_t s
 {
     const LatArgs<Real> la = lattice_args<Real>(c);
     using Cfg = LatticeCfg<ST, K>;
-    auto kern = c->model.intercept ? lattice_sweep_kernel<Real, Cfg, true>
-                                   : lattice_sweep_kernel<Real, Cfg, false>;
+    const bool v2 = c->model.rng_version == 2;
+    auto kern = c->model.intercept
+                    ? (v2 ? lattice_sweep_kernel<Real, Cfg, true, true>
+                          : lattice_sweep_kernel<Real, Cfg, true, false>)
+                    : (v2 ? lattice_sweep_kernel<Real, Cfg, false, true>
+                          : lattice_sweep_kernel<Real, Cfg, false, false>);
     if (ev0 || ev1)
         hipExtLaunchKernelGGL(kern, dim3(c->total_slots), dim3(Cfg::NT), 0, s, ev0, ev1, 0, la,
                               a, rel, fold);
@@ -2224,8 +2366,12 @@ void launch_persistent_typed(const gmrf_chain *c, const SweepArgs &a, int nsweep
 {
     const LatArgs<Real> la = lattice_args<Real>(c);
     using Cfg = LatticeCfg<ST, 0>;
-    auto kern = c->model.intercept ? lattice_persistent_kernel<Real, Cfg, true>
-                                   : lattice_persistent_kernel<Real, Cfg, false>;
+    const bool v2 = c->model.rng_version == 2;
+    auto kern = c->model.intercept
+                    ? (v2 ? lattice_persistent_kernel<Real, Cfg, true, true>
+                          : lattice_persistent_kernel<Real, Cfg, true, false>)
+                    : (v2 ? lattice_persistent_kernel<Real, Cfg, false, true>
+                          : lattice_persistent_kernel<Real, Cfg, false, false>);
     if (ev0 || ev1)
         hipExtLaunchKernelGGL(kern, dim3(1), dim3(Cfg::NT), 0, s, ev0, ev1, 0, la, a, nsweeps);
     else
@@ -2759,6 +2905,9 @@ int check_batch_chains(gmrf_chain *const *chains, int32_t count, gmrf_precision 
         if (c->binomial)
             return fail(GMRF_E_INVALID_ARG, "batch: binomial chains are swept on their own "
                                             "(chain at index " + std::to_string(i) + ")");
+        if (c->model.rng_version == 2)
+            return fail(GMRF_E_INVALID_ARG, "batch: rng_version 2 chains are swept on their own "
+                                            "(chain at index " + std::to_string(i) + ")");
     }
     *prec = chains[0]->prec;
     return GMRF_OK;
@@ -3245,6 +3394,11 @@ static int chain_create_impl(const char *who, const gmrf_graph *g, const gmrf_mo
         return fail(GMRF_E_INVALID_ARG, w + ": beta0_var applies to the binomial model only");
     if (binomial && (!(m->beta0_var >= 0.0) || !std::isfinite(m->beta0_var)))
         return fail(GMRF_E_INVALID_ARG, w + ": beta0_var must be finite and >= 0");
+    if (m->rng_version < 0 || m->rng_version > 2)
+        return fail(GMRF_E_INVALID_ARG, w + ": rng_version must be 0, 1 or 2");
+    if (m->rng_version == 2 && (!is_lattice(g) || g->h.cols % 4 != 0))
+        return fail(GMRF_E_INVALID_ARG, w + ": rng_version 2 needs a lattice whose width is a "
+                                            "multiple of 4");
     if (!finite_array(y, n) || (x0 && !finite_array(x0, n)))
         return fail(GMRF_E_INVALID_ARG, w + ": y and x0 must be finite");
     std::vector<double> kappa;

@@ -128,6 +128,16 @@ __host__ __device__ inline double cos_2pi_unit(double u)
     return neg ? -p : p;
 }
 
+// sin(2 pi u) for u in [0, 1] as cos(2 pi (u - 1/4)), the argument moved
+// back into [0, 1] by one period below u = 1/4.  For multiples of 2^-53 (the
+// open uniforms) both shifts are exact: u - 1/4 lies in [0, 3/4] and u + 3/4
+// in [3/4, 1), and every multiple of 2^-53 there is a double, so the error is
+// cos_2pi_unit's.
+__host__ __device__ inline double sin_2pi_unit(double u)
+{
+    return cos_2pi_unit(u < 0.25 ? u + 0.75 : u - 0.25);
+}
+
 // FP64 standard normal of one Philox block.  log u1 and cos(2 pi u2) come
 // from log_open_unit and cos_2pi_unit: the library values up to a few ulps
 // (no double-double logarithm, no general range reduction), with much
@@ -153,6 +163,28 @@ __device__ __forceinline__ float normal_f32(const Words4 &w)
            __builtin_amdgcn_cosf(u2);
 }
 
+// Both Box-Muller normals of one block (the paired contract: the cosine
+// branch for the lower-ranked site of a pair, the sine branch for its
+// partner); one logarithm and one square root serve the two.
+__device__ __forceinline__ void normal_pair_f64(const Words4 &w, double &zc, double &zs)
+{
+    const double u1 = open_uniform_f64(w.w0, w.w1);
+    const double u2 = open_uniform_f64(w.w2, w.w3);
+    const double r = sqrt(-2.0 * log_open_unit(u1));
+    zc = r * cos_2pi_unit(u2);
+    zs = r * sin_2pi_unit(u2);
+}
+
+__device__ __forceinline__ void normal_pair_f32(const Words4 &w, float &zc, float &zs)
+{
+    const float u1 = fmaf((float)w.w0, 0x1p-32f, fmaf((float)(w.w1 >> 8), 0x1p-56f, 0x1p-57f));
+    const float u2 = (float)w.w2 * 0x1p-32f;
+    constexpr float kMinus2Ln2 = -1.38629436111989061883f;   // -2 ln 2
+    const float r = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(u1));
+    zc = r * __builtin_amdgcn_cosf(u2);
+    zs = r * __builtin_amdgcn_sinf(u2);
+}
+
 template <typename Real> __device__ __forceinline__ Real site_normal(const Words4 &w);
 template <> __device__ __forceinline__ double site_normal<double>(const Words4 &w)
 {
@@ -161,6 +193,19 @@ template <> __device__ __forceinline__ double site_normal<double>(const Words4 &
 template <> __device__ __forceinline__ float site_normal<float>(const Words4 &w)
 {
     return normal_f32(w);
+}
+
+template <typename Real>
+__device__ __forceinline__ void site_normal_pair(const Words4 &w, Real &zc, Real &zs);
+template <>
+__device__ __forceinline__ void site_normal_pair<double>(const Words4 &w, double &zc, double &zs)
+{
+    normal_pair_f64(w, zc, zs);
+}
+template <>
+__device__ __forceinline__ void site_normal_pair<float>(const Words4 &w, float &zc, float &zs)
+{
+    normal_pair_f32(w, zc, zs);
 }
 
 constexpr int kGammaMaxAttempts = 64;

@@ -44,7 +44,7 @@ class Model(C.Structure):
     _fields_ = [("a_tau", C.c_double), ("b_tau", C.c_double), ("a_lam", C.c_double),
                 ("b_lam", C.c_double), ("tau0", C.c_double), ("lam0", C.c_double),
                 ("burn_in", C.c_int64), ("intercept", C.c_int32), ("likelihood", C.c_int32),
-                ("beta0", C.c_double), ("beta0_var", C.c_double)]
+                ("beta0", C.c_double), ("beta0_var", C.c_double), ("rng_version", C.c_int32)]
 
 
 _lib = None
@@ -245,10 +245,12 @@ class Chain:
 
     def __init__(self, graph: Graph, y, *, precision=FP64, seed=1, instance=0, x0=None,
                  a_tau=1.0, b_tau=1.0, a_lam=1.0, b_lam=1.0, tau0=1.0, lam0=1.0, burn_in=0,
-                 intercept=False, beta0=0.0, trials=None, beta0_var=0.0, stream=None):
+                 intercept=False, beta0=0.0, trials=None, beta0_var=0.0, rng_version=1,
+                 stream=None):
         """With ``trials`` (m_i) the chain is the binomial logit model and y
         holds the successes Y_i; ``beta0_var`` is then the prior variance of
-        beta0 (0 = flat)."""
+        beta0 (0 = flat).  ``rng_version`` 2 selects the paired site normals
+        (lattices of width a multiple of 4)."""
         L = lib()
         self.graph = graph
         self.n = graph.n
@@ -257,7 +259,7 @@ class Chain:
         binom = trials is not None
         self.model = Model(a_tau, b_tau, a_lam, b_lam, tau0, lam0, int(burn_in),
                            1 if intercept else 0, BINOMIAL if binom else GAUSSIAN, float(beta0),
-                           float(beta0_var))
+                           float(beta0_var), int(rng_version))
         if binom:
             tt = np.ascontiguousarray(trials, dtype=np.int32)
             if tt.size != self.n:

@@ -7,7 +7,8 @@ against the x87 long-double library:
   (m + 1/2) 2^-52 grid), every binade down to 2^-53, and the neighbourhoods
   of 1 and of the reduction's switch point sqrt(1/2);
 * cos_2pi_unit (cos(2 pi u) for u in [0, 1]): within 4e-16 absolute over
-  random uniforms and around the fold points k / 8.
+  random uniforms and around the fold points k / 8;
+* sin_2pi_unit (the sine branch of the paired normals): the same bound.
 
 The FP64 draws' agreement with the oracle's library functions rests on
 these bounds."""
@@ -118,6 +119,28 @@ def test_cos_2pi_unit_within_4e16(tmp_path):
     src = tmp_path / "cos_check.hip"
     exe = tmp_path / "cos_check"
     src.write_text(COS_PROGRAM)
+    subprocess.run([hipcc, "-O2", "-std=c++17", "--offload-host-only",
+                    "-I", os.path.join(ROOT, "paper_1702_05518_amd", "csrc"),
+                    "-I", os.path.join(ROOT, "include"), "-x", "hip", str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    n, worst = int(out[0]), float(out[1])
+    assert n > 2_000_000
+    assert worst <= 4e-16, worst
+
+
+SIN_PROGRAM = COS_PROGRAM.replace("gmrf::cos_2pi_unit(u)", "gmrf::sin_2pi_unit(u)").replace(
+    "cosl(2.0L", "sinl(2.0L")
+
+
+def test_sin_2pi_unit_within_4e16(tmp_path):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    assert "sin_2pi_unit" in SIN_PROGRAM and "sinl(" in SIN_PROGRAM
+    src = tmp_path / "sin_check.hip"
+    exe = tmp_path / "sin_check"
+    src.write_text(SIN_PROGRAM)
     subprocess.run([hipcc, "-O2", "-std=c++17", "--offload-host-only",
                     "-I", os.path.join(ROOT, "paper_1702_05518_amd", "csrc"),
                     "-I", os.path.join(ROOT, "include"), "-x", "hip", str(src), "-o", str(exe)],

@@ -82,6 +82,21 @@ def test_static_general_graph_and_fixed_hyperparameters(G, shape):
         assert_same(ref, st)
 
 
+def test_static_paired_normals(G):
+    # the paired random-number contract: a 256 x 200 8-neighbour FP64
+    # lattice, then a smaller 64 x 36 4-neighbour FP32 one (one block)
+    g1, y1 = lattice(G, 256, 200, 8, 9)
+    ref, st = twins(G, g1, y1, G.FP64, 13, rng_version=2)
+    ref.sweep(7)
+    st.sweep_static(7)
+    assert_same(ref, st)
+    g2, y2 = lattice(G, 64, 36, 4, 10)
+    ref2, st2 = twins(G, g2, y2, G.FP32_ACC64, 14, rng_version=2)
+    ref2.sweep(5)
+    st2.sweep_static(5)
+    assert_same(ref2, st2)
+
+
 def test_static_rejects_more_slots_than_the_array(G):
     g, y = lattice(G, 4096, 4096, 8, 7)
     ch = G.Chain(g, y, precision=G.FP32_ACC64, seed=1)
