@@ -88,12 +88,14 @@ ORACLE_RUN = textwrap.dedent("""
     rp, cl = inputs.lattice_csr(12, 12, 8)
     color, k = oracle.greedy_coloring(rp, cl)
     y = np.random.default_rng(1).normal(size=144)
-    for kw in ({}, {"intercept": True, "beta0": 0.5}, {"rho": 0.9}):
+    for kw in ({}, {"intercept": True, "beta0": 0.5}, {"rho": 0.9}, {"rng_version": 2}):
         ch = oracle.Chain(rp, cl, color, y, seed=3, burn_in=2, **kw)
         ch.sweeps(12)
         m, v = ch.stats()
         assert np.isfinite(m).all() and np.isfinite(v).all()
     assert oracle.components(rp, cl) == 1
+    key, br = oracle.rng_pairs(color)
+    assert key.size == 144 and int(br.sum()) > 0
     _, rp2, cl2 = inputs.delaunay_graph(200, data_seed=6)
     color2, _ = oracle.greedy_coloring(rp2, cl2)
     trials = np.random.default_rng(2).integers(0, 30, 200).astype(np.int32)
