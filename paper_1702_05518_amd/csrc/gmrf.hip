@@ -1461,7 +1461,6 @@ template <typename Real> struct FusedArgs {
     Real *x0, *x1;                                   // ping-pong state, slab order
     const Real *y;                                   // y (slab order)
     int k;                                           // colors
-    int max_local, max_r, max_adj;                   // sizes of the LDS image's parts
 };
 
 constexpr int kFusedGather = 8;                      // neighbour indices read per batch
@@ -1504,15 +1503,6 @@ __device__ __forceinline__ void csr_fused_block(const FusedArgs<Real> &fa, const
                                                 const int b, const int rel, const int fold)
 {
     extern __shared__ __align__(16) unsigned char fused_lds[];
-    Real *xs = reinterpret_cast<Real *>(fused_lds);
-    size_t off = lds_align16(sizeof(Real) * (size_t)fa.max_local);
-    Real *ys = reinterpret_cast<Real *>(fused_lds + off);
-    off += lds_align16(sizeof(Real) * (size_t)fa.max_r);
-    Real *zs = reinterpret_cast<Real *>(fused_lds + off);
-    off += lds_align16(sizeof(Real) * (size_t)fa.max_r);
-    unsigned short *lrow = reinterpret_cast<unsigned short *>(fused_lds + off);
-    off += lds_align16(sizeof(unsigned short) * (size_t)(fa.max_r + 1));
-    unsigned short *ladj = reinterpret_cast<unsigned short *>(fused_lds + off);
     __shared__ Real qtab[2 * kQtabDeg];
     __shared__ int sm[3 * kFusedMaxColors + 1];
     __shared__ FoldLds fl;
@@ -1527,6 +1517,18 @@ __device__ __forceinline__ void csr_fused_block(const FusedArgs<Real> &fa, const
     const int row0 = fa.ch_row[b], adj0 = fa.ch_adj[b], nadj = fa.ch_adj[b + 1] - adj0;
     const int *site = fa.loc_site + loc0;
     const unsigned *sid = fa.loc_id + loc0;
+    // the chunk's own LDS image (chunk_lds_bytes of its counts; the launch
+    // reserves the graph's largest): staged values, y and variates of R, R's
+    // local rows (padded to whole 16-byte vectors) and neighbours
+    Real *xs = reinterpret_cast<Real *>(fused_lds);
+    size_t off = lds_align16(sizeof(Real) * (size_t)nloc);
+    Real *ys = reinterpret_cast<Real *>(fused_lds + off);
+    off += lds_align16(sizeof(Real) * (size_t)nr);
+    Real *zs = reinterpret_cast<Real *>(fused_lds + off);
+    off += lds_align16(sizeof(Real) * (size_t)nr);
+    unsigned short *lrow = reinterpret_cast<unsigned short *>(fused_lds + off);
+    off += lds_align16(sizeof(unsigned short) * (size_t)(nr + 1));
+    unsigned short *ladj = reinterpret_cast<unsigned short *>(fused_lds + off);
     for (int i = (int)threadIdx.x; i < 3 * k + 1; i += kThreads)
         sm[i] = meta[i];
 
@@ -2441,8 +2443,7 @@ bool csr_persist_fits(const HostGraph &h, gmrf_precision p)
 bool csr_fused_fits(const HostGraph &h, gmrf_precision p, bool binomial)
 {
     return h.stencil == 0 && h.chunks_ok && !binomial &&
-           chunk_lds_bytes(h.max_local, h.max_r, h.max_adj, (int64_t)real_size(p)) <=
-               kFusedLaunchLds;
+           (p == GMRF_FP64 ? h.max_image8 : h.max_image4) <= kFusedLaunchLds;
 }
 
 // Default shape of a general-graph chain: the one block while it covers
@@ -2511,16 +2512,14 @@ template <typename Real> FusedArgs<Real> fused_args(const gmrf_chain *c, bool sw
     fa.x1 = static_cast<Real *>(c->d_x[swap ? 0 : 1]);
     fa.y = static_cast<const Real *>(c->d_y);
     fa.k = g->h.k;
-    fa.max_local = g->h.max_local;
-    fa.max_r = g->h.max_r;
-    fa.max_adj = g->h.max_adj;
     return fa;
 }
 
-// LDS of the chunked sweep for a graph's chunks in precision Real.
+// LDS of the chunked sweep for a graph's chunks in precision Real: the
+// largest chunk image (each block lays out its own chunk's).
 template <typename Real> size_t fused_lds_bytes(const HostGraph &h)
 {
-    return (size_t)chunk_lds_bytes(h.max_local, h.max_r, h.max_adj, sizeof(Real));
+    return (size_t)(sizeof(Real) == 8 ? h.max_image8 : h.max_image4);
 }
 
 template <typename Real>

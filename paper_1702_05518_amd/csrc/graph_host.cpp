@@ -133,6 +133,7 @@ ChunkSize chunk_size(const std::vector<int64_t> &rp, const int32_t *col, const i
                 hmark[col[e]] = tag;
                 cs.nloc++;
             }
+    cs.nadj = (cs.nadj + 7) / 8 * 8;     // padded as the chunk tables pad it
     return cs;
 }
 
@@ -338,7 +339,7 @@ void chunk_cells(int64_t n, const std::vector<int64_t> &rp, const int32_t *col,
             if ((int64_t)mem[c].size() < 64)
                 continue;
             const ChunkSize cs = chunk_size(rp, col, color, mem[c], mark, hmark, ++tag, scratch);
-            if (chunk_lds_bytes(cs.nloc, cs.nr, cs.nadj, 8) <= kFusedLdsBytes)
+            if (chunk_fits_lds(cs.nloc, cs.nr, cs.nadj))
                 continue;
             // two far-apart members: the farthest from the first member, then
             // the farthest from that (hop distances inside the cell)
@@ -440,6 +441,7 @@ void build_chunks(HostGraph *g, const std::vector<int32_t> &cell)
     g->loc_row.clear();
     g->loc_adj.clear();
     g->max_local = g->max_r = g->max_adj = 0;
+    g->max_image4 = g->max_image8 = 0;
     for (int32_t b = 0; b < g->nchunks; ++b) {
         R.clear();
         H.clear();
@@ -481,12 +483,13 @@ void build_chunks(HostGraph *g, const std::vector<int32_t> &cell)
         for (int32_t u : R)
             nadj += g->row_ptr[u + 1] - g->row_ptr[u];
         nadj = (nadj + 7) / 8 * 8;       // padded to whole 16-byte vectors
-        if (nadj > kMaxLocalAdj ||
-            chunk_lds_bytes(nloc, (int64_t)R.size(), nadj, 8) > kFusedLdsBytes)
+        if (nadj > kMaxLocalAdj || !chunk_fits_lds(nloc, (int64_t)R.size(), nadj))
             return;                      // this graph sweeps by color passes only
         g->max_local = std::max(g->max_local, (int32_t)nloc);
         g->max_r = std::max(g->max_r, (int32_t)R.size());
         g->max_adj = std::max(g->max_adj, (int32_t)nadj);
+        g->max_image4 = std::max(g->max_image4, chunk_lds_bytes(nloc, (int64_t)R.size(), nadj, 4));
+        g->max_image8 = std::max(g->max_image8, chunk_lds_bytes(nloc, (int64_t)R.size(), nadj, 8));
         int32_t s = 0;
         for (int32_t u : R)
             slot[u] = s++;

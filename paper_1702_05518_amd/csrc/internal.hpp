@@ -43,6 +43,7 @@ struct HostGraph {
     int32_t max_local = 0;               // most staged sites of any chunk
     int32_t max_r = 0;                   // most recomputed (R) sites of any chunk
     int32_t max_adj = 0;                 // most local neighbour entries of any chunk
+    int64_t max_image4 = 0, max_image8 = 0;   // largest chunk LDS image, FP32 / FP64 values
     bool chunks_ok = false;              // every chunk within the LDS and index limits
     std::vector<int32_t> ch_loc;         // nchunks + 1: first staged site of each chunk
     std::vector<int32_t> ch_row;         // nchunks + 1: first local row offset of each chunk
@@ -58,11 +59,14 @@ struct HostGraph {
 };
 
 // Owned sites per chunk, and the limits of a chunk: its LDS image (staged
-// values, y and normal variates of the R sites, local rows and neighbours) in FP64, and
-// 16-bit local offsets.  A launch reserves the largest image part by part
-// (chunk_lds_bytes of the per-part maxima), at most kFusedLaunchLds.
+// values, y and normal variates of the R sites, local rows and neighbours)
+// with FP64 and with FP32 values, and 16-bit local offsets.  A block lays out
+// its own chunk's image; a launch reserves the largest image of the graph
+// (at most kFusedLaunchLds).  The caps keep four FP64 or six FP32 blocks of
+// the chunked sweep kernel (with its static LDS) within a CU's 160 KB.
 constexpr int32_t kChunkSites = 512;
-constexpr int64_t kFusedLdsBytes = 40960;
+constexpr int64_t kFusedLdsBytes = 38000;
+constexpr int64_t kFusedLdsBytes32 = 25000;
 constexpr int64_t kFusedLaunchLds = 65536;
 constexpr int64_t kMaxLocalAdj = 65535;
 constexpr int32_t kFusedMaxColors = 32;  // colorings with more colors sweep by color passes
@@ -75,6 +79,13 @@ inline int64_t chunk_lds_bytes(int64_t nloc, int64_t nr, int64_t nadj, int64_t r
 {
     auto al = [](int64_t b) { return (b + 15) / 16 * 16; };
     return al(real_bytes * nloc) + 2 * al(real_bytes * nr) + al(2 * (nr + 1)) + al(2 * nadj);
+}
+
+// Does a chunk's image fit both caps?
+inline bool chunk_fits_lds(int64_t nloc, int64_t nr, int64_t nadj)
+{
+    return chunk_lds_bytes(nloc, nr, nadj, 8) <= kFusedLdsBytes &&
+           chunk_lds_bytes(nloc, nr, nadj, 4) <= kFusedLdsBytes32;
 }
 
 // Validate a description and build its host form; returns a gmrf_status.

@@ -59,6 +59,7 @@ static int check_graph(int gi, int64_t n, int32_t k, double rho, const std::vect
         for (int32_t p = g.slab_offsets[c]; p < g.slab_offsets[c + 1]; ++p)
             colpos[p] = c;
     std::vector<int> owner(n, -1);
+    int64_t img4 = 0, img8 = 0;
     for (int32_t b = 0; b < g.nchunks; ++b) {
         const int32_t l0 = g.ch_loc[b], nloc = g.ch_loc[b + 1] - l0;
         const int32_t *m = g.ch_meta.data() + (size_t)b * (3 * k + 1);
@@ -66,7 +67,11 @@ static int check_graph(int gi, int64_t n, int32_t k, double rho, const std::vect
         const int32_t r0 = g.ch_row[b], a0 = g.ch_adj[b], nadj = g.ch_adj[b + 1] - a0;
         CHECK(nloc >= nr && nr >= 1 && nloc <= g.max_local && nr <= g.max_r);
         CHECK(r0 % 8 == 0 && a0 % 8 == 0 && nadj % 8 == 0 && nadj <= g.max_adj);
-        CHECK(chunk_lds_bytes(nloc, nr, nadj, 8) <= kFusedLdsBytes);
+        CHECK(chunk_fits_lds(nloc, nr, nadj));
+        CHECK(chunk_lds_bytes(nloc, nr, nadj, 4) <= g.max_image4);
+        CHECK(chunk_lds_bytes(nloc, nr, nadj, 8) <= g.max_image8);
+        img4 = std::max(img4, chunk_lds_bytes(nloc, nr, nadj, 4));
+        img8 = std::max(img8, chunk_lds_bytes(nloc, nr, nadj, 8));
         CHECK(m[0] == 0);
         std::vector<int32_t> slot_of(n, -1);
         for (int32_t s = 0; s < nloc; ++s) {
@@ -104,6 +109,7 @@ static int check_graph(int gi, int64_t n, int32_t k, double rho, const std::vect
     }
     for (int64_t p = 0; p < n; ++p)
         CHECK(owner[p] >= 0);                                 // every site owned once
+    CHECK(img4 == g.max_image4 && img8 == g.max_image8);   // the launch reserves the largest
     return 0;
 }
 
