@@ -3,7 +3,8 @@ UndefinedBehaviorSanitizer, built with gcc / g++ (no device code).
 
 * The graph builder (graph_host.cpp) under tests/sanitize/graph_check.cpp,
   which also checks the invariants of the color slabs and the chunk tables
-  on Delaunay, lattice, hub and isolated-site graphs.
+  on Delaunay (up to 60,000 sites, where some chunks exceed the LDS caps
+  and split), lattice, hub and isolated-site graphs.
 * The oracle (gmrf_oracle.c), loaded through its own Python wrapper in a
   child process with the sanitizer runtime preloaded, over Gaussian,
   intercept, proper-CAR and binomial chains.
@@ -63,6 +64,7 @@ def test_graph_builder_under_sanitizers(tmp_path):
     a, b = rng.integers(0, 400, 900), rng.integers(0, 400, 900)
     keep = (a < 350) & (b < 350)                     # sites 350 .. 399 isolated
     graphs = [colored(*inputs.delaunay_graph(3000, data_seed=2)[1:]),
+              colored(*inputs.delaunay_graph(60000, data_seed=9)[1:], rho=0.95),
               colored(*inputs.delaunay_graph(700, data_seed=4)[1:], rho=0.9),
               colored(*inputs.lattice_csr(37, 29, 8)),
               colored(*inputs.lattice_csr(20, 20, 4)),
