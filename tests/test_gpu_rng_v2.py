@@ -165,6 +165,33 @@ def test_fp32_multi_tile_against_fp64_oracle(G, orc):
     assert np.max(np.abs(mean - om)) <= 1e-4
 
 
+def test_checkpoint_resume_autotune_and_timed_sweeps(G, orc):
+    """The paired contract's draws are keyed by (seed, instance, sweep, key
+    site) like version 1's: a chain resumed from its state and accumulators
+    continues bit for bit, the autotuner leaves a chain unchanged, and timed
+    sweeps equal plain ones."""
+    rows, cols, st = 130, 140, 8
+    wl = inputs.lattice_workload(rows, cols, st, noise_sd=0.1, data_seed=4)
+    g = G.Graph(lattice=(rows, cols, st))
+    kw = dict(precision=G.FP64, seed=21, instance=3, rng_version=2)
+    full = G.Chain(g, wl["y"], **kw)
+    full.sweep(12)
+    part = G.Chain(g, wl["y"], **kw)
+    part.sweep(5)
+    x, tau, lam, sw = part.get_state()
+    s1, s2, nacc = part.get_accumulators()
+    res = G.Chain(g, wl["y"], **kw)
+    res.set_state(x, tau, lam, sw)
+    res.set_accumulators(s1, s2, nacc)
+    best, _ = res.autotune(reps=3)
+    res.set_tile(full.tile[0])          # the shape of the uninterrupted chain
+    ms, span = res.sweep_timed(7, span=True)
+    assert 0.0 < ms <= span and best in (0, 1, 2)
+    a, b = full.get_state(), res.get_state()
+    assert np.array_equal(a[0], b[0]) and a[1:] == b[1:]
+    assert np.array_equal(full.posterior_stats()[0], res.posterior_stats()[0])
+
+
 def test_lattice2048_two_sweeps_fp64_all_sites(G, orc):
     """The 2048 x 2048 8-neighbour workload in the benchmark's launch shape:
     two captured FP64 sweeps from an injected state (the first sweep's end
