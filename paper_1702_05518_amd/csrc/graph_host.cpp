@@ -151,9 +151,9 @@ ChunkSize chunk_size(const std::vector<int64_t> &rp, const int32_t *col, const i
 //     to the nearest seed (graph distance), a cell closing at 5/4 of the
 //     chunk size; sites left over seed further cells.  Cells below a quarter
 //     of the chunk size join their smallest neighbouring cell.
-//  4. A cell whose chunk would outgrow the LDS limit (FP64) is split in two
-//     by distance from two far-apart members, until every chunk fits or
-//     the cell is small.
+//  4. A cell whose chunk would outgrow either LDS cap (FP64 or FP32 values)
+//     is split in two by distance from two far-apart members, until every
+//     chunk fits or the cell is small.
 // The cells are compact (a ball of the graph), which keeps the recomputed
 // closure and the read-only halo of each chunk small.
 void chunk_cells(int64_t n, const std::vector<int64_t> &rp, const int32_t *col,
