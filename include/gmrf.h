@@ -229,7 +229,8 @@ int gmrf_chain_destroy(gmrf_chain *c);
 /* Device workspace bytes of one binomial chain on a general graph g with the
  * given trials (host, n values m_i, original order): the Gaussian layout plus
  * the trials, the Polya-Gamma term chunk tables and sums (about 6 bytes per
- * trial), and a per-site envelope and psi (about 40 bytes per site).  Returns 0 and sets the error message on bad input. */
+ * trial), and a per-site envelope and psi (about 40 bytes per site).
+ * Returns 0 and sets the error message on bad input. */
 size_t gmrf_binomial_footprint(const gmrf_graph *g, gmrf_precision p, const int32_t *trials);
 
 /* Create a binomial logit chain (Sec. 3.2) on a general graph: successes

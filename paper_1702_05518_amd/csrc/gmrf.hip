@@ -584,11 +584,12 @@ __device__ __forceinline__ void qtab_fill(Real *qtab, Real tau, Real lam)
 
 // One site of Algorithm 1 on the LDS tile: neighbour sum in ascending
 // original-id order, conditional mean and precision, the draw with the
-// site's standard normal z; for interior sites also the q / sse terms.  Cells of the tile outside the lattice hold
-// 0 (lattice_stage), so the neighbour sum adds every stencil cell: a missing
-// neighbour adds 0, which leaves each partial sum of the in-lattice
-// neighbours unchanged.  INTERIOR: the tile and its halo lie inside the
-// lattice, so every site has all its neighbours (compile-time flags).
+// site's standard normal z; for interior sites also the q / sse terms.
+// Cells of the tile outside the lattice hold 0 (lattice_load), so the
+// neighbour sum adds every stencil cell: a missing neighbour adds 0, which
+// leaves each partial sum of the in-lattice neighbours unchanged.
+// INTERIOR: the tile and its halo lie inside the lattice, so every site has
+// all its neighbours (compile-time flags).
 template <typename Real, typename Cfg, int J, bool INTERIOR, bool B0>
 __device__ __forceinline__ void lattice_site(Real *xs, Real yv, Real z, int r, int c, int r0,
                                              int c0, int rows, int cols, const SiteCtx<Real> &sc,
