@@ -5,8 +5,10 @@ intrinsic CAR on the 2048 x 2048 block image (Gamma(1,1) priors, seed 1,
 instance 0, burn-in 0) and stores, for a fixed set of sites, the posterior
 mean and variance and the final field, plus the tau / lam trajectory and the
 last q / sse.  Only the oracle and the seeded input generator are used.
+--rng-version 2 runs the paired random-number contract and writes the
+_v2 file.
 
-    python tests/golden/make_lattice2048_reference.py [--threads N]
+    python tests/golden/make_lattice2048_reference.py [--threads N] [--rng-version 2]
 """
 import argparse
 import os
@@ -24,7 +26,8 @@ from paper_1702_05518_amd import inputs  # noqa: E402
 
 ROWS = COLS = 2048
 SWEEPS = 1000
-OUT = os.path.join(HERE, "lattice2048_s8_fp64_oracle.npz")
+OUT = {1: os.path.join(HERE, "lattice2048_s8_fp64_oracle.npz"),
+       2: os.path.join(HERE, "lattice2048_s8_fp64_oracle_v2.npz")}
 
 
 def sample_sites(rows, cols):
@@ -39,11 +42,12 @@ def sample_sites(rows, cols):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
+    ap.add_argument("--rng-version", type=int, default=1, choices=(1, 2))
     args = ap.parse_args()
     oracle.build(force=False)
     wl = inputs.lattice_workload(ROWS, COLS, 8, noise_sd=0.1, data_seed=1)
     ch = oracle.Chain(wl["row_ptr"], wl["col"], wl["color"], wl["y"], rho=1.0, seed=1,
-                      instance=0)
+                      instance=0, rng_version=args.rng_version)
     taus, lams = np.empty(SWEEPS), np.empty(SWEEPS)
     t0 = time.time()
     for t in range(SWEEPS):
@@ -54,10 +58,11 @@ def main():
                   flush=True)
     mean, var = ch.stats()
     sites = sample_sites(ROWS, COLS)
-    np.savez_compressed(OUT, sites=sites, mean=mean[sites], var=var[sites], x=ch.x[sites],
+    out = OUT[args.rng_version]
+    np.savez_compressed(out, sites=sites, mean=mean[sites], var=var[sites], x=ch.x[sites],
                         tau=taus, lam=lams, q=ch.q, sse=ch.sse, sweeps=SWEEPS,
                         full_mean_abs_max=np.abs(mean).max())
-    print("wrote", OUT)
+    print("wrote", out)
 
 
 if __name__ == "__main__":

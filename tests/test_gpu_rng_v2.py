@@ -214,6 +214,44 @@ def test_lattice2048_two_sweeps_fp64_all_sites(G, orc):
     assert rel(tau, oc.tau) <= RTOL64 and rel(lam, oc.lam) <= RTOL64
 
 
+REF2048_V2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                          "lattice2048_s8_fp64_oracle_v2.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(REF2048_V2), reason="reference not generated")
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_lattice2048_1000_sweeps_against_reference(G, prec):
+    """The 2048 x 2048 8-neighbour workload for 1000 captured sweeps under
+    the paired contract against the stored FP64 oracle reference
+    (make_lattice2048_reference.py --rng-version 2): FP64 field, posterior
+    mean and tau / lam after every sweep at 1e-12; FP32 posterior mean
+    within 1e-4."""
+    ref = np.load(REF2048_V2)
+    wl = inputs.lattice_workload(2048, 2048, 8, noise_sd=0.1, data_seed=1)
+    p = G.FP32_ACC64 if prec == "fp32" else G.FP64
+    ch = G.Chain(G.Graph(lattice=(2048, 2048, 8)), wl["y"], precision=p, seed=1, rng_version=2)
+    ch.enable_trace(1000)
+    for _ in range(10):
+        ch.sweep(100, capture=True)
+    x, _, _, sw = ch.get_state()
+    assert sw == 1000
+    tr = ch.trace()
+    mean, var, nacc = ch.posterior_stats()
+    assert nacc == 1000
+    sites = ref["sites"]
+    mean_err = np.max(np.abs(mean[sites] - ref["mean"]))
+    print(f"rng v2 {prec}: posterior mean max abs err {mean_err:.3e}, "
+          f"tau rel {rel(tr[:, 0], ref['tau']):.3e}")
+    if prec == "fp32":
+        assert mean_err <= 1e-4
+        assert rel(tr[:, 0], ref["tau"]) <= 1e-3 and rel(tr[:, 1], ref["lam"]) <= 1e-3
+    else:
+        assert rel(mean[sites], ref["mean"]) <= RTOL64
+        assert rel(x[sites], ref["x"]) <= RTOL64
+        assert rel(tr[:, 0], ref["tau"]) <= RTOL64 and rel(tr[:, 1], ref["lam"]) <= RTOL64
+        assert np.max(np.abs(var[sites] - ref["var"])) <= 1e-9 * float(np.max(ref["var"]))
+
+
 def test_refusals(G):
     wl = inputs.lattice_workload(8, 6, 4, noise_sd=0.1, data_seed=1)
     with pytest.raises(G.GmrfError):      # width not a multiple of 4
