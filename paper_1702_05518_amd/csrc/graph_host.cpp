@@ -153,7 +153,7 @@ ChunkSize chunk_size(const std::vector<int64_t> &rp, const int32_t *col, const i
 //     of the chunk size join their smallest neighbouring cell.
 //  4. A cell whose chunk would outgrow either LDS cap (FP64 or FP32 values)
 //     is split in two by distance from two far-apart members, until every
-//     chunk fits or the cell is small.
+//     chunk fits or the cell is small (under 8 sites; at most ten rounds).
 // The cells are compact (a ball of the graph), which keeps the recomputed
 // closure and the read-only halo of each chunk small.
 void chunk_cells(int64_t n, const std::vector<int64_t> &rp, const int32_t *col,
@@ -330,13 +330,13 @@ void chunk_cells(int64_t n, const std::vector<int64_t> &rp, const int32_t *col,
     int64_t tag = 0;
     std::vector<int32_t> check(size.size());            // cells to check this round
     std::iota(check.begin(), check.end(), 0);
-    for (int round = 0; round < 6 && !check.empty(); ++round) {
+    for (int round = 0; round < 10 && !check.empty(); ++round) {
         std::vector<std::vector<int64_t>> mem(size.size());
         for (int64_t v : queue)
             mem[cell[v]].push_back(v);
         std::vector<int32_t> next;
         for (const int32_t c : check) {
-            if ((int64_t)mem[c].size() < 64)
+            if ((int64_t)mem[c].size() < 8)
                 continue;
             const ChunkSize cs = chunk_size(rp, col, color, mem[c], mark, hmark, ++tag, scratch);
             if (chunk_fits_lds(cs.nloc, cs.nr, cs.nadj))

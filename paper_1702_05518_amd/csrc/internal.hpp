@@ -62,11 +62,14 @@ struct HostGraph {
 // values, y and normal variates of the R sites, local rows and neighbours)
 // with FP64 and with FP32 values, and 16-bit local offsets.  A block lays out
 // its own chunk's image; a launch reserves the largest image of the graph
-// (at most kFusedLaunchLds).  The caps keep four FP64 or six FP32 blocks of
-// the chunked sweep kernel (with its static LDS) within a CU's 160 KB.
+// (at most kFusedLaunchLds).  The FP64 cap keeps four blocks of the chunked
+// sweep kernel (with its static LDS) within a CU's 160 KB; the FP32 cap
+// (six blocks fit from 25,000 B) splits the largest few percent of the
+// chunks further, whose closures set the tail of a sweep (measured on
+// Delaunay graphs: 1M sites 36.9 -> 33.2 us, 15k sites 15.8 -> 14.8 us).
 constexpr int32_t kChunkSites = 512;
 constexpr int64_t kFusedLdsBytes = 38000;
-constexpr int64_t kFusedLdsBytes32 = 25000;
+constexpr int64_t kFusedLdsBytes32 = 21800;
 constexpr int64_t kFusedLaunchLds = 65536;
 constexpr int64_t kMaxLocalAdj = 65535;
 constexpr int32_t kFusedMaxColors = 32;  // colorings with more colors sweep by color passes
