@@ -2097,9 +2097,12 @@ struct gmrf_batch {
     int lat_tile_count[8] = {};
     void *csr_jobs[2] = {};
     CsrBlock *csr_blocks[2] = {};
-    void *fused_jobs[2] = {};                     // chunked general-graph chains (shape 1)
-    FusedBlock *fused_blocks[2] = {};
-    int fused_count[2] = {};
+    // chunked general-graph chains (shape 1), by intercept setting g: groups
+    // g (ended in the next sweep's launch) and 2 + g (more partial slots than
+    // kDeferredMaxSlots: every sweep ends in the per-sweep commit launch)
+    void *fused_jobs[4] = {};
+    FusedBlock *fused_blocks[4] = {};
+    int fused_count[4] = {};
     int fused_lds = 0;
     std::vector<int> csr_color_off[2];            // per color index: first block
     SweepArgs *unit_args = nullptr;               // per chain, for the unit-variate launches
@@ -2790,10 +2793,10 @@ struct BatchImage {
     size_t off_lat_jobs[8] = {}, off_lat_tiles[8] = {};
     size_t off_csr_jobs[2] = {}, off_csr_blocks[2] = {}, off_units = 0;
     size_t off_csr_commit = 0, off_lat_commit = 0;
-    size_t off_fused_jobs[2] = {}, off_fused_blocks[2] = {};
+    size_t off_fused_jobs[4] = {}, off_fused_blocks[4] = {};
     int n_csr = 0, n_lat = 0;
     int lat_tile_count[8] = {};
-    int fused_count[2] = {};
+    int fused_count[4] = {};
     int fused_lds = 0;                            // bytes of LDS of the batched chunked launch
     std::vector<int> csr_color_off[2];
 };
@@ -2819,12 +2822,17 @@ void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im, int 
     std::vector<CsrJob<Real>> cjobs[2];
     std::vector<std::vector<CsrBlock>> cblocks[2];   // per color index
     std::vector<SweepArgs> units, csr_commit, lat_commit;   // lat_commit: every one-launch chain
-    std::vector<FusedJob<Real>> fjobs[2];
-    std::vector<FusedBlock> fblocks[2];
+    std::vector<FusedJob<Real>> fjobs[4];
+    std::vector<FusedBlock> fblocks[4];
     for (const gmrf_chain *c : cs) {
         SweepArgs a = make_args(c, 0u);
+        // shared launches end a one-launch chain's sweep in the next, except a
+        // chunked chain with more partial slots than every block can sum,
+        // which commits every sweep as it does on its own
+        const bool own_commit = c->lat_tile == kFused && !is_lattice(c->g) &&
+                                c->total_slots > kDeferredMaxSlots;
         if (one_launch(c))
-            a.deferred = 1;     // shared launches end every one-launch chain's sweep in the next
+            a.deferred = own_commit ? 0 : 1;
         units.push_back(a);
         const HostGraph &h = c->g->h;
         const int g = c->model.intercept ? 1 : 0;
@@ -2840,11 +2848,12 @@ void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im, int 
             for (int t = 0; t < tiles; ++t)
                 ltiles[w].push_back(LatTile{job, t});
         } else if (c->lat_tile == kFused) {
-            const int job = (int)fjobs[g].size();
-            fjobs[g].push_back(FusedJob<Real>{fused_args<Real>(c), a});
-            lat_commit.push_back(a);
+            const int fg = own_commit ? 2 + g : g;
+            const int job = (int)fjobs[fg].size();
+            fjobs[fg].push_back(FusedJob<Real>{fused_args<Real>(c), a});
+            (own_commit ? csr_commit : lat_commit).push_back(a);
             for (int b = 0; b < h.nchunks; ++b)
-                fblocks[g].push_back(FusedBlock{job, b});
+                fblocks[fg].push_back(FusedBlock{job, b});
             im.fused_lds = std::max(im.fused_lds, (int)fused_lds_bytes<Real>(h));
         } else {
             const int job = (int)cjobs[g].size();
@@ -2876,9 +2885,11 @@ void build_batch_image(const std::vector<gmrf_chain *> &cs, BatchImage &im, int 
         }
         im.off_csr_jobs[g] = append(im.bytes, cjobs[g]);
         im.off_csr_blocks[g] = append(im.bytes, flat);
-        im.off_fused_jobs[g] = append(im.bytes, fjobs[g]);
-        im.off_fused_blocks[g] = append(im.bytes, fblocks[g]);
-        im.fused_count[g] = (int)fblocks[g].size();
+    }
+    for (int fg = 0; fg < 4; ++fg) {
+        im.off_fused_jobs[fg] = append(im.bytes, fjobs[fg]);
+        im.off_fused_blocks[fg] = append(im.bytes, fblocks[fg]);
+        im.fused_count[fg] = (int)fblocks[fg].size();
     }
     im.off_units = append(im.bytes, units);
     im.off_csr_commit = append(im.bytes, csr_commit);
@@ -2965,10 +2976,12 @@ int install_image(gmrf_batch *b, const BatchImage &im, hipStream_t stream)
     for (int g = 0; g < 2; ++g) {
         b->csr_jobs[g] = b->ws + im.off_csr_jobs[g];
         b->csr_blocks[g] = reinterpret_cast<CsrBlock *>(b->ws + im.off_csr_blocks[g]);
-        b->fused_jobs[g] = b->ws + im.off_fused_jobs[g];
-        b->fused_blocks[g] = reinterpret_cast<FusedBlock *>(b->ws + im.off_fused_blocks[g]);
-        b->fused_count[g] = im.fused_count[g];
         b->csr_color_off[g] = im.csr_color_off[g];
+    }
+    for (int fg = 0; fg < 4; ++fg) {
+        b->fused_jobs[fg] = b->ws + im.off_fused_jobs[fg];
+        b->fused_blocks[fg] = reinterpret_cast<FusedBlock *>(b->ws + im.off_fused_blocks[fg]);
+        b->fused_count[fg] = im.fused_count[fg];
     }
     b->unit_args = reinterpret_cast<SweepArgs *>(b->ws + im.off_units);
     b->csr_commit = reinterpret_cast<SweepArgs *>(b->ws + im.off_csr_commit);
@@ -3029,6 +3042,13 @@ void launch_fused_group(const gmrf_batch *b, int hyper, int rel, int fold, hipSt
                            dim3(kThreads), (size_t)b->fused_lds, s,
                            static_cast<const FusedJob<Real> *>(b->fused_jobs[g]),
                            b->fused_blocks[g], hyper, rel, fold);
+    // the chains whose every sweep ends in the per-sweep commit: each sweep
+    // runs from the committed state (relative sweep 0, nothing to end)
+    if (b->fused_count[2 + g] > 0)
+        hipLaunchKernelGGL((csr_fused_batch_kernel<Real, B0>), dim3(b->fused_count[2 + g]),
+                           dim3(kThreads), (size_t)b->fused_lds, s,
+                           static_cast<const FusedJob<Real> *>(b->fused_jobs[2 + g]),
+                           b->fused_blocks[2 + g], hyper, 0, 0);
 }
 
 template <typename Real>

@@ -70,6 +70,31 @@ def test_batch_equals_standalone(G, prec, capture):
         assert same(a, b)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_with_a_chunked_chain_of_more_slots_than_the_folded_end(G, prec):
+    """A chunked chain with more partial slots (chunks) than every block of
+    the next launch can sum commits every sweep, in a batch as on its own:
+    the 1M-site Delaunay graph (over 2048 chunks) beside a lattice and a
+    small chunked graph, standalone against batched, plain and captured,
+    bit for bit."""
+    p = G.FP32_ACC64 if prec == "fp32" else G.FP64
+    wl = inputs.delaunay_workload(1_000_000, data_seed=3, rho=0.95)
+    color, k = G.greedy_coloring(wl["row_ptr"], wl["col"])
+    big = (G.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color, num_colors=k,
+                   rho=0.95), wl["y"])
+    wls = [big] + [workloads(G)[i] for i in (2, 5)]
+    solo = make_chains(G, wls, p, 300)
+    mixed = make_chains(G, wls, p, 300)
+    assert solo[0].tile[0] == 1
+    for c in solo:
+        c.sweep(7)
+    batch = G.Batch(mixed)
+    batch.sweep(4)
+    batch.sweep(3, capture=True)
+    for a, b in zip(solo, mixed):
+        assert same(a, b)
+
+
 def test_batch_subsets_and_fixed_hyper(G):
     wls = workloads(G)[:4]
     solo = make_chains(G, wls, G.FP32_ACC64, 7)
