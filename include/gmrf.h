@@ -440,10 +440,12 @@ size_t gmrf_batch_footprint(gmrf_chain *const *chains, int32_t count);
  * launches per sweep: one lattice launch per stencil covering the tiles of
  * every lattice chain, one chunked launch (per intercept setting) covering
  * the chunks of every shape-1 general-graph chain (these chains' sweep
- * kernels end their previous sweep), one launch per color index covering
- * that color's slab of every other general-graph chain followed by one
- * commit launch with a block per such chain, and at the end of the call one
- * commit launch with a block per one-launch (lattice or shape-1) chain
+ * kernels end their previous sweep; chains with more than 2048 chunks get a
+ * launch of their own and end every sweep in the per-sweep commit, as on
+ * their own), one launch per color index covering that color's slab of
+ * every other general-graph chain followed by one commit launch with a
+ * block per such chain, and at the end of the call one commit launch with a
+ * block per one-launch (lattice or shape-1) chain
  * (Sec. 2.3, Algorithm 1, for every chain; the independent chains need no
  * communication).  Each chain keeps its own workspace, state, reductions and
  * random streams, so its results equal those of gmrf_sweep on that chain bit
