@@ -328,7 +328,7 @@ void chunk_cells(int64_t n, const std::vector<int64_t> &rp, const int32_t *col,
     // 4. split cells whose chunk would outgrow the LDS limit
     std::vector<int64_t> mark(n, -1), hmark(n, -1), scratch, dist(n, -1);
     int64_t tag = 0;
-    std::vector<int32_t> check(size.size());            // cells to check this round
+    std::vector<int32_t> check(size.size());            // cells to check in this pass
     std::iota(check.begin(), check.end(), 0);
     for (int round = 0; round < 10 && !check.empty(); ++round) {
         std::vector<std::vector<int64_t>> mem(size.size());
