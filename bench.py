@@ -38,6 +38,7 @@ HBM_PEAK_GBS = 8000.0
 # write + y read + S1 / S2 read-modify-write; a general graph adds its CSR
 # row (row offset + column indices at mean degree ~6) and the slab-to-id map
 BYTES_PER_SITE = {"fp32_acc": 44, "fp64_acc": 56}
+GRAPH_PROBE_SITES = 1_000_000       # sites of the Delaunay counter probe
 BURN_IN_BYTES_PER_SITE = 12          # FP32 burn-in sweep: x read + x write + y read
 CSR_BYTES_PER_SITE = {"fp32_acc": 72, "fp64_acc": 84}
 METRIC = ("site-updates/s + HBM GB/s fraction per sweep; p50/p99 solve latency "
@@ -191,6 +192,69 @@ def traffic_summary(fetch_csv, write_csv, dram_csv, side, commands):
                 f"{wr * write_b / 1e6:.1f} MB |", ""]
         fig.update(dram_read_share=float(rd), dram_write_share=float(wr),
                    dram_bytes=float(rd * fetch_b + wr * write_b))
+    return "\n".join(out), fig
+
+
+def _fused_variant(name):
+    """'fp32' / 'fp64' for the chunked general-graph sweep kernel without an
+    intercept, else None."""
+    n = name.replace("gmrf::", "").replace(" ", "")
+    for real, tag in (("float", "fp32"), ("double", "fp64")):
+        if f"csr_fused_kernel<{real},false>" in n:
+            return tag
+    return None
+
+
+def graph_traffic_summary(fetch_csv, write_csv, commands):
+    """Markdown summary of the counter probes of the 1,000,000-site Delaunay
+    workload (bench.py --probe --probe-graph): FETCH_SIZE and WRITE_SIZE of the
+    chunked sweep kernel, FP32 and FP64, each scaled by the counter's reading
+    for the probe's 512 MiB device copy, against the algorithmic bytes."""
+    def per_kernel(path, counter):
+        copy, sweep = [], {}
+        for r in _csv_rows(path):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"])
+            if r["Kernel_Name"] == "__amd_rocclr_copyBuffer":
+                copy.append(v)
+            else:
+                tag = _fused_variant(r["Kernel_Name"])
+                if tag:
+                    sweep.setdefault(tag, []).append(v)
+        return max(copy), sweep
+
+    copy_kib = 512 * 1024
+    f_copy, f_sweep = per_kernel(fetch_csv, "FETCH_SIZE")
+    w_copy, w_sweep = per_kernel(write_csv, "WRITE_SIZE")
+    f_scale, w_scale = copy_kib / f_copy, copy_kib / w_copy
+    n = GRAPH_PROBE_SITES
+    out = ["# HBM traffic counters: chunked general-graph sweep kernel, Delaunay graph of "
+           "1,000,000 sites", "",
+           "Commands (from the repository root on the GPU box):", "", "```", *commands, "```", "",
+           "`bench.py --probe --probe-graph` first copies 512 MiB device-to-device (one dispatch "
+           "of the runtime's `__amd_rocclr_copyBuffer`), which must read and write exactly "
+           "524288 KiB: its readings give each counter's scale.", "",
+           f"Scale factors: FETCH_SIZE {f_scale:.3f} (the copy's reading {f_copy:.1f} KiB), "
+           f"WRITE_SIZE {w_scale:.3f} (the copy's reading {w_copy:.1f} KiB).", "",
+           "| Kernel | launches | FETCH_SIZE, scaled MB | WRITE_SIZE, scaled MB | total MB | "
+           "B per site | algorithmic B per site |", "|---|---|---|---|---|---|---|"]
+    fig = {"sites": n, "fetch_scale": f_scale, "write_scale": w_scale}
+    for tag, prec in (("fp32", "fp32_acc"), ("fp64", "fp64_acc")):
+        if tag not in f_sweep or tag not in w_sweep:
+            continue
+        fb = float(np.mean(f_sweep[tag])) * f_scale * 1024
+        wb = float(np.mean(w_sweep[tag])) * w_scale * 1024
+        out.append(f"| `csr_fused_kernel` {tag} | {len(f_sweep[tag])} | {fb / 1e6:.1f} | "
+                   f"{wb / 1e6:.1f} | {(fb + wb) / 1e6:.1f} | {(fb + wb) / n:.1f} | "
+                   f"{CSR_BYTES_PER_SITE[prec]} |")
+        fig[tag] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_site": (fb + wb) / n}
+    out += ["", "The algorithmic bytes count each site's value, y, accumulators and CSR "
+            "adjacency (4-byte column indices) once per sweep.  The kernel reads instead its "
+            "chunk tables (16-bit local rows and neighbours, slab positions, original ids) "
+            "and re-reads the values of each chunk's halo and recomputed closure.  The "
+            "counters measure the L2's traffic to the fabric, Infinity Cache hits included.",
+            ""]
     return "\n".join(out), fig
 
 
@@ -551,21 +615,31 @@ def cpu_baseline(wl, seconds_budget=10.0, wl1m=None):
             "delaunay1m_sample": big}
 
 
-def probe(torch, gmrf, inputs, steps, side=ROWS, variants=False):
+def probe(torch, gmrf, inputs, steps, side=ROWS, variants=False, on_graph=False):
     """A plain device copy of 512 MiB (its counters give the scale factor of
     FETCH_SIZE / WRITE_SIZE), then warm-up and `steps` FP32 sweeps, one launch
     each, of the benchmark workload (side x side, 8 neighbours).  variants:
-    then the same for FP32 under rng_version 2 and FP64 under both."""
+    then the same for FP32 under rng_version 2 and FP64 under both.  on_graph:
+    instead the 1,000,000-site Delaunay workload's chunked sweeps, FP32 then
+    FP64."""
     src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
-    wl = inputs.lattice_workload(side, side, STENCIL, noise_sd=0.1, data_seed=1, with_csr=False)
-    graph = gmrf.Graph(lattice=(side, side, STENCIL))
-    runs = [(gmrf.FP32_ACC64, 1)]
-    if variants:
-        runs += [(gmrf.FP32_ACC64, 2), (gmrf.FP64, 1), (gmrf.FP64, 2)]
+    if on_graph:
+        wl = inputs.delaunay_workload(GRAPH_PROBE_SITES, data_seed=3, rho=0.95)
+        color, k = gmrf.greedy_coloring(wl["row_ptr"], wl["col"])
+        graph = gmrf.Graph(row_ptr=wl["row_ptr"], col_idx=wl["col"], color=color, num_colors=k,
+                           rho=0.95)
+        runs = [(gmrf.FP32_ACC64, 1), (gmrf.FP64, 1)]
+    else:
+        wl = inputs.lattice_workload(side, side, STENCIL, noise_sd=0.1, data_seed=1,
+                                     with_csr=False)
+        graph = gmrf.Graph(lattice=(side, side, STENCIL))
+        runs = [(gmrf.FP32_ACC64, 1)]
+        if variants:
+            runs += [(gmrf.FP32_ACC64, 2), (gmrf.FP64, 1), (gmrf.FP64, 2)]
     for prec, v in runs:
         chain = gmrf.Chain(graph, wl["y"], precision=prec, seed=1, rng_version=v)
         chain.sweep(5, hyper=True)
@@ -573,8 +647,9 @@ def probe(torch, gmrf, inputs, steps, side=ROWS, variants=False):
             chain.sweep(1, hyper=True)
         torch.cuda.synchronize()
         del chain
-    print(json.dumps({"probe": "copy 512 MiB + sweeps", "side": side, "sweeps": steps + 5,
-                      "chains": len(runs)}), flush=True)
+    print(json.dumps({"probe": "copy 512 MiB + sweeps", "workload": "delaunay1m" if on_graph
+                      else f"lattice {side}x{side}", "sweeps": steps + 5, "chains": len(runs)}),
+          flush=True)
 
 
 def bench_batch(torch, gmrf, inputs, args):
@@ -857,7 +932,8 @@ def main():
                          "with the paper's burn-in fractions 4/5 and 1/2)")
     ap.add_argument("--summarize", nargs="+", metavar="ARG",
                     help="print a profiles/ summary: 'trace KERNEL_TRACE_CSV', 'traffic SIDE "
-                         "FETCH_CSV WRITE_CSV [DRAM_CSV]' or 'counters CSV...' (rocprofv3 "
+                         "FETCH_CSV WRITE_CSV [DRAM_CSV]', 'traffic-graph FETCH_CSV WRITE_CSV' or "
+                         "'counters CSV...' (rocprofv3 "
                          "outputs; no GPU needed)")
     ap.add_argument("--command", action="append", default=[],
                     help="with --summarize: a command line to record in the summary")
@@ -865,6 +941,9 @@ def main():
                     help="lattice side of --probe (8 neighbours, FP32)")
     ap.add_argument("--probe-variants", action="store_true",
                     help="with --probe: also FP32 under rng_version 2 and FP64 under both")
+    ap.add_argument("--probe-graph", action="store_true",
+                    help="with --probe: the 1,000,000-site Delaunay workload (chunked sweeps, "
+                         "FP32 then FP64) instead of the lattice")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe for rocprofv3 --pmc: a 512 MiB device copy (the "
                          "scale reference for FETCH_SIZE / WRITE_SIZE), then --steps sweeps")
@@ -875,6 +954,8 @@ def main():
             text, fig = trace_summary(rest[0], args.command)
         elif kind == "counters":
             text, fig = counter_summary(rest, args.command)
+        elif kind == "traffic-graph":
+            text, fig = graph_traffic_summary(rest[0], rest[1], args.command)
         else:
             text, fig = traffic_summary(rest[1], rest[2], rest[3] if len(rest) > 3 else None,
                                         int(rest[0]), args.command)
@@ -897,7 +978,8 @@ def main():
     gmrf.lib()
     n = ROWS * COLS
     if args.probe:
-        probe(torch, gmrf, inputs, args.steps, args.probe_side, args.probe_variants)
+        probe(torch, gmrf, inputs, args.steps, args.probe_side, args.probe_variants,
+              args.probe_graph)
         return
     if args.workload == "batch512":
         bench_batch(torch, gmrf, inputs, args)
