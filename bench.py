@@ -54,6 +54,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 TRACE_SUMMARY = os.path.join(PROFILES, "lattice_sweep_2048x2048_s8_kernel_trace.md")
 TRAFFIC_SUMMARY = os.path.join(PROFILES, "lattice_sweep_2048x2048_s8_fp32_traffic.md")
 TRAFFIC_SUMMARY_BIG = os.path.join(PROFILES, "lattice_sweep_8192x8192_s8_fp32_traffic.md")
+TRAFFIC_SUMMARY_GRAPH = os.path.join(PROFILES, "chunked_sweep_delaunay1m_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1702_05518_amd", "csrc", f)
                   for f in ("gmrf.hip", "rng.hpp")]
 
@@ -239,7 +240,8 @@ def graph_traffic_summary(fetch_csv, write_csv, commands):
            f"WRITE_SIZE {w_scale:.3f} (the copy's reading {w_copy:.1f} KiB).", "",
            "| Kernel | launches | FETCH_SIZE, scaled MB | WRITE_SIZE, scaled MB | total MB | "
            "B per site | algorithmic B per site |", "|---|---|---|---|---|---|---|"]
-    fig = {"sites": n, "fetch_scale": f_scale, "write_scale": w_scale}
+    fig = {"sites": n, "fetch_scale": f_scale, "write_scale": w_scale,
+           "kernel_sources_sha256": kernel_sources_sha256()}
     for tag, prec in (("fp32", "fp32_acc"), ("fp64", "fp64_acc")):
         if tag not in f_sweep or tag not in w_sweep:
             continue
@@ -486,6 +488,7 @@ def delaunay_row(torch, gmrf, inputs, args, wl):
                        f"greedy coloring ({k} colors), accumulating sweeps",
            "sites": n, "colors": int(k)}
     steps = max(args.steps, 10)
+    traffic = profile_figures(TRAFFIC_SUMMARY_GRAPH)
     for name, prec in (("fp32_acc", gmrf.FP32_ACC64), ("fp64_acc", gmrf.FP64)):
         ch = gmrf.Chain(g, wl["y"], precision=prec, seed=5, instance=1)
         ch.sweep(args.warmup, hyper=True)
@@ -495,6 +498,12 @@ def delaunay_row(torch, gmrf, inputs, args, wl):
         row[name] = {"site_updates_per_s": n / sweep_s, "us_per_sweep": sweep_s * 1e6,
                      "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS,
                      "bytes_per_site": CSR_BYTES_PER_SITE[name], "shape": ch.tile[0]}
+        tag = name[:4]
+        if traffic and traffic["sites"] == n and tag in traffic:
+            t = traffic[tag]
+            row[name]["traffic"] = t["fetch_bytes"] + t["write_bytes"]
+            row[name]["traffic_unit"] = ("bytes/launch of csr_fused_kernel (rocprofv3 FETCH_SIZE + "
+                                         "WRITE_SIZE scaled by a device copy's reading)")
         log(f"[bench] Delaunay 1M {name}: {sweep_s * 1e6:.1f} us per sweep "
             f"({gbs / HBM_PEAK_GBS:.3f} of peak)")
         del ch
