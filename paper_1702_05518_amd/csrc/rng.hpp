@@ -254,6 +254,8 @@ __device__ inline bool gamma_draw(GammaShape g, double rate, uint64_t seed, uint
 // ---------------------------------------------------------------------------
 constexpr double kPi = 3.141592653589793;
 constexpr double kPgT = 0.64;
+constexpr float kLn2f = 0.693147180559945309f;
+constexpr float kLog2ef = 1.442695040888963407f;
 constexpr unsigned kPgMaxUniforms = 2048;   // uniforms available to one PG(1, c) draw
 constexpr int kPgMaxTerms = 200;            // series terms per acceptance test
 
@@ -338,13 +340,50 @@ __device__ inline double pg_left(double z, PgStream &s)
     const double t = kPgT;
     if (z < 1.0 / t) {
         for (;;) {
-            double e1, e2;
-            do {
-                e1 = -log_open_unit(s.next());
-                e2 = -log_open_unit(s.next());
-            } while (e1 * e1 > 2.0 * e2 / t && !s.exhausted);
+            double u1, e1 = -1.0;
+            for (;;) {
+                u1 = s.next();
+                const double u2 = s.next();
+                // The test e1^2 > 2 e2 / t first from single-precision
+                // logarithms (hardware log2): their error is below 1e-6 (1 + e)
+                // for every e, so a difference beyond 1e-3 (1 + both sides)
+                // decides it as the double-precision test would; only closer
+                // calls take the double logarithms.  The same decisions, so
+                // the same draws, with far fewer double logarithms.
+                const float a1 = -kLn2f * __builtin_amdgcn_logf((float)u1);
+                const float a2 = -kLn2f * __builtin_amdgcn_logf((float)u2);
+                const float lhs = a1 * a1, rhs = 2.0f * a2 / (float)t;
+                const float guard = 1e-3f * (1.0f + lhs + rhs);
+                bool reject;
+                if (lhs - rhs > guard) {
+                    reject = true;
+                } else if (rhs - lhs > guard) {
+                    reject = false;
+                } else {
+                    e1 = -log_open_unit(u1);
+                    reject = e1 * e1 > 2.0 * -log_open_unit(u2) / t;
+                }
+                if (!reject || s.exhausted)
+                    break;
+                e1 = -1.0;
+            }
+            if (e1 < 0.0)
+                e1 = -log_open_unit(u1);
             const double x = t / ((1.0 + t * e1) * (1.0 + t * e1));
-            if (s.next() <= exp(-0.5 * z * z * x) || s.exhausted)
+            // u <= exp(w), w = -z^2 x / 2 in (-0.79, 0]: first against the
+            // single-precision exponential (relative error below 1e-6), the
+            // double one only within 1e-4 of it
+            const double u = s.next();
+            const double w = -0.5 * z * z * x;
+            const double ef = (double)__builtin_amdgcn_exp2f((float)w * kLog2ef);
+            bool keep;
+            if (u < ef * (1.0 - 1e-4))
+                keep = true;
+            else if (u > ef * (1.0 + 1e-4))
+                keep = false;
+            else
+                keep = u <= exp(w);
+            if (keep || s.exhausted)
                 return x;
         }
     }
