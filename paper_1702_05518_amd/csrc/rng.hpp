@@ -256,6 +256,7 @@ constexpr double kPi = 3.141592653589793;
 constexpr double kPgT = 0.64;
 constexpr float kLn2f = 0.693147180559945309f;
 constexpr float kLog2ef = 1.442695040888963407f;
+constexpr float kPi2f = 9.869604401089358619f;      // pi^2
 constexpr unsigned kPgMaxUniforms = 2048;   // uniforms available to one PG(1, c) draw
 constexpr int kPgMaxTerms = 200;            // series terms per acceptance test
 
@@ -436,11 +437,27 @@ __device__ inline bool pg1_draw(const PgEnvelope &e, uint64_t seed, uint32_t sit
             x = kPgT - log_open_unit(s.next()) / e.K;
         else
             x = pg_left(e.z, s);
-        PgSeries terms(x);
-        double S = terms.next();
-        const double Y = s.next() * S;
+        const double u = s.next();
         if (s.exhausted)
             return false;
+        // The first test of the series, Y = u a0 <= a0 - a1, is u <= 1 - 3 E^8
+        // (a1 / a0 = 3 E^8 for both forms of the terms), with 3 E^8 below
+        // 0.006 here.  From the single-precision exponential (error below
+        // 1e-8 absolute at these values) a u more than 1e-5 below it is
+        // accepted as the double-precision series would; otherwise the
+        // series runs as written.
+        {
+            const float xf = (float)x;
+            const float w = x > kPgT ? -kPi2f * xf : -4.0f * __builtin_amdgcn_rcpf(xf);
+            const float q = 3.0f * __builtin_amdgcn_exp2f(w * kLog2ef);
+            if (u < 1.0 - (double)q - 1e-5) {
+                *out = 0.25 * x;
+                return true;
+            }
+        }
+        PgSeries terms(x);
+        double S = terms.next();
+        const double Y = u * S;
         for (int n = 1; n <= kPgMaxTerms; ++n) {
             if (n & 1) {
                 S -= terms.next();
