@@ -1884,7 +1884,7 @@ __global__ __launch_bounds__(kCsrPersistThreads) void csr_persistent_kernel(CsrA
 // Each color pass then runs one thread per site: x_p ~ N(m, 1/Q) with
 // Q = tau D_pp + psi_p, m = (kappa_p - psi_p beta0 + tau rho sum_{j~p} x_j) / Q.
 constexpr int kPsiSites = kThreads / 64;        // sites per block of the psi kernel
-constexpr int kPgChunk = 2;                     // PG(1, .) terms per chunk
+constexpr int kPgChunk = 4;                     // PG(1, .) terms per chunk
 
 // The PG envelope of sites lo .. lo + cnt - 1 (tilt beta0 + x_p), so that
 // the term kernel's threads need not each evaluate its erfc and exp.  Run

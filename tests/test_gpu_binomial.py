@@ -154,7 +154,7 @@ def test_binomial_fp32_agrees_statistically(G, orc):
 @pytest.mark.parametrize("layout", ["mixed", "no_trials"])
 def test_binomial_extreme_trial_counts(G, orc, layout):
     """Sites without trials (psi = 0) next to one site with 5,000 trials,
-    whose 2,500 PG term chunks span many wavefronts; and a graph with no
+    whose 1,250 PG term chunks span many wavefronts; and a graph with no
     trials at all (no PG terms to draw)."""
     wl = case(G, n=500, median=10.0, seed=12)
     trials, y = wl["trials"].copy(), wl["y"].copy()
